@@ -1,0 +1,500 @@
+"""FP64 CPU oracle for generalized DWD solved by the inexact sGS-ADMM.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, plain reference that the
+GPU solver is checked against.  Only the test suite, the package smoke check
+and the benchmark's CPU-baseline leg may import it; the solver library never
+does, and this module imports nothing from the solver.
+
+It follows the paper (arXiv 2305.12019) step by step, in its notation:
+
+* problem: generalized DWD primal (Section 2, eq-primal) with e = 1;
+* reformulation with u = w and D (w - u) = 0 (Section 3, eq-gen);
+* Algorithm 1 (Steps 1a, 1b, 1c, 2, 3) with the inexactness sequence
+  eps_k = c / (k + 1)^1.5;
+* Step 1a/1c linear system eq-linsys with T = 0, solved by the
+  Sherman-Morrison-Woodbury form of Section 3.3.2 (eq-Anew, eq-Ainv, eq-H)
+  with a Cholesky factor of I_n + Z^T D^-1 Z and the rank-one formula for
+  H^-1.  Every product with Z is an explicit product, as the paper counts
+  them (three per solve);
+* Step 1b prox of theta_q by the Newton map of Section 3.2 (eq-varphi),
+  warm-started at r^k;
+* data scaling Z~ = Z / sqrt(||X||_F) (Section 4.2, eq-gen-scale);
+* relative KKT residuals, duality gap and stopping rule (Section 4.3);
+* sigma adaptation (Section 4.4).
+
+Readings where the paper is silent or ambiguous (all are plain parameters
+that a caller may change):
+
+* mu: the (1,1) block of the eq-linsys matrix is Z Z^T + mu I, i.e. the
+  scaling matrix of the constraint D (w - u) = 0 is D = sqrt(mu) I.  The
+  default mu = 1 makes the three ways the paper writes this block agree.
+* initial point (r, xi, w, beta, u) = (1, 1, 0, 0, 0), (alpha, rho) = (0, 0).
+* eps_k constant c = 1 / ||Z~||_F by default; c = 0 means "always redo
+  Step 1c" (the exact sGS-ADMM).
+* Newton safeguard: a step that leaves (0, inf) restarts from the lower end
+  of a bracket of the root (from there Newton increases monotonically to the
+  root, because the derivative of the prox objective is increasing and
+  concave); at most 50 steps; a step below 4 ulp also stops.
+* the dual objective takes alpha^(q/(q+1)) on max(alpha, 0).
+* sigma is updated after every iteration's stopping test; no update when
+  eta_P or eta_D is below 1e-300.
+* eta_D also carries eta_D3 = ||Z~ alpha + D rho|| / (1 + C), the dual
+  feasibility of the multipliers: the infimum of the Lagrangian of eq-gen
+  over w is finite only when Z~ alpha + D rho = 0.  The paper's eta_D1 and
+  eta_D2 only measure the box 0 <= alpha <= C, which the iterates almost
+  always satisfy, so with them alone eta_D is (nearly) zero, the sigma rule
+  can only raise sigma, and the iteration stalls on many (C, q) pairs.
+  ``rho_residual=False`` restores the literal two-term eta_D.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+TAU_DEFAULT = 1.618          # Step 3 step length
+THETA_SIGMA = 5.0            # sigma rule threshold (Section 4.4)
+MAX_NEWTON = 50
+
+
+# ---------------------------------------------------------------------------
+# Section 2: loss, dual constant, reduced primal objective.
+# ---------------------------------------------------------------------------
+
+def theta(t, q):
+    """theta_q(t) = t^-q for t > 0, +inf otherwise (Section 2, eq-primal)."""
+    t = np.asarray(t, dtype=np.float64)
+    out = np.full(t.shape, np.inf)
+    pos = t > 0
+    out[pos] = t[pos] ** (-q)
+    return out
+
+
+def kappa(q):
+    """kappa = (q+1)/q * q^(1/(q+1)): inf_r theta_q(r) + a r = kappa a^(q/(q+1))
+    for a >= 0 (Section 2, the Lagrangian infima before eq-dual)."""
+    return (q + 1.0) / q * q ** (1.0 / (q + 1.0))
+
+
+def scale_data(X, y):
+    """Z = X diag(y) (eq-r), Z_scale = sqrt(||X||_F), Z~ = Z / Z_scale
+    (Section 4.2).  ``X`` has shape (n, d) with row i = x_i; the returned
+    Z~ is the d-by-n matrix of the paper as an ndarray of shape (d, n)."""
+    X = np.asarray(X, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    Z = (X * y[:, None]).T
+    zscale = math.sqrt(np.linalg.norm(X))
+    return Z / zscale, zscale
+
+
+def margins(X, y, w, beta):
+    """m = Z^T w + beta y for the unscaled problem (eq-r without xi)."""
+    X = np.asarray(X, dtype=np.float64)
+    return y * (X @ w + beta)
+
+
+def reduced_loss(m, C, q):
+    """min over xi >= 0 (with r = m + xi > 0) of theta_q(r) + C xi.
+
+    The minimiser is xi = max(0, t* - m) with t* = (q / C)^(1/(q+1)), where
+    the derivative -q r^(-q-1) + C of the one-dimensional problem vanishes.
+    This is the primal eq-primal with (r, xi) eliminated for fixed (w, beta).
+    """
+    m = np.asarray(m, dtype=np.float64)
+    ts = (q / C) ** (1.0 / (q + 1.0))
+    out = np.empty_like(m)
+    hi = m >= ts
+    out[hi] = m[hi] ** (-q)
+    out[~hi] = ts ** (-q) + C * (ts - m[~hi])
+    return out
+
+
+def reduced_objective(X, y, w, beta, C, q):
+    """Primal objective of eq-primal (e = 1) at (w, beta) with the optimal
+    (r, xi) for that (w, beta); requires ||w|| <= 1 to be feasible."""
+    return float(np.sum(reduced_loss(margins(X, y, w, beta), C, q)))
+
+
+def primal_objective(r, xi, C, q):
+    """Phi(r, xi) = sum theta_q(r_i) + C <e, xi> (eq-primal, e = 1)."""
+    return float(np.sum(theta(r, q)) + C * np.sum(xi))
+
+
+def dual_objective_unscaled(X, y, alpha, q):
+    """-Psi(alpha) = kappa sum alpha_i^(q/(q+1)) - ||Z alpha|| (eq-dual)."""
+    Zalpha = np.asarray(X, dtype=np.float64).T @ (y * alpha)
+    a = np.maximum(alpha, 0.0)
+    return float(kappa(q) * np.sum(a ** (q / (q + 1.0))) - np.linalg.norm(Zalpha))
+
+
+def training_error(X, y, w, beta):
+    """|{i : y_i sgn(beta + x_i^T w) <= 0}| / n (Section 4.5)."""
+    return float(np.mean(y * np.sign(beta + np.asarray(X, np.float64) @ w) <= 0))
+
+
+# ---------------------------------------------------------------------------
+# Section 3.2: prox of theta_q by Newton (eq-varphi), and the q = 1 cubic.
+# ---------------------------------------------------------------------------
+
+def prox_grad(s, a, sigma, q):
+    """phi'(s) for phi(s) = s^-q + sigma/2 (s - a)^2 (eq-varphi)."""
+    return -q * s ** (-q - 1.0) + sigma * (s - a)
+
+
+def prox_bracket(a, sigma, q):
+    """Interval [lo, hi] that holds the minimiser of eq-varphi.
+
+    With s0 = (q/sigma)^(1/(q+2)) (the root for a = 0): for a >= 0 the root
+    lies in [max(a, s0), a + s0]; for a < 0 it lies in
+    [(q / (sigma (s0 + |a|)))^(1/(q+1)), min(s0, (q / (sigma |a|))^(1/(q+1)))].
+    Both follow from the optimality condition s - a = q sigma^-1 / s^(q+1)
+    and the monotonicity of its two sides.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    s0 = (q / sigma) ** (1.0 / (q + 2.0))
+    lo = np.empty_like(a)
+    hi = np.empty_like(a)
+    pos = a >= 0
+    lo[pos] = np.maximum(a[pos], s0)
+    hi[pos] = a[pos] + s0
+    na = -a[~pos]
+    lo[~pos] = (q / (sigma * (s0 + na))) ** (1.0 / (q + 1.0))
+    hi[~pos] = np.minimum(s0, (q / (sigma * na)) ** (1.0 / (q + 1.0)))
+    return lo, hi
+
+
+def prox_newton(a, sigma, q, s_init, tol, max_steps=MAX_NEWTON):
+    """Newton's method of Section 3.2 for argmin_{s>0} s^-q + sigma/2 (s-a)^2,
+    element by element, warm-started at ``s_init``.
+
+    Iterates s <- s (q(q+2)/sigma + a s^(q+1)) / (q(q+1)/sigma + s^(q+2))
+    until |phi'(s)| <= tol (the Step 1b accuracy test).  Safeguard: a
+    non-positive or non-finite start or iterate is replaced by the lower end
+    of :func:`prox_bracket`; a relative step below 4 ulp also ends the
+    iteration.  Returns (s, steps) with steps the Newton steps per element.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    s = np.array(s_init, dtype=np.float64, copy=True)
+    lo, _ = prox_bracket(a, sigma, q)
+    bad = ~(np.isfinite(s) & (s > 0))
+    s[bad] = lo[bad]
+    steps = np.zeros(a.shape, dtype=np.int64)
+    done = np.abs(prox_grad(s, a, sigma, q)) <= tol
+    c1 = q * (q + 2.0) / sigma
+    c2 = q * (q + 1.0) / sigma
+    for _ in range(max_steps):
+        act = ~done
+        if not act.any():
+            break
+        sa = s[act]
+        aa = a[act]
+        s_new = sa * (c1 + aa * sa ** (q + 1.0)) / (c2 + sa ** (q + 2.0))
+        out = ~(np.isfinite(s_new) & (s_new > 0))
+        s_new[out] = lo[act][out]
+        tiny = np.abs(s_new - sa) <= 4.0 * np.finfo(np.float64).eps * sa
+        s[act] = s_new
+        steps[act] += 1
+        g_new = np.abs(prox_grad(s_new, aa, sigma, q)) <= tol
+        done[act] = g_new | tiny
+    return s, steps
+
+
+def prox_cubic_q1(a, sigma):
+    """Closed form of the q = 1 prox: the positive root of
+    s^3 - a s^2 - 1/sigma = 0 (the optimality condition of eq-varphi times
+    s^2).  For a >= 0 Cardano's formula has one real root and every term is
+    non-negative.  For a < 0 the substitution s = 1/t gives
+    t^3 + sigma a t - sigma = 0, whose positive root is the dominant one and
+    comes from Cardano (one real root) or the trigonometric form (three)."""
+    a = np.asarray(a, dtype=np.float64)
+    out = np.empty_like(a)
+    pos = a >= 0
+    if pos.any():
+        ap = a[pos]
+        h = ap ** 3 / 27.0 + 0.5 / sigma            # -q'/2 of the depressed cubic
+        disc = ap ** 3 / (27.0 * sigma) + 0.25 / sigma ** 2
+        A = h + np.sqrt(disc)
+        B = (ap ** 6 / 729.0) / A                    # h - sqrt(disc) without cancellation
+        out[pos] = np.cbrt(A) + np.cbrt(B) + ap / 3.0
+    if (~pos).any():
+        an = a[~pos]
+        p = sigma * an                                # < 0
+        half = 0.5 * sigma                            # -q'/2 with q' = -sigma
+        disc = half ** 2 + (p / 3.0) ** 3
+        t = np.empty_like(an)
+        one = disc >= 0
+        if one.any():
+            sd = np.sqrt(disc[one])
+            A = half + sd
+            B = (-(p[one] / 3.0) ** 3) / A
+            t[one] = np.cbrt(A) + np.cbrt(B)
+        three = ~one
+        if three.any():
+            pm = p[three]
+            m = 2.0 * np.sqrt(-pm / 3.0)
+            arg = (3.0 * (-sigma) / (2.0 * pm)) * np.sqrt(-3.0 / pm)
+            arg = np.clip(arg, -1.0, 1.0)
+            t[three] = m * np.cos(np.arccos(arg) / 3.0)
+        out[~pos] = 1.0 / t
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Section 3.3.2: the Sherman-Morrison-Woodbury solve of eq-linsys (T = 0).
+# ---------------------------------------------------------------------------
+
+class SMWFactor:
+    """Precomputation for eq-Ainv: the Cholesky factor of the first diagonal
+    block of J, I_n + Z~^T D^-1 Z~ with D = mu I in the (1,1) block, and
+    J^-1 ybar with ybar = [y/||y||; 1] (done once, Section 3.3.2)."""
+
+    def __init__(self, Zt, y, mu=1.0):
+        self.Zt = Zt
+        self.y = np.asarray(y, dtype=np.float64)
+        self.mu = float(mu)
+        n = Zt.shape[1]
+        self.ny = float(np.linalg.norm(self.y))
+        Mmat = np.eye(n) + (Zt.T @ Zt) / self.mu
+        self.cho = sla.cho_factor(Mmat, lower=True)
+        # J = diag(M, -1), ybar = [y/||y||; 1]
+        self.Jy_n = sla.cho_solve(self.cho, self.y / self.ny)
+        self.Jy_l = -1.0
+        self.denom = 1.0 + (self.y / self.ny) @ self.Jy_n + 1.0 * self.Jy_l
+
+    def H_inv_apply(self, v_n, v_l):
+        """H^-1 v = J^-1 v - (J^-1 ybar)(J^-1 ybar)^T v / (1 + ybar^T J^-1 ybar)."""
+        Jv_n = sla.cho_solve(self.cho, v_n)
+        Jv_l = -v_l
+        coef = (self.Jy_n @ v_n + self.Jy_l * v_l) / self.denom
+        return Jv_n - coef * self.Jy_n, Jv_l - coef * self.Jy_l
+
+    def solve(self, hw, hb):
+        """[w; beta] = A^-1 [hw; hb] via eq-Ainv:
+        A^-1 = Dhat^-1 - Dhat^-1 U H^-1 U^T Dhat^-1, Dhat = diag(mu I, ||y||^2),
+        U = [[Z~, 0], [y^T, ||y||]]."""
+        n = self.y.shape[0]
+        xw = hw / self.mu
+        xb = hb / (self.ny ** 2)
+        # U^T x
+        v_n = self.Zt.T @ xw + self.y * xb
+        v_l = self.ny * xb
+        z_n, z_l = self.H_inv_apply(v_n, v_l)
+        # x - Dhat^-1 U z
+        w = xw - (self.Zt @ z_n) / self.mu
+        beta = xb - (self.y @ z_n + self.ny * z_l) / (self.ny ** 2)
+        del n
+        return w, float(beta)
+
+
+def linsys_matrix_apply(Zt, y, mu, w, beta):
+    """A [w; beta] for the eq-linsys matrix with T = 0:
+    A = [[Z~ Z~^T + mu I, Z~ y], [(Z~ y)^T, y^T y]]."""
+    Zty = Zt @ y
+    top = Zt @ (Zt.T @ w) + mu * w + Zty * beta
+    bot = Zty @ w + (y @ y) * beta
+    return top, float(bot)
+
+
+def linsys_rhs(Zt, y, mu, sigma, r, xi, u, alpha, rho):
+    """Right-hand side hbar of eq-linsys (T = 0, D = sqrt(mu) I):
+    [-Z~(xi - r - alpha/sigma) + mu u + sqrt(mu) rho / sigma; -y^T(xi - r - alpha/sigma)]."""
+    t = xi - r - alpha / sigma
+    hw = -(Zt @ t) + mu * u + math.sqrt(mu) * rho / sigma
+    hb = -float(y @ t)
+    return hw, hb
+
+
+# ---------------------------------------------------------------------------
+# Section 4.3: KKT residuals, gap, stopping rule; Section 4.4: sigma rule.
+# ---------------------------------------------------------------------------
+
+def kkt_residuals(Zt, zscale, y, C, q, mu, r, w, beta, xi, u, alpha, rho=None,
+                  Ztw=None, rho_residual=True):
+    """Relative residuals of Section 4.3 on the scaled problem eq-gen-scale.
+    eta_C3 uses the squared norm as printed.  With ``rho`` given and
+    ``rho_residual`` set, eta_D3 = ||Z~ alpha + D rho|| / (1 + C) joins
+    eta_D.  Returns a dict with every eta, the maxima eta_P, eta_D, eta_C,
+    the objectives and eta_gap."""
+    if Ztw is None:
+        Ztw = Zt.T @ w
+    den = 1.0 + C
+    e = {}
+    e["P1"] = np.linalg.norm(Ztw + beta * y + xi - r) / den
+    e["P2"] = math.sqrt(mu) * np.linalg.norm(w - u) / den
+    e["P3"] = max(np.linalg.norm(w) - zscale, 0.0) / den
+    e["D1"] = np.linalg.norm(np.minimum(0.0, alpha)) / den
+    e["D2"] = np.linalg.norm(np.maximum(0.0, alpha - C)) / den
+    e["C1"] = abs(float(y @ alpha)) / den
+    e["C2"] = abs(float(xi @ (C - alpha))) / den
+    s = q / r ** (q + 1.0)
+    e["C3"] = float(np.sum((alpha - s) ** 2)) / den
+    Zalpha = Zt @ alpha
+    if rho is not None:
+        e["D3"] = np.linalg.norm(Zalpha + math.sqrt(mu) * rho) / den
+    primobj = float(np.sum(r ** (-q)) + C * np.sum(xi))
+    dualobj = float(kappa(q) * np.sum(np.maximum(alpha, 0.0) ** (q / (q + 1.0)))
+                    - zscale * np.linalg.norm(Zalpha))
+    e["primobj"] = primobj
+    e["dualobj"] = dualobj
+    e["gap"] = abs(primobj - dualobj) / (1.0 + abs(primobj) + abs(dualobj))
+    e["P"] = max(e["P1"], e["P2"], e["P3"])
+    e["D"] = max(e["D1"], e["D2"], e["D3"] if (rho_residual and "D3" in e) else 0.0)
+    e["C"] = max(e["C1"], e["C2"], e["C3"])
+    return e
+
+
+def stop_test(e, tol):
+    """max{eta_P, eta_D} < tol, min{eta_C, eta_gap} < sqrt(tol) and
+    max{eta_C, eta_gap} < 0.05 (Section 4.3)."""
+    return (max(e["P"], e["D"]) < tol and min(e["C"], e["gap"]) < math.sqrt(tol)
+            and max(e["C"], e["gap"]) < 0.05)
+
+
+def sigma_update(sigma, eta_p, eta_d):
+    """Section 4.4: chi = eta_P/eta_D; sigma *= zeta if chi > 5, sigma /= zeta
+    if 1/chi > 5; zeta = 2.2 if max(chi, 1/chi) > 500, 1.65 if > 50, else 1.1."""
+    if eta_p < 1e-300 or eta_d < 1e-300:
+        return sigma
+    chi = eta_p / eta_d
+    m = max(chi, 1.0 / chi)
+    zeta = 2.2 if m > 500.0 else (1.65 if m > 50.0 else 1.1)
+    if chi > THETA_SIGMA:
+        return sigma * zeta
+    if 1.0 / chi > THETA_SIGMA:
+        return sigma / zeta
+    return sigma
+
+
+def step2(w, beta, r, alpha, rho, Ztw, y, C, sigma, mu, radius):
+    """Step 2 of Algorithm 1: u = projection of g = w - sigma^-1 D^-1 rho onto
+    the ball of radius ``radius``; xi = projection onto R^n_+ of
+    r - Z~^T w - y beta + sigma^-1 alpha - sigma^-1 C e."""
+    g = w - rho / (sigma * math.sqrt(mu))
+    ng = np.linalg.norm(g)
+    u = g if ng <= radius else g * (radius / ng)
+    xi = np.maximum(0.0, r - Ztw - y * beta + (alpha - C) / sigma)
+    return u, xi
+
+
+def step3(alpha, rho, Ztw, y, beta, xi, r, w, u, sigma, mu, tau):
+    """Step 3 of Algorithm 1: alpha -= tau sigma (Z~^T w + y beta + xi - r),
+    rho -= tau sigma D (w - u)."""
+    alpha = alpha - tau * sigma * (Ztw + y * beta + xi - r)
+    rho = rho - tau * sigma * math.sqrt(mu) * (w - u)
+    return alpha, rho
+
+
+def default_sigma0(C, q, n):
+    """sigma_0 = min{10 C, n}^q (Section 4.4)."""
+    return min(10.0 * C, float(n)) ** q
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1.
+# ---------------------------------------------------------------------------
+
+def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
+          sigma0: Optional[float] = None, eps_c: Optional[float] = None,
+          record: bool = False, start: Optional[Dict] = None,
+          scale: bool = True, rho_residual: bool = True) -> Dict:
+    """Run Algorithm 1 on eq-gen-scale and return the unscaled solution.
+
+    ``X`` has shape (n, d) (row i = sample x_i), ``y`` is +-1.  Returns a dict
+    with w, u (unscaled), beta, r, xi, alpha, the scaled w~/u~/rho, the
+    iteration count ``iters`` (number of completed iterations), ``n_double``
+    (iterations in which Step 1c solved again), ``newton_max``, the final
+    residuals ``eta`` and ``converged``.  ``start`` may hold a previous
+    result's scaled state to resume from.  ``scale=False`` skips the data
+    scaling of Section 4.2 (Z_scale = 1), for the check that scaling does
+    not change the solution.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    if scale:
+        Zt, zscale = scale_data(X, y)
+    else:
+        Zt, zscale = (np.asarray(X, np.float64) * y[:, None]).T.copy(), 1.0
+    d, n = Zt.shape
+    F = SMWFactor(Zt, y, mu)
+    R = zscale
+    if start is None:
+        r = np.ones(n)
+        xi = np.ones(n)
+        w = np.zeros(d)
+        beta = 0.0
+        u = np.zeros(d)
+        alpha = np.zeros(n)
+        rho = np.zeros(d)
+        sigma = default_sigma0(C, q, n) if sigma0 is None or sigma0 <= 0 else float(sigma0)
+        k0 = 0
+    else:
+        r, xi, w, beta, u, alpha, rho = (start["r"].copy(), start["xi"].copy(),
+                                         start["w_scaled"].copy(), start["beta"],
+                                         start["u_scaled"].copy(), start["alpha"].copy(),
+                                         start["rho"].copy())
+        sigma = start["sigma"]
+        k0 = start["iters"]
+    c_eps = (1.0 / np.linalg.norm(Zt)) if (eps_c is None or eps_c < 0) else float(eps_c)
+    n_double = 0
+    newton_max = 0
+    hist = []
+    e = None
+    converged = False
+    it = k0
+    for k in range(k0, k0 + max_iter):
+        eps_k = c_eps / (k + 1.0) ** 1.5
+        # Step 1a
+        hw, hb = linsys_rhs(Zt, y, mu, sigma, r, xi, u, alpha, rho)
+        wbar, bbar = F.solve(hw, hb)
+        # Step 1b
+        c = Zt.T @ wbar + y * bbar + xi - alpha / sigma
+        r_new, steps = prox_newton(c, sigma, q, r, eps_k / math.sqrt(n))
+        newton_max = max(newton_max, int(steps.max()))
+        # Step 1c
+        hw1, hb1 = linsys_rhs(Zt, y, mu, sigma, r_new, xi, u, alpha, rho)
+        Aw, Ab = linsys_matrix_apply(Zt, y, mu, wbar, bbar)
+        res = math.sqrt(float(np.sum((hw1 - Aw) ** 2)) + (hb1 - Ab) ** 2)
+        if res > 5.0 * eps_k:
+            w, beta = F.solve(hw1, hb1)
+            n_double += 1
+        else:
+            w, beta = wbar, bbar
+        r = r_new
+        # Step 2
+        Ztw = Zt.T @ w
+        u, xi = step2(w, beta, r, alpha, rho, Ztw, y, C, sigma, mu, R)
+        # Step 3
+        alpha, rho = step3(alpha, rho, Ztw, y, beta, xi, r, w, u, sigma, mu, tau)
+        # Section 4.3
+        e = kkt_residuals(Zt, zscale, y, C, q, mu, r, w, beta, xi, u, alpha, rho=rho,
+                          Ztw=Ztw, rho_residual=rho_residual)
+        it = k + 1
+        if record:
+            hist.append(dict(k=k, sigma=sigma, P=e["P"], D=e["D"], C=e["C"], gap=e["gap"],
+                             doubled=res > 5.0 * eps_k))
+        if stop_test(e, tol):
+            converged = True
+            break
+        # Section 4.4
+        sigma = sigma_update(sigma, e["P"], e["D"])
+    return dict(w=w / zscale, u=u / zscale, beta=float(beta), r=r, xi=xi, alpha=alpha,
+                w_scaled=w, u_scaled=u, rho=rho, sigma=sigma, zscale=zscale,
+                iters=it, n_double=n_double, newton_max=newton_max, eta=e,
+                converged=converged, history=hist)
+
+
+def kkt_of_solution(X, y, C, q, sol, mu=1.0, rho_residual=True):
+    """Recompute every residual of Section 4.3 in FP64 from a returned state
+    (w and u unscaled, rho of the scaled problem, as :func:`solve` and the
+    GPU solver return them)."""
+    y = np.asarray(y, dtype=np.float64)
+    Zt, zscale = scale_data(X, y)
+    rho = sol.get("rho")
+    return kkt_residuals(Zt, zscale, y, C, q, mu, np.asarray(sol["r"], np.float64),
+                         np.asarray(sol["w"], np.float64) * zscale, float(sol["beta"]),
+                         np.asarray(sol["xi"], np.float64),
+                         np.asarray(sol["u"], np.float64) * zscale,
+                         np.asarray(sol["alpha"], np.float64),
+                         rho=None if rho is None else np.asarray(rho, np.float64),
+                         rho_residual=rho_residual)
