@@ -1,0 +1,219 @@
+/*
+ * dwd.h -- C ABI of an MI355X (gfx950) solver for generalized distance
+ * weighted discrimination (DWD) by the inexact symmetric Gauss-Seidel ADMM
+ * (arXiv 2305.12019), Sherman-Morrison-Woodbury branch.
+ *
+ * Problem (Section 2, eq-primal, with e = 1):
+ *     min  sum_i theta_q(r_i) + C <1, xi>
+ *     s.t. Z^T w + beta y + xi - r = 0,  ||w|| <= 1,  xi >= 0,
+ * with Z = X diag(y), theta_q(t) = t^-q for t > 0 (+inf otherwise), q > 0,
+ * C > 0.  X is d x n (column i is the sample x_i), y in {-1,+1}^n.
+ *
+ * The solver scales the data as in Section 4.2 (Z~ = Z / sqrt(||X||_F)),
+ * runs Algorithm 1 of Section 3 (Steps 1a, 1b, 1c, 2, 3) with the linear
+ * system eq-linsys (T = 0) solved through eq-Ainv / eq-H, the Newton prox
+ * of Section 3.2 and the residuals, stopping rule and sigma rule of
+ * Sections 4.3-4.4, and returns the unscaled solution.
+ *
+ * Conventions for every call:
+ *   - Inputs are borrowed for the duration of the call only.
+ *   - Output arrays are caller-allocated HOST buffers of the stated length;
+ *     a NULL output pointer means "not wanted".
+ *   - No exception or longjmp crosses the ABI; every call returns a
+ *     dwd_status.  Outputs are written only when the status is >= 0.
+ *   - dwd_last_error() returns a message for the last failing call on the
+ *     calling thread.
+ *   - A dwd_problem handle is not thread-safe; distinct handles may be used
+ *     from distinct threads on distinct streams.
+ */
+#ifndef DWD_H
+#define DWD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DWD_OK = 0,             /* converged to the requested tolerance              */
+  DWD_NOT_CONVERGED = 1,  /* iteration cap reached; outputs are valid          */
+  DWD_E_INVALID = -1,     /* bad argument (message in dwd_last_error)          */
+  DWD_E_NOMEM = -2,       /* device or host allocation failed / over budget    */
+  DWD_E_DEVICE = -3,      /* HIP runtime error                                 */
+  DWD_E_NUMERIC = -4,     /* non-positive pivot in the n x n factorisation     */
+  DWD_E_BUSY = -5         /* serving: no slot could ever admit the request     */
+} dwd_status;
+
+typedef enum { DWD_FP64 = 0, DWD_FP32 = 1, DWD_BF16 = 2 } dwd_dtype;
+typedef enum { DWD_DENSE = 0, DWD_CSR = 1 } dwd_layout;
+
+/* The data matrix X (d x n), Section 2 "X Matrix".
+ * DWD_DENSE: values is d x n column-major with leading dimension d, i.e.
+ *            sample i occupies values[i*d .. i*d+d-1]; dtype FP64 or FP32.
+ * DWD_CSR:   X^T in compressed sparse rows: row i (sample i) holds the
+ *            entries indices[indptr[i] .. indptr[i+1]-1] (feature ids in
+ *            [0, d)) with values of type dtype (FP64 or FP32); nnz entries.
+ * on_device: 1 if values/indptr/indices are device pointers on the current
+ *            HIP device, 0 if host pointers.                                   */
+typedef struct {
+  int64_t d, n;
+  int32_t dtype;
+  int32_t layout;
+  const void* values;
+  const int64_t* indptr;
+  const int32_t* indices;
+  int64_t nnz;
+  int32_t on_device;
+  int32_t reserved;
+} dwd_matrix;
+
+/* Solver parameters.  dwd_default_params() fills the defaults below. */
+typedef struct {
+  double C;          /* penalty on xi, > 0 (Section 2)                          */
+  double q;          /* exponent of theta_q, > 0 (Section 2)                    */
+  double tol;        /* relative KKT tolerance in (0, 1) (Section 4.3); 1e-5    */
+  int32_t max_iter;  /* iteration cap; 2000 (Section 4.3)                       */
+  int32_t storage;   /* dwd_dtype of the device copy of X: FP64, FP32 or BF16;
+                        BF16 requires an FP32 or FP64 X                         */
+  double tau;        /* Step 3 step length; 1.618                               */
+  double mu;         /* (1,1) shift of eq-linsys, D = sqrt(mu) I; 1             */
+  double sigma0;     /* <= 0: min(10 C, n)^q (Section 4.4)                      */
+  double eps_c;      /* constant of eps_k = c/(k+1)^1.5; < 0: 1/||Z~||_F,
+                        0: always redo Step 1c                                  */
+  int32_t rho_residual; /* 1: eta_D includes ||Z~ alpha + D rho||/(1+C)         */
+  int32_t resync;    /* recompute Z~^T u and Z~^T rho by a pass over Z every
+                        `resync` iterations (1 = two passes per iteration;
+                        0 = only at start and at the final check)               */
+  int32_t check_every; /* iterations queued between host reads of the stop flag */
+  int32_t refine;    /* BF16 storage: continue on FP32 data until tol is met    */
+  double lowp_tol;   /* BF16 storage: tolerance of the BF16 phase; <= 0: 30*tol */
+  int32_t profile;   /* 1: time the Z-streaming kernels with HIP events         */
+  int32_t reserved;
+} dwd_params;
+
+/* Per-solve report.  Residuals are those of Section 4.3 on the scaled
+ * problem (eq-gen-scale); *_check are recomputed after the loop with an
+ * explicit pass Z~^T w over the data of record, in FP64.                       */
+typedef struct {
+  double beta;
+  double primal_obj, dual_obj;
+  double eta_p, eta_d, eta_c, eta_gap;
+  double eta_p_check, eta_d_check, kkt_check;  /* kkt_check = max of the two   */
+  double sigma;                                 /* final sigma                  */
+  int32_t iters;        /* iterations performed                                */
+  int32_t n_double;     /* iterations where Step 1c solved again               */
+  int32_t newton_max;   /* most Newton steps of any prox in the solve          */
+  int32_t converged;    /* 1 if the stopping rule of Section 4.3 was met       */
+  int32_t iters_lowp;   /* iterations run on BF16 storage                      */
+  int32_t status;       /* dwd_status of this problem                          */
+  double setup_ms, solve_ms;
+  double stream_ms;     /* profile=1: summed duration of Z-streaming kernels   */
+  int32_t stream_launches; /* profile=1: number of such launches               */
+  int32_t reserved;
+} dwd_info;
+
+typedef struct dwd_problem_s* dwd_problem;
+
+/* Fill *p with the defaults listed in dwd_params. */
+void dwd_default_params(dwd_params* p);
+
+/* Set up a problem on the current HIP device: validate X and y, copy X into
+ * device storage of type p->storage (column-major, sample-contiguous, padded
+ * leading dimension), compute Z_scale = sqrt(||X||_F) (Section 4.2), the
+ * Gram matrix G~ = Z~^T Z~ and the inverse of I_n + G~/mu (the first
+ * diagonal block of J in eq-H, Section 3.3.2), and J^-1 ybar.
+ *   X:       data matrix (see dwd_matrix).
+ *   y:       host array of n labels, each exactly +1 or -1, both present.
+ *   p:       parameters (storage and mu are used here; C, q, tol are not).
+ *   stream:  hipStream_t to run on (NULL: the default stream).
+ *   out:     receives the handle; free it with dwd_free.
+ * Errors: DWD_E_INVALID (sizes < 1, labels not +-1 or one class empty,
+ * non-finite or all-zero X, CSR indices out of range), DWD_E_NOMEM,
+ * DWD_E_NUMERIC (factorisation failed), DWD_E_DEVICE.                          */
+dwd_status dwd_setup(const dwd_matrix* X, const double* y, const dwd_params* p,
+                     void* stream, dwd_problem* out);
+
+/* Run Algorithm 1 on the problem set up in P with the (C, q, tol, ...) of p,
+ * from the initial point (r, xi, w, beta, u) = (1, 1, 0, 0, 0),
+ * (alpha, rho) = (0, 0).  May be called repeatedly on one handle with
+ * different parameters (the eq-linsys matrix depends only on X, y and mu).
+ *   w:     d doubles, the unscaled normal vector (w~ / Z_scale).
+ *   info:  report (may be NULL).
+ *   alpha, r, xi: n doubles each (nullable).
+ *   u:     d doubles, unscaled (nullable).   rho: d doubles, scaled (nullable).
+ * Returns DWD_OK, DWD_NOT_CONVERGED (outputs valid), or an error.               */
+dwd_status dwd_solve(dwd_problem P, const dwd_params* p, double* w, dwd_info* info,
+                     double* alpha, double* r, double* xi, double* u, double* rho);
+
+/* Solve B problems that share P's X and y but have their own (C, q, tol,
+ * sigma0, ...) in p[0..B-1], stepping all of them together: the products
+ * with Z become d x n by n x B and n x d by d x B matrix products.
+ *   W:    d x B column-major host array (column j = w of problem j).
+ *   info: B reports (nullable).
+ * Each problem follows exactly the iteration it would follow alone; a
+ * converged problem is frozen.  Returns DWD_OK if all converged, else
+ * DWD_NOT_CONVERGED, or an error.                                               */
+dwd_status dwd_solve_batch(dwd_problem P, int32_t B, const dwd_params* p, double* W,
+                           dwd_info* info);
+
+/* Release every device and host resource of P (NULL is allowed). */
+void dwd_free(dwd_problem P);
+
+/* ---------------------------------------------------------------------
+ * Serving: a trace of solve requests with arrival times is replayed in
+ * real time.  Requests are admitted while their device footprint fits the
+ * HBM budget and a slot is free; admitted problems are set up on the device
+ * and stepped together with the other admitted problems, one iteration of
+ * each per round, so requests that arrive while others run join them.
+ * ------------------------------------------------------------------- */
+typedef struct {
+  dwd_matrix X;        /* data (host or device)                               */
+  const double* y;     /* n labels, host                                      */
+  dwd_params params;   /* per-request parameters (storage, C, q, tol, ...)    */
+  double t_arrival;    /* seconds after the start of the replay               */
+} dwd_request;
+
+typedef struct {
+  double hbm_budget_bytes;  /* admission budget; <= 0: 80% of free device memory */
+  int32_t max_slots;        /* problems stepped together; <= 0: 64               */
+  int32_t iters_per_round;  /* iterations per admitted problem per round; >= 1   */
+} dwd_serve_opts;
+
+typedef struct {
+  double* w;           /* caller-allocated, d doubles (nullable)              */
+  dwd_info info;       /* filled by dwd_serve                                  */
+  double t_admit, t_done;  /* seconds after the start of the replay            */
+  int32_t status;      /* dwd_status of this request                          */
+  int32_t reserved;
+} dwd_response;
+
+/* Replay nreq requests (sorted by t_arrival).  Returns DWD_OK when every
+ * request was served (each response carries its own status), or an error
+ * that stopped the replay.  A request whose footprint exceeds the whole
+ * budget gets status DWD_E_BUSY and is skipped.                                */
+dwd_status dwd_serve(const dwd_request* reqs, int32_t nreq, const dwd_serve_opts* opts,
+                     dwd_response* out);
+
+/* Diagnostics: copy a set-up quantity of P to the host array out (count
+ * doubles, must equal the quantity's size).  what is one of
+ *   "zscale" (1): Z_scale = sqrt(||X||_F) of Section 4.2;
+ *   "ymy"    (1): y^T M^-1 y with M = I + Z~^T Z~ / mu;
+ *   "G"    (n*n): G~ = Z~^T Z~, row-major;
+ *   "Minv" (n*n): M^-1, row-major;
+ *   "my"     (n): M^-1 y.
+ * Returns DWD_E_INVALID for an unknown name or a wrong count.                  */
+dwd_status dwd_inspect(dwd_problem P, const char* what, double* out, int64_t count);
+
+/* Device bytes dwd_setup would allocate for X with parameters p (used for
+ * admission); 0 on invalid input.                                              */
+int64_t dwd_footprint(const dwd_matrix* X, const dwd_params* p);
+
+const char* dwd_status_str(dwd_status s);
+const char* dwd_last_error(void);
+const char* dwd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DWD_H */

@@ -1,0 +1,712 @@
+// C ABI of libdwd: argument validation, problem set-up and the host driver
+// of the iteration (Algorithm 1).  Device work is queued on the caller's
+// stream; the host reads the device stop flag only every `check_every`
+// iterations, one chunk behind the queue, so the GPU never waits for it.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "dwd_internal.h"
+#include "dwd_solver.h"
+
+namespace dwd {
+
+thread_local std::string g_err;
+
+dwd_status fail(dwd_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+dwd_status hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? DWD_E_NOMEM : DWD_E_DEVICE;
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);   \
+  } while (0)
+
+int64_t padded_ld(int64_t d) { return ((d + kLdAlign - 1) / kLdAlign) * kLdAlign; }
+
+static size_t storage_bytes(int storage, int64_t ld, int n) {
+  const size_t cnt = (size_t)ld * n;
+  if (storage == DWD_FP64) return cnt * 8;
+  if (storage == DWD_FP32) return cnt * 4;
+  return cnt * 6;  // FP32 image of record + BF16 image
+}
+
+// Device bytes held by a set-up problem plus the set-up peak.
+int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz) {
+  const int64_t ld = padded_ld(d);
+  int64_t b = (int64_t)storage_bytes(storage, ld, n);
+  if (layout == DWD_CSR) b = (int64_t)storage_bytes(DWD_FP32, ld, n) + nnz * 24;
+  const int64_t nn = (int64_t)n * n * 8;
+  b += 2 * nn;                                          // G~, M^-1
+  b += (int64_t)n * 8 * 24 + ld * 8 * 4;                // vectors
+  b += (ld / kLdAlign) * 2 * (int64_t)n * 8;            // pass partials
+  const int splits = gram_splits(ld, n);
+  b += std::max<int64_t>((int64_t)splits * nn, nn);     // set-up scratch (Gram / inverse)
+  return b;
+}
+
+dwd_status validate_params(const dwd_params* p, bool for_solve) {
+  if (!p) return fail(DWD_E_INVALID, "params is NULL");
+  if (!(p->mu > 0.0) || !std::isfinite(p->mu)) return fail(DWD_E_INVALID, "mu must be > 0");
+  if (p->storage != DWD_FP64 && p->storage != DWD_FP32 && p->storage != DWD_BF16)
+    return fail(DWD_E_INVALID, "storage must be DWD_FP64, DWD_FP32 or DWD_BF16");
+  if (!for_solve) return DWD_OK;
+  if (!(p->C > 0.0) || !std::isfinite(p->C)) return fail(DWD_E_INVALID, "C must be > 0");
+  if (!(p->q > 0.0) || !std::isfinite(p->q) || p->q > 64.0)
+    return fail(DWD_E_INVALID, "q must be in (0, 64]");
+  if (!(p->tol > 0.0 && p->tol < 1.0)) return fail(DWD_E_INVALID, "tol must be in (0, 1)");
+  if (p->max_iter < 1) return fail(DWD_E_INVALID, "max_iter must be >= 1");
+  if (!(p->tau > 0.0 && p->tau < 0.5 * (1.0 + sqrt(5.0))))
+    return fail(DWD_E_INVALID, "tau must be in (0, (1+sqrt 5)/2)");
+  if (!std::isfinite(p->sigma0) || !std::isfinite(p->eps_c))
+    return fail(DWD_E_INVALID, "sigma0 and eps_c must be finite");
+  return DWD_OK;
+}
+
+static dwd_status validate_matrix(const dwd_matrix* X) {
+  if (!X) return fail(DWD_E_INVALID, "X is NULL");
+  if (X->d < 1 || X->n < 1) return fail(DWD_E_INVALID, "d and n must be >= 1");
+  if (X->n > 65536) return fail(DWD_E_INVALID, "n > 65536 is not supported by the n x n factor");
+  if (X->d > ((int64_t)1 << 40)) return fail(DWD_E_INVALID, "d too large");
+  if (X->dtype != DWD_FP64 && X->dtype != DWD_FP32)
+    return fail(DWD_E_INVALID, "X dtype must be DWD_FP64 or DWD_FP32");
+  if (X->layout != DWD_DENSE && X->layout != DWD_CSR)
+    return fail(DWD_E_INVALID, "X layout must be DWD_DENSE or DWD_CSR");
+  if (!X->values) return fail(DWD_E_INVALID, "X values is NULL");
+  if (X->layout == DWD_CSR) {
+    if (!X->indptr || !X->indices) return fail(DWD_E_INVALID, "CSR indptr/indices is NULL");
+    if (X->nnz < 0) return fail(DWD_E_INVALID, "nnz < 0");
+  }
+  return DWD_OK;
+}
+
+static dwd_status validate_labels(const double* y, int64_t n) {
+  if (!y) return fail(DWD_E_INVALID, "y is NULL");
+  int64_t npos = 0, nneg = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (y[i] == 1.0) ++npos;
+    else if (y[i] == -1.0) ++nneg;
+    else return fail(DWD_E_INVALID, "labels must be exactly +1 or -1");
+  }
+  if (npos == 0 || nneg == 0) return fail(DWD_E_INVALID, "both classes must be present");
+  return DWD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Problem set-up.
+// ---------------------------------------------------------------------------
+static void release(Problem* P) {
+  if (!P) return;
+  for (void* ptr : P->allocs) (void)hipFree(ptr);
+  P->allocs.clear();
+  if (P->h_flags) (void)hipHostFree(P->h_flags);
+  P->h_flags = nullptr;
+  for (auto& e : P->ev_pool) (void)hipEventDestroy(e);
+  P->ev_pool.clear();
+  if (P->ev_a) (void)hipEventDestroy(P->ev_a);
+  if (P->ev_b) (void)hipEventDestroy(P->ev_b);
+  for (auto& e : P->ev_chunk) if (e) (void)hipEventDestroy(e);
+  P->ev_a = P->ev_b = nullptr;
+}
+
+hipError_t Problem::alloc(void** ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, bytes ? bytes : 8);
+  if (e == hipSuccess) allocs.push_back(*ptr);
+  return e;
+}
+
+static hipError_t alloc_tmp(void** ptr, size_t bytes) { return hipMalloc(ptr, bytes ? bytes : 8); }
+
+// CSR of X^T (host arrays) -> dense d x n column-major host array of dtype.
+template <typename T>
+static void csr_to_dense_host(const dwd_matrix* X, std::vector<T>& out) {
+  out.assign((size_t)X->d * X->n, T(0));
+  const T* vals = (const T*)X->values;
+  for (int64_t i = 0; i < X->n; ++i)
+    for (int64_t e = X->indptr[i]; e < X->indptr[i + 1]; ++e)
+      out[(size_t)i * X->d + X->indices[e]] = vals[e];
+}
+
+dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params* p,
+                         hipStream_t st, Problem** out) {
+  dwd_status s;
+  if ((s = validate_matrix(X)) != DWD_OK) return s;
+  if ((s = validate_params(p, false)) != DWD_OK) return s;
+  if ((s = validate_labels(y, X->n)) != DWD_OK) return s;
+  auto t0 = std::chrono::steady_clock::now();
+  Problem* P = new Problem();
+  P->stream = st;
+  P->d = X->d;
+  P->n = (int)X->n;
+  P->ld = padded_ld(X->d);
+  P->storage = p->storage;
+  P->mu = p->mu;
+  P->layout = X->layout;
+  HIP_TRY(hipGetDevice(&P->device));
+  const int n = P->n;
+  const int64_t d = P->d, ld = P->ld;
+
+  // Stage the input as a dense d x n device array in its own dtype.
+  const void* Xdev = X->values;
+  void* Xtmp = nullptr;
+  const size_t in_el = X->dtype == DWD_FP64 ? 8 : 4;
+  if (X->layout == DWD_CSR) {
+    // Validate the CSR structure on the host.
+    std::vector<int64_t> ip(n + 1);
+    std::vector<int32_t> ix;
+    std::vector<char> vals;
+    if (X->on_device) {
+      HIP_TRY(hipMemcpy(ip.data(), X->indptr, (n + 1) * 8, hipMemcpyDeviceToHost));
+    } else {
+      memcpy(ip.data(), X->indptr, (n + 1) * 8);
+    }
+    if (ip[0] != 0 || ip[n] != X->nnz) {
+      delete P;
+      return fail(DWD_E_INVALID, "CSR indptr must start at 0 and end at nnz");
+    }
+    for (int i = 0; i < n; ++i)
+      if (ip[i + 1] < ip[i]) {
+        delete P;
+        return fail(DWD_E_INVALID, "CSR indptr must be non-decreasing");
+      }
+    ix.resize(X->nnz);
+    vals.resize(X->nnz * in_el);
+    if (X->on_device) {
+      HIP_TRY(hipMemcpy(ix.data(), X->indices, X->nnz * 4, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(vals.data(), X->values, X->nnz * in_el, hipMemcpyDeviceToHost));
+    } else {
+      memcpy(ix.data(), X->indices, X->nnz * 4);
+      memcpy(vals.data(), X->values, X->nnz * in_el);
+    }
+    for (int64_t e = 0; e < X->nnz; ++e)
+      if (ix[e] < 0 || ix[e] >= d) {
+        delete P;
+        return fail(DWD_E_INVALID, "CSR column index out of range");
+      }
+    dwd_matrix H = *X;
+    H.indptr = ip.data();
+    H.indices = ix.data();
+    H.values = vals.data();
+    size_t bytes = (size_t)d * n * in_el;
+    hipError_t e = alloc_tmp(&Xtmp, bytes);
+    if (e != hipSuccess) { delete P; return hip_fail(e, "hipMalloc(X staging)"); }
+    if (X->dtype == DWD_FP64) {
+      std::vector<double> dense;
+      csr_to_dense_host<double>(&H, dense);
+      e = hipMemcpyAsync(Xtmp, dense.data(), bytes, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+    } else {
+      std::vector<float> dense;
+      csr_to_dense_host<float>(&H, dense);
+      e = hipMemcpyAsync(Xtmp, dense.data(), bytes, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e != hipSuccess) { (void)hipFree(Xtmp); delete P; return hip_fail(e, "CSR staging"); }
+    Xdev = Xtmp;
+    // keep the sparse structure for the sparse passes
+    P->csr_indptr_h = ip;
+    P->csr_indices_h = ix;
+    P->nnz = X->nnz;
+  } else if (!X->on_device) {
+    size_t bytes = (size_t)d * n * in_el;
+    hipError_t e = alloc_tmp(&Xtmp, bytes);
+    if (e != hipSuccess) { delete P; return hip_fail(e, "hipMalloc(X staging)"); }
+    e = hipMemcpyAsync(Xtmp, X->values, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) { (void)hipFree(Xtmp); delete P; return hip_fail(e, "H2D X"); }
+    Xdev = Xtmp;
+  }
+
+  auto cleanup = [&](dwd_status st_) {
+    if (Xtmp) (void)hipFree(Xtmp);
+    release(P);
+    delete P;
+    return st_;
+  };
+
+  hipError_t e;
+  // Storage of Z (X itself; signs and 1/Z_scale are applied in n-space).
+  if ((e = P->alloc(&P->Xs, storage_bytes(P->storage, ld, n))) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMalloc(Z storage)"));
+  P->X_rec = P->Xs;
+  P->st_rec = P->storage == DWD_FP64 ? DWD_FP64 : DWD_FP32;
+  if (P->storage == DWD_BF16) {
+    P->X_lowp = (char*)P->Xs + (size_t)ld * n * 4;
+  }
+  // scalars + y
+  double* dscal = nullptr;
+  if ((e = P->alloc((void**)&dscal, 64 * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  P->d_scal = dscal;
+  if ((e = P->alloc((void**)&P->y, (size_t)n * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = hipMemcpyAsync(P->y, y, (size_t)n * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
+    return cleanup(hip_fail(e, "H2D y"));
+
+  // a0: copy + ||X||_F^2
+  const int ychunks = (int)std::max<int64_t>(1, std::min<int64_t>(64, ld / 8192));
+  double* part = nullptr;
+  if ((e = alloc_tmp((void**)&part, (size_t)n * ychunks * 8)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMalloc(part)"));
+  e = launch_frob_copy(Xdev, X->dtype, d, n, P->Xs, P->storage, ld, part, ychunks, st);
+  if (e == hipSuccess) e = launch_sum(part, n * ychunks, dscal, st);
+  double frob2 = 0.0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&frob2, dscal, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(part);
+  if (Xtmp) {
+    (void)hipFree(Xtmp);
+    Xtmp = nullptr;
+  }
+  if (e != hipSuccess) return cleanup(hip_fail(e, "frob/copy"));
+  if (!std::isfinite(frob2)) return cleanup(fail(DWD_E_INVALID, "X has non-finite entries"));
+  if (!(frob2 > 0.0)) return cleanup(fail(DWD_E_INVALID, "X is all zero"));
+  P->zscale = sqrt(sqrt(frob2));  // Z_scale = sqrt(||X||_F)
+
+  // a1: Gram G~ and M = I + G~/mu
+  const size_t nn = (size_t)n * n;
+  if ((e = P->alloc((void**)&P->G, nn * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(G)"));
+  if ((e = P->alloc((void**)&P->Minv, nn * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(Minv)"));
+  const int splits = gram_splits(ld, n);
+  double* Gpart = nullptr;
+  if ((e = alloc_tmp((void**)&Gpart, std::max(nn * splits, nn) * 8)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMalloc(Gram partials)"));
+  e = launch_gram(P->X_rec, P->st_rec, ld, n, Gpart, splits, st);
+  if (e == hipSuccess)
+    e = launch_gram_finish(Gpart, splits, n, P->y, 1.0 / (P->zscale * P->zscale), P->mu, P->G,
+                           P->Minv, st);
+  // a2: M^-1 in place (Gpart reused as work space), then M^-1 y and y^T M^-1 y
+  int* d_status = (int*)(dscal + 8);
+  int zero = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(d_status, &zero, 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = spd_inverse_inplace(P->Minv, n, Gpart, d_status, st);
+  if (e == hipSuccess) e = P->alloc((void**)&P->my, (size_t)n * 8);
+  if (e == hipSuccess) e = launch_gemv_rows(P->Minv, n, P->y, P->my, st);
+  if (e == hipSuccess) e = launch_dot(P->y, P->my, n, dscal + 1, st);
+  double hv[2] = {0, 0};
+  int hstat = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(hv, dscal, 16, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hstat, d_status, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(Gpart);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "Gram/inverse"));
+  if (hstat != 0 || !(hv[1] > 0.0) || !std::isfinite(hv[1]))
+    return cleanup(fail(DWD_E_NUMERIC, "factorisation of I + Z~^T Z~/mu failed"));
+  P->ymy = hv[1];
+
+  // Iteration buffers.
+  if ((e = P->alloc_iter_buffers()) != hipSuccess) return cleanup(hip_fail(e, "iteration buffers"));
+  if ((e = hipHostMalloc((void**)&P->h_flags, 4096, 0)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipHostMalloc"));
+  if ((e = hipEventCreate(&P->ev_a)) != hipSuccess) return cleanup(hip_fail(e, "event"));
+  if ((e = hipEventCreate(&P->ev_b)) != hipSuccess) return cleanup(hip_fail(e, "event"));
+  for (auto& ev : P->ev_chunk)
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+      return cleanup(hip_fail(e, "event"));
+  auto t1 = std::chrono::steady_clock::now();
+  P->setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  *out = P;
+  return DWD_OK;
+}
+
+hipError_t Problem::alloc_iter_buffers() {
+  const int n_ = n;
+  hipError_t e;
+  // 18 n-vectors
+  double* nb = nullptr;
+  if ((e = alloc((void**)&nb, (size_t)n_ * 8 * 18)) != hipSuccess) return e;
+  double* q = nb;
+  auto take = [&](double*& dst) {
+    dst = q;
+    q += n_;
+  };
+  take(ip.r); take(ip.xi); take(ip.alpha); take(ip.Pu); take(ip.Prho); take(ip.t); take(ip.x);
+  take(ip.f); take(ip.s); take(ip.v); take(ip.dr); take(ip.hG); take(ip.hM); take(ip.sp);
+  take(ip.ap);
+  double* db = nullptr;
+  if ((e = alloc((void**)&db, (size_t)ld * 8 * 4)) != hipSuccess) return e;
+  ip.u = db;
+  ip.rho = db + ld;
+  ip.w = db + 2 * ld;
+  ip.za = db + 3 * ld;
+  nchunks = (int)(ld / kLdAlign);
+  if ((e = alloc((void**)&ip.partT, (size_t)nchunks * 2 * n_ * 8)) != hipSuccess) return e;
+  const int npb = std::max(pass2_blocks(DWD_FP64, ld), 1);  // FP64 has the most blocks
+  if ((e = alloc((void**)&ip.part_g, (size_t)npb * 8)) != hipSuccess) return e;
+  if ((e = alloc((void**)&ip.part_d, (size_t)dspace_blocks(ld) * 5 * 8)) != hipSuccess) return e;
+  if ((e = alloc((void**)&ip.part_n1, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
+  if ((e = alloc((void**)&ip.part_n2, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
+  if ((e = alloc((void**)&ip.sc, sizeof(Scal))) != hipSuccess) return e;
+  ip.y = y;
+  ip.my = my;
+  ip.Minv = Minv;
+  ip.G = G;
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Solve.
+// ---------------------------------------------------------------------------
+static int qkind_of(double q) {
+  if (q == 1.0) return 1;
+  if (q == 2.0) return 2;
+  if (q == 4.0) return 4;
+  if (q == 0.5) return 5;
+  return 0;
+}
+
+Consts make_consts(const Problem* P, const dwd_params* p) {
+  Consts c;
+  c.d = P->d;
+  c.ld = P->ld;
+  c.n = P->n;
+  c.max_iter = p->max_iter;
+  c.C = p->C;
+  c.q = p->q;
+  c.tau = p->tau;
+  c.mu = P->mu;
+  c.sqmu = sqrt(P->mu);
+  c.R = P->zscale;
+  c.inv_zs = 1.0 / P->zscale;
+  c.tol = p->tol;
+  // ||Z~||_F = ||X||_F / Z_scale = Z_scale
+  c.eps_c = p->eps_c < 0.0 ? 1.0 / P->zscale : p->eps_c;
+  c.ymy = P->ymy;
+  c.kappa = (p->q + 1.0) / p->q * pow(p->q, 1.0 / (p->q + 1.0));
+  c.opC = 1.0 + p->C;
+  c.c1 = p->q * (p->q + 2.0);
+  c.c2 = p->q * (p->q + 1.0);
+  c.qexp = p->q / (p->q + 1.0);
+  c.rho_residual = p->rho_residual ? 1 : 0;
+  c.qkind = qkind_of(p->q);
+  return c;
+}
+
+double default_sigma0(const dwd_params* p, int n) {
+  return p->sigma0 > 0.0 ? p->sigma0 : pow(std::min(10.0 * p->C, (double)n), p->q);
+}
+
+// Queue one iteration of Algorithm 1 for problem P on its stream.
+hipError_t Problem::queue_iteration(const Consts& c, const void* Xit, int st_it, bool fresh,
+                                    bool profile) {
+  hipError_t e;
+  const hipStream_t s = stream;
+  if (fresh) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (profile) {
+      e0 = next_event();
+      e1 = next_event();
+      (void)hipEventRecord(e0, s);
+    }
+    if ((e = launch_gemvT(Xit, st_it, ld, n, ip.u, ip.rho, ip.partT, ip.sc, s)) != hipSuccess)
+      return e;
+    if (profile) (void)hipEventRecord(e1, s);
+  }
+  if ((e = launch_rhs(c, ip, nchunks, fresh ? 1 : 0, s)) != hipSuccess) return e;
+  const int nb = ngemv_blocks(n);
+  if ((e = launch_ngemv(n, ip.Minv, ip.x, ip.f, nullptr, nullptr, nullptr, ip.y, ip.part_n1, ip.sc,
+                        s)) != hipSuccess)
+    return e;
+  if ((e = launch_step1b(c, ip, nb, s)) != hipSuccess) return e;
+  if ((e = launch_ngemv(n, ip.G, ip.dr, ip.hG, ip.Minv, ip.dr, ip.hM, ip.dr, ip.part_n2, ip.sc,
+                        s)) != hipSuccess)
+    return e;
+  if ((e = launch_step1c(c, ip, nb, s)) != hipSuccess) return e;
+  {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (profile) {
+      e0 = next_event();
+      e1 = next_event();
+      (void)hipEventRecord(e0, s);
+    }
+    if ((e = launch_pass2(Xit, st_it, c, ip, s)) != hipSuccess) return e;
+    if (profile) (void)hipEventRecord(e1, s);
+  }
+  if ((e = launch_dspace(c, ip, pass2_blocks(st_it, ld), s)) != hipSuccess) return e;
+  if ((e = launch_tail(c, ip, dspace_blocks(ld), s)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipEvent_t Problem::next_event() {
+  if (ev_used >= (int)ev_pool.size()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    ev_pool.push_back(ev);
+  }
+  return ev_pool[ev_used++];
+}
+
+// Run iterations until the device stop flag is set.  Returns the number of
+// iterations queued.
+hipError_t Problem::run_loop(const Consts& c, const void* Xit, int st_it, int resync,
+                             int check_every, bool profile, int k_start) {
+  const int chunk = std::max(1, check_every);
+  int queued = 0;
+  int pending = -1;  // index of the chunk whose flag is in flight
+  volatile int32_t* hf = (volatile int32_t*)h_flags;
+  hipError_t e;
+  for (int cidx = 0;; ++cidx) {
+    for (int j = 0; j < chunk && k_start + queued < c.max_iter; ++j, ++queued) {
+      const int k = k_start + queued;
+      const bool fresh = (queued == 0) || (resync > 0 && (k % resync) == 0);
+      if ((e = queue_iteration(c, Xit, st_it, fresh, profile)) != hipSuccess) return e;
+    }
+    // flag copy for this chunk
+    const int slot = cidx & 1;
+    if ((e = hipMemcpyAsync((void*)(hf + slot * 16), &ip.sc->done, 4, hipMemcpyDeviceToHost,
+                            stream)) != hipSuccess)
+      return e;
+    if ((e = hipEventRecord(ev_chunk[slot], stream)) != hipSuccess) return e;
+    if (k_start + queued >= c.max_iter) break;
+    if (pending >= 0) {
+      if ((e = hipEventSynchronize(ev_chunk[pending & 1])) != hipSuccess) return e;
+      if (hf[(pending & 1) * 16]) break;
+    }
+    pending = cidx;
+  }
+  return hipStreamSynchronize(stream);
+}
+
+__global__ void k_reset_done(Scal* sc) {
+  sc->done = 0;
+  sc->converged = 0;
+}
+
+dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* info,
+                         double* alpha, double* r, double* xi, double* u, double* rho) {
+  dwd_status s;
+  if (!P) return fail(DWD_E_INVALID, "problem is NULL");
+  if ((s = validate_params(p, true)) != DWD_OK) return s;
+  HIP_TRY(hipSetDevice(P->device));
+  const hipStream_t st = P->stream;
+  HIP_TRY(hipEventRecord(P->ev_a, st));
+  Consts c = make_consts(P, p);
+  if (!iter_ptrs_ok(P->ip)) return fail(DWD_E_DEVICE, "iteration buffers are not allocated");
+  const double sigma0 = default_sigma0(p, P->n);
+  HIP_TRY(launch_init(c, P->ip, sigma0, st));
+  P->ev_used = 0;
+  const bool profile = p->profile != 0;
+  const int check_every = p->check_every > 0 ? p->check_every : 8;
+  int iters_lowp = 0;
+  if (P->storage == DWD_BF16) {
+    // Phase 1 on the BF16 image, to the looser tolerance.
+    Consts c1 = c;
+    c1.tol = p->lowp_tol > 0.0 ? p->lowp_tol : std::min(0.5, 30.0 * p->tol);
+    HIP_TRY(P->run_loop(c1, P->X_lowp, DWD_BF16, p->resync, check_every, profile, 0));
+    Scal hs;
+    HIP_TRY(hipMemcpy(&hs, P->ip.sc, sizeof(Scal), hipMemcpyDeviceToHost));
+    iters_lowp = hs.k;
+    if (p->refine && hs.k < p->max_iter) {
+      hipLaunchKernelGGL(k_reset_done, dim3(1), dim3(1), 0, st, P->ip.sc);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(P->run_loop(c, P->X_rec, P->st_rec, p->resync, check_every, profile, hs.k));
+    }
+  } else {
+    HIP_TRY(P->run_loop(c, P->X_rec, P->st_rec, p->resync, check_every, profile, 0));
+  }
+  // Final check over the data of record.
+  HIP_TRY(launch_gemvT(P->X_rec, P->st_rec, P->ld, P->n, P->ip.w, P->ip.rho, P->ip.partT, nullptr,
+                       st));
+  HIP_TRY(launch_ngemv(P->n, P->G, P->ip.alpha, P->ip.hG, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, st));
+  HIP_TRY(launch_check(c, P->ip, P->nchunks, st));
+  HIP_TRY(hipEventRecord(P->ev_b, st));
+  Scal hs;
+  HIP_TRY(hipMemcpyAsync(&hs, P->ip.sc, sizeof(Scal), hipMemcpyDeviceToHost, st));
+  std::vector<double> hw;
+  const bool want_w = w || u || rho;
+  if (want_w) hw.resize(P->ld);
+  if (w) HIP_TRY(hipMemcpyAsync(hw.data(), P->ip.w, P->d * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (w)
+    for (int64_t k = 0; k < P->d; ++k) w[k] = hw[k] / P->zscale;
+  if (u) {
+    HIP_TRY(hipMemcpy(u, P->ip.u, P->d * 8, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < P->d; ++k) u[k] /= P->zscale;
+  }
+  if (rho) HIP_TRY(hipMemcpy(rho, P->ip.rho, P->d * 8, hipMemcpyDeviceToHost));
+  if (alpha) HIP_TRY(hipMemcpy(alpha, P->ip.alpha, P->n * 8, hipMemcpyDeviceToHost));
+  if (r) HIP_TRY(hipMemcpy(r, P->ip.r, P->n * 8, hipMemcpyDeviceToHost));
+  if (xi) HIP_TRY(hipMemcpy(xi, P->ip.xi, P->n * 8, hipMemcpyDeviceToHost));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, P->ev_a, P->ev_b));
+  double stream_ms = 0.0;
+  int launches = 0;
+  if (profile) {
+    for (int j = 0; j + 1 < P->ev_used; j += 2) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, P->ev_pool[j], P->ev_pool[j + 1]) == hipSuccess) {
+        stream_ms += t;
+        ++launches;
+      }
+    }
+  }
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->beta = hs.beta;
+    info->primal_obj = hs.eta[E_PRIM];
+    info->dual_obj = hs.eta[E_DUAL];
+    info->eta_p = hs.eta[E_P];
+    info->eta_d = hs.eta[E_D];
+    info->eta_c = hs.eta[E_C];
+    info->eta_gap = hs.eta[E_GAP];
+    info->eta_p_check = hs.eta[E_PCHK];
+    info->eta_d_check = hs.eta[E_DCHK];
+    info->kkt_check = std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]);
+    info->sigma = hs.sigma;
+    info->iters = hs.k;
+    info->n_double = hs.n_double;
+    info->newton_max = hs.newton_max;
+    info->converged = hs.converged;
+    info->iters_lowp = iters_lowp;
+    info->setup_ms = P->setup_ms;
+    info->solve_ms = ms;
+    info->stream_ms = stream_ms;
+    info->stream_launches = launches;
+    info->status = hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
+  }
+  return hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
+}
+
+}  // namespace dwd
+
+// ---------------------------------------------------------------------------
+// extern "C"
+// ---------------------------------------------------------------------------
+using namespace dwd;
+
+struct dwd_problem_s {
+  Problem* P;
+};
+
+extern "C" {
+
+void dwd_default_params(dwd_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->C = 1.0;
+  p->q = 1.0;
+  p->tol = 1e-5;
+  p->max_iter = 2000;
+  p->storage = DWD_FP32;
+  p->tau = 1.618;
+  p->mu = 1.0;
+  p->sigma0 = 0.0;
+  p->eps_c = -1.0;
+  p->rho_residual = 1;
+  p->resync = 1;
+  p->check_every = 8;
+  p->refine = 1;
+  p->lowp_tol = 0.0;
+  p->profile = 0;
+}
+
+dwd_status dwd_setup(const dwd_matrix* X, const double* y, const dwd_params* p, void* stream,
+                     dwd_problem* out) {
+  if (!out) return fail(DWD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  try {
+    Problem* P = nullptr;
+    dwd_status s = setup_problem(X, y, p, (hipStream_t)stream, &P);
+    if (s != DWD_OK) return s;
+    *out = new dwd_problem_s{P};
+    return DWD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DWD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(DWD_E_DEVICE, "unexpected exception in dwd_setup");
+  }
+}
+
+dwd_status dwd_solve(dwd_problem H, const dwd_params* p, double* w, dwd_info* info,
+                     double* alpha, double* r, double* xi, double* u, double* rho) {
+  if (!H) return fail(DWD_E_INVALID, "problem is NULL");
+  try {
+    return solve_problem(H->P, p, w, info, alpha, r, xi, u, rho);
+  } catch (const std::bad_alloc&) {
+    return fail(DWD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(DWD_E_DEVICE, "unexpected exception in dwd_solve");
+  }
+}
+
+dwd_status dwd_solve_batch(dwd_problem H, int32_t B, const dwd_params* p, double* W,
+                           dwd_info* info) {
+  if (!H) return fail(DWD_E_INVALID, "problem is NULL");
+  if (B < 1 || !p) return fail(DWD_E_INVALID, "B must be >= 1 and p non-NULL");
+  try {
+    return solve_batch(H->P, B, p, W, info);
+  } catch (const std::bad_alloc&) {
+    return fail(DWD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(DWD_E_DEVICE, "unexpected exception in dwd_solve_batch");
+  }
+}
+
+void dwd_free(dwd_problem H) {
+  if (!H) return;
+  if (H->P) {
+    (void)hipSetDevice(H->P->device);
+    (void)hipStreamSynchronize(H->P->stream);
+    release(H->P);
+    delete H->P;
+  }
+  delete H;
+}
+
+dwd_status dwd_inspect(dwd_problem H, const char* what, double* out, int64_t count) {
+  if (!H || !H->P || !what || !out) return fail(DWD_E_INVALID, "NULL argument");
+  Problem* P = H->P;
+  const std::string w(what);
+  const int64_t nn = (int64_t)P->n * P->n;
+  if (w == "zscale" || w == "ymy") {
+    if (count != 1) return fail(DWD_E_INVALID, "count must be 1");
+    out[0] = w == "zscale" ? P->zscale : P->ymy;
+    return DWD_OK;
+  }
+  const double* src = nullptr;
+  int64_t m = 0;
+  if (w == "G") { src = P->G; m = nn; }
+  else if (w == "Minv") { src = P->Minv; m = nn; }
+  else if (w == "my") { src = P->my; m = P->n; }
+  else return fail(DWD_E_INVALID, "unknown quantity");
+  if (count != m) return fail(DWD_E_INVALID, "wrong count");
+  hipError_t e = hipSetDevice(P->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+  if (e == hipSuccess) e = hipMemcpy(out, src, (size_t)m * 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "dwd_inspect");
+  return DWD_OK;
+}
+
+int64_t dwd_footprint(const dwd_matrix* X, const dwd_params* p) {
+  if (!X || !p || X->d < 1 || X->n < 1) return 0;
+  return problem_footprint(X->d, (int)X->n, p->storage, X->layout, X->nnz);
+}
+
+const char* dwd_status_str(dwd_status s) {
+  switch (s) {
+    case DWD_OK: return "DWD_OK";
+    case DWD_NOT_CONVERGED: return "DWD_NOT_CONVERGED";
+    case DWD_E_INVALID: return "DWD_E_INVALID";
+    case DWD_E_NOMEM: return "DWD_E_NOMEM";
+    case DWD_E_DEVICE: return "DWD_E_DEVICE";
+    case DWD_E_NUMERIC: return "DWD_E_NUMERIC";
+    case DWD_E_BUSY: return "DWD_E_BUSY";
+  }
+  return "unknown dwd_status";
+}
+
+const char* dwd_last_error(void) { return g_err.c_str(); }
+
+const char* dwd_version(void) { return "libdwd 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// Internal declarations shared by the HIP sources of libdwd.
+//
+// Data layout in HBM (per problem):
+//   Xs   : d x n, column-major, sample-contiguous, leading dimension ld
+//          (ld = d rounded up to a multiple of kLdAlign; padding rows are 0).
+//          Holds X itself (not X diag(y)/Z_scale): the label signs and the
+//          1/Z_scale of Section 4.2 are folded into the n-vectors that
+//          multiply it, so the stored values are exactly the data of record
+//          (FP64/FP32) or its round-to-nearest-even BF16 image.
+//   G    : n x n FP64, G~ = Z~^T Z~ (Z~ = X diag(y) / Z_scale).
+//   Minv : n x n FP64, inverse of M = I + G~/mu.
+//   n-vectors FP64 (r, xi, alpha, ...), d-vectors FP64 of length ld.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dwd.h"
+
+namespace dwd {
+
+constexpr int kLdAlign = 1024;   // elements; every Z-streaming tile divides it
+constexpr int kWave = 64;        // CDNA wavefront size
+constexpr int kMaxEta = 24;
+
+// Indices into Scal::red / Scal::eta.
+enum RedIdx {
+  R_PRES2 = 0,     // ||Z~^T w + beta y + xi - r||^2
+  R_AMIN2,         // ||min(0, alpha)||^2
+  R_AMAX2,         // ||max(0, alpha - C)||^2
+  R_YA,            // y^T alpha
+  R_XCA,           // xi^T (C - alpha)
+  R_COMP2,         // ||alpha - q / r^(q+1)||^2
+  R_SUMRQ,         // sum r^-q
+  R_SUMXI,         // sum xi
+  R_SUMAQ,         // sum max(alpha,0)^(q/(q+1))
+  R_WU2,           // ||w - u||^2
+  R_W2,            // ||w||^2
+  R_DRES2,         // ||Z~ alpha + sqrt(mu) rho||^2
+  R_ZA2,           // ||Z~ alpha||^2
+  R_G2,            // ||g||^2
+  R_RHO2,          // ||rho||^2
+  R_COUNT
+};
+
+enum EtaIdx {
+  E_P1 = 0, E_P2, E_P3, E_D1, E_D2, E_D3, E_C1, E_C2, E_C3, E_GAP,
+  E_PRIM, E_DUAL, E_P, E_D, E_C, E_PCHK, E_DCHK, E_COUNT
+};
+
+// Device-resident scalar state of one problem.
+struct Scal {
+  double sigma;
+  double beta;
+  double beta_bar;
+  double gamma;        // Step 2 ball scaling min(1, R/||g||)
+  double ytdr;         // y^T (r^{k+1} - r^k)
+  int32_t k;           // iterations completed
+  int32_t done;        // stop flag read by every kernel
+  int32_t converged;
+  int32_t n_double;
+  int32_t newton_max;
+  int32_t doubled;     // this iteration redid Step 1c
+  int32_t status;      // 0 ok, else a dwd_status error code
+  int32_t frozen_iter; // batch: iteration at which the problem stopped
+  double red[R_COUNT];
+  double eta[E_COUNT];
+};
+
+// Per-solve constants, passed to kernels by value.
+struct Consts {
+  int64_t d, ld;
+  int32_t n, max_iter;
+  double C, q, tau, mu, sqmu, R, inv_zs, tol, eps_c, ymy, kappa, opC;
+  double c1, c2;       // q(q+2), q(q+1) (divided by sigma inside)
+  double qexp;         // q/(q+1)
+  int32_t rho_residual;
+  int32_t qkind;       // 1,2,4: integer q; 5: q = 0.5; 0: general
+};
+
+// Pointers of one problem's iteration state (all device).
+struct IterPtrs {
+  const double* y;
+  const double* my;     // M^-1 y
+  const double* Minv;
+  const double* G;
+  double *r, *xi, *alpha, *Pu, *Prho, *t, *x, *f, *s, *v, *dr, *hG, *hM;
+  double *sp, *ap;      // y .* s / Z_scale, y .* alpha / Z_scale
+  double *u, *rho, *w, *za;   // d-space, length ld
+  double *part_g;       // pass-2 partials of ||g||^2 (one per block)
+  double *part_d;       // d-space partials (4 per block)
+  double *part_n1;      // n-gemv partial dots (one per block)
+  double *part_n2;
+  double *partT;        // GEMV-T partials: [chunks][2][n]
+  Scal* sc;
+};
+
+// ---------------------------------------------------------------------------
+// Reductions (fixed order, hence deterministic).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum K values over a block of NT threads; the result is valid in every thread.
+// lds must hold (NT/64)*K doubles.
+template <int NT, int K>
+__device__ __forceinline__ void block_sum_k(double (&v)[K], double* lds) {
+  constexpr int NW = NT / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int j = 0; j < K; ++j) v[j] = wave_sum(v[j]);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) lds[wid * K + j] = v[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    double s = 0.0;
+    for (int ww = 0; ww < NW; ++ww) s += lds[ww * K + j];
+    v[j] = s;
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  double a[1] = {v};
+  block_sum_k<NT, 1>(a, lds);
+  return a[0];
+}
+
+// bf16 (stored as uint16) -> float
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits16) {
+  return __uint_as_float(bits16 << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+struct Problem;
+
+hipError_t launch_frob_copy(const void* X, int in_dtype, int64_t d, int n, void* Xs,
+                            int storage, int64_t ld, double* part, int nparts, hipStream_t st);
+hipError_t launch_sum(const double* part, int count, double* out, hipStream_t st);
+hipError_t launch_gram(const void* Xs, int storage, int64_t ld, int n, double* Gpart,
+                       int splits, hipStream_t st);
+hipError_t launch_gram_finish(const double* Gpart, int splits, int n, const double* y,
+                              double inv_zs2, double mu, double* G, double* M, hipStream_t st);
+hipError_t spd_inverse_inplace(double* M, int n, double* work, int* d_status, hipStream_t st);
+hipError_t launch_gemv_rows(const double* A, int n, const double* x, double* out,
+                            hipStream_t st);
+hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipStream_t st);
+int gram_splits(int64_t ld, int n);
+
+}  // namespace dwd

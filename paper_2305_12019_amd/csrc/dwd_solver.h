@@ -1,0 +1,86 @@
+// Host-side problem object and the launchers used by the drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "dwd_internal.h"
+
+namespace dwd {
+
+// launchers (kernels_iter.hip)
+hipError_t launch_gemvT(const void* X, int storage, int64_t ld, int n, const double* v1,
+                        const double* v2, double* part, const Scal* sc, hipStream_t st);
+hipError_t launch_init(const Consts& c, const IterPtrs& p, double sigma0, hipStream_t st);
+hipError_t launch_rhs(const Consts& c, const IterPtrs& p, int nchunks, int fresh, hipStream_t st);
+hipError_t launch_ngemv(int n, const double* A1, const double* x1, double* o1, const double* A2,
+                        const double* x2, double* o2, const double* wdot, double* part,
+                        const Scal* sc, hipStream_t st);
+int ngemv_blocks(int n);
+hipError_t launch_step1b(const Consts& c, const IterPtrs& p, int nblk, hipStream_t st);
+hipError_t launch_step1c(const Consts& c, const IterPtrs& p, int nblk, hipStream_t st);
+hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterPtrs& p,
+                        hipStream_t st);
+int pass2_blocks(int storage, int64_t ld);
+hipError_t launch_dspace(const Consts& c, const IterPtrs& p, int nblk_p2, hipStream_t st);
+int dspace_blocks(int64_t ld);
+hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, hipStream_t st);
+hipError_t launch_check(const Consts& c, const IterPtrs& p, int nchunks, hipStream_t st);
+bool iter_ptrs_ok(const IterPtrs& p);
+hipError_t launch_norm2(const double* v, int64_t m, double* out, hipStream_t st);
+
+struct Problem {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t d = 0, ld = 0;
+  int n = 0;
+  int storage = DWD_FP32;
+  int layout = DWD_DENSE;
+  int64_t nnz = 0;
+  double mu = 1.0, zscale = 1.0, ymy = 1.0;
+  double setup_ms = 0.0;
+  void* Xs = nullptr;          // storage image(s)
+  const void* X_rec = nullptr; // data of record (FP64 or FP32 image)
+  int st_rec = DWD_FP32;
+  const void* X_lowp = nullptr;  // BF16 image (storage == BF16)
+  double* y = nullptr;
+  double* G = nullptr;
+  double* Minv = nullptr;
+  double* my = nullptr;
+  double* d_scal = nullptr;
+  IterPtrs ip{};
+  int nchunks = 0;
+  void* h_flags = nullptr;     // pinned host words for stop flags
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  hipEvent_t ev_chunk[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> ev_pool;
+  int ev_used = 0;
+  std::vector<void*> allocs;
+  std::vector<int64_t> csr_indptr_h;
+  std::vector<int32_t> csr_indices_h;
+
+  hipError_t alloc(void** ptr, size_t bytes);
+  hipError_t alloc_iter_buffers();
+  hipError_t queue_iteration(const Consts& c, const void* Xit, int st_it, bool fresh,
+                             bool profile);
+  hipError_t run_loop(const Consts& c, const void* Xit, int st_it, int resync, int check_every,
+                      bool profile, int k_start);
+  hipEvent_t next_event();
+};
+
+dwd_status fail(dwd_status s, const std::string& msg);
+dwd_status hip_fail(hipError_t e, const char* where);
+dwd_status validate_params(const dwd_params* p, bool for_solve);
+Consts make_consts(const Problem* P, const dwd_params* p);
+double default_sigma0(const dwd_params* p, int n);
+int64_t padded_ld(int64_t d);
+int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz);
+dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params* p,
+                         hipStream_t st, Problem** out);
+dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* info,
+                         double* alpha, double* r, double* xi, double* u, double* rho);
+dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_info* info);
+
+}  // namespace dwd

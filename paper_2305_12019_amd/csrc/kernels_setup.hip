@@ -1,0 +1,413 @@
+// Setup kernels: data scaling (Section 4.2), the Gram matrix Z~^T Z~ and
+// the inverse of M = I_n + Z~^T D^-1 Z~ (the first diagonal block of J in
+// eq-H, Section 3.3.2).  All of this runs once per problem.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "dwd_internal.h"
+
+namespace dwd {
+
+// ---------------------------------------------------------------------------
+// a0: copy X (d x n, column-major, ld_in = d) into padded device storage and
+// accumulate ||X||_F^2 in FP64.  For BF16 storage both an FP32 image (data
+// of record) and a BF16 image are written.
+// grid = (n, chunks); part[chunk * n + col] receives the block's sum.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t b = __float_as_uint(f);
+  uint32_t lsb = (b >> 16) & 1u;
+  b += 0x7FFFu + lsb;
+  return (uint16_t)(b >> 16);
+}
+
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_frob_copy(const Tin* __restrict__ X, int64_t d, int n,
+                                                   void* __restrict__ Xs, int storage, int64_t ld,
+                                                   uint16_t* __restrict__ X16,
+                                                   double* __restrict__ part) {
+  __shared__ double lds[4];
+  const int col = blockIdx.x;
+  const int64_t per = (ld + gridDim.y - 1) / gridDim.y;
+  const int64_t r0 = (int64_t)blockIdx.y * per;
+  const int64_t r1 = min(ld, r0 + per);
+  double acc = 0.0;
+  for (int64_t k = r0 + threadIdx.x; k < r1; k += blockDim.x) {
+    double v = 0.0;
+    if (k < d) v = (double)X[(int64_t)col * d + k];
+    acc += v * v;
+    const int64_t o = (int64_t)col * ld + k;
+    if (storage == DWD_FP64) {
+      ((double*)Xs)[o] = v;
+    } else {
+      float f = (float)v;
+      ((float*)Xs)[o] = f;
+      if (X16) X16[o] = f32_to_bf16_rne(f);
+    }
+  }
+  acc = block_sum<256>(acc, lds);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * n + col] = acc;
+}
+
+hipError_t launch_frob_copy(const void* X, int in_dtype, int64_t d, int n, void* Xs, int storage,
+                            int64_t ld, double* part, int nparts_y, hipStream_t st) {
+  // storage == DWD_BF16: Xs is the FP32 image and the BF16 image follows it
+  // at (char*)Xs + ld*n*4 (allocated contiguously by the caller).
+  uint16_t* X16 = nullptr;
+  int st_eff = storage;
+  if (storage == DWD_BF16) {
+    X16 = (uint16_t*)((char*)Xs + (size_t)ld * n * sizeof(float));
+    st_eff = DWD_FP32;
+  }
+  dim3 grid(n, nparts_y);
+  if (in_dtype == DWD_FP64)
+    hipLaunchKernelGGL(k_frob_copy<double>, grid, dim3(256), 0, st, (const double*)X, d, n, Xs,
+                       st_eff, ld, X16, part);
+  else
+    hipLaunchKernelGGL(k_frob_copy<float>, grid, dim3(256), 0, st, (const float*)X, d, n, Xs,
+                       st_eff, ld, X16, part);
+  return hipGetLastError();
+}
+
+// Deterministic sum of `count` doubles by one block.
+__global__ void __launch_bounds__(1024) k_sum(const double* __restrict__ part, int count,
+                                              double* __restrict__ out) {
+  __shared__ double lds[16];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += part[i];
+  acc = block_sum<1024>(acc, lds);
+  if (threadIdx.x == 0) *out = acc;
+}
+
+hipError_t launch_sum(const double* part, int count, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, st, part, count, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a1: Gram matrix X^T X (n x n) in FP64, upper-triangular 64x64 tiles,
+// split over the d dimension into `splits` partial tiles (summed in a fixed
+// order by k_gram_finish).  FP64 MFMA 16x16x4: each of the 4 waves of a
+// block owns a 32x32 quarter of the 64x64 tile (2x2 MFMA blocks).
+// ---------------------------------------------------------------------------
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 64;   // tile edge
+constexpr int GK = 16;   // k-depth per LDS stage
+
+template <typename T>
+__device__ __forceinline__ double load_el(const void* Xs, int64_t o) {
+  if constexpr (sizeof(T) == 8) return ((const double*)Xs)[o];
+  else return (double)((const float*)Xs)[o];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gram_mfma(const void* __restrict__ Xs, int64_t ld, int n,
+                                                   int ntile, int splits,
+                                                   double* __restrict__ Gpart) {
+  // tile index -> (ti, tj), tj >= ti
+  int t = blockIdx.x;
+  int ti = 0;
+  while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
+  const int tj = ti + t;
+  const int split = blockIdx.y;
+  const int64_t per = ((ld / GK + splits - 1) / splits) * GK;
+  const int64_t k0 = (int64_t)split * per;
+  const int64_t k1 = min(ld, k0 + per);
+
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;           // 0..3
+  const int wr = (wid >> 1) * 32;     // wave's row offset in tile
+  const int wc = (wid & 1) * 32;      // wave's col offset
+  const int i0 = ti * GT, j0 = tj * GT;
+
+  d4v acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
+
+  for (int64_t kb = k0; kb < k1; kb += GK) {
+    // load GK x 64 of columns i0.. and j0.. (column-major: k contiguous)
+    for (int e = tid; e < GK * GT; e += 256) {
+      const int c = e / GK, kk = e % GK;
+      const int64_t k = kb + kk;
+      const int gi = i0 + c, gj = j0 + c;
+      As[kk][c] = (gi < n && k < k1) ? load_el<T>(Xs, (int64_t)gi * ld + k) : 0.0;
+      Bs[kk][c] = (gj < n && k < k1) ? load_el<T>(Xs, (int64_t)gj * ld + k) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 4) {
+      // A operand: element (row i = lane%16, k = lane/16) of a 16x4 block
+      // B operand: element (k = lane/16, col j = lane%16) of a 4x16 block
+      const int li = lane & 15, lk = lane >> 4;
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[ks + lk][wr + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[ks + lk][wc + b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of the FP64 16x16 block: column j = lane%16; lane group
+  // g = lane/16 holds rows g, g+4, g+8, g+12 in registers 0..3.
+  double* out = Gpart + (size_t)split * n * n;
+  const int lj = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + wr + a * 16 + v * 4 + lg;
+        const int gj = j0 + wc + b * 16 + lj;
+        if (gi < n && gj < n) out[(size_t)gi * n + gj] = acc[a][b][v];
+      }
+}
+
+int gram_splits(int64_t ld, int n) {
+  const int nt = (n + GT - 1) / GT;
+  const int tiles = nt * (nt + 1) / 2;
+  int s = (2048 + tiles - 1) / tiles;           // aim for >= 2048 blocks
+  const int64_t kmax = ld / GK;
+  if (s > kmax) s = (int)kmax;
+  if (s > 64) s = 64;
+  if (s < 1) s = 1;
+  return s;
+}
+
+hipError_t launch_gram(const void* Xs, int storage, int64_t ld, int n, double* Gpart, int splits,
+                       hipStream_t st) {
+  const int nt = (n + GT - 1) / GT;
+  dim3 grid(nt * (nt + 1) / 2, splits);
+  if (storage == DWD_FP64)
+    hipLaunchKernelGGL(k_gram_mfma<double>, grid, dim3(256), 0, st, Xs, ld, n, nt, splits, Gpart);
+  else
+    hipLaunchKernelGGL(k_gram_mfma<float>, grid, dim3(256), 0, st, Xs, ld, n, nt, splits, Gpart);
+  return hipGetLastError();
+}
+
+// G~_ij = y_i y_j (sum_s Gpart[s]_ij) / Z_scale^2 for the upper-tile entry,
+// mirrored; M = I + G~/mu.
+__global__ void __launch_bounds__(256) k_gram_finish(const double* __restrict__ Gpart, int splits,
+                                                     int n, const double* __restrict__ y,
+                                                     double inv_zs2, double mu,
+                                                     double* __restrict__ G,
+                                                     double* __restrict__ M) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  // entry stored in the upper tile triangle: tile(i) <= tile(j)
+  int a = i, b = j;
+  if (i / GT > j / GT) { a = j; b = i; }
+  double s = 0.0;
+  for (int p = 0; p < splits; ++p) s += Gpart[(size_t)p * n * n + (size_t)a * n + b];
+  const double g = y[i] * y[j] * s * inv_zs2;
+  G[idx] = g;
+  M[idx] = (i == j ? 1.0 : 0.0) + g / mu;
+}
+
+hipError_t launch_gram_finish(const double* Gpart, int splits, int n, const double* y,
+                              double inv_zs2, double mu, double* G, double* M, hipStream_t st) {
+  const int64_t tot = (int64_t)n * n;
+  hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Gpart,
+                     splits, n, y, inv_zs2, mu, G, M);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a2: inverse of the SPD matrix M by Schur-complement recursion:
+//   M = [A B; B^T C],  A^-1 by recursion, T = A^-1 B, S = C - B^T T,
+//   S^-1 by recursion, M^-1 = [A^-1 + T S^-1 T^T, -T S^-1; (.)^T, S^-1].
+// This is block LDL^T elimination (no pivoting is needed for SPD M, whose
+// eigenvalues are >= 1 here).  Leaves of size <= 64 are inverted in LDS by
+// Gauss-Jordan elimination with the diagonal pivots (positive for SPD).
+// ---------------------------------------------------------------------------
+constexpr int LEAF = 64;
+
+__global__ void __launch_bounds__(256) k_spd_leaf_inv(double* __restrict__ M, int ldm, int m,
+                                                      int* __restrict__ status) {
+  __shared__ double A[LEAF][LEAF + 1];
+  __shared__ double prow[LEAF];
+  __shared__ double pcol[LEAF];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < m * m; e += 256) A[e / m][e % m] = M[(size_t)(e / m) * ldm + (e % m)];
+  __syncthreads();
+  for (int p = 0; p < m; ++p) {
+    const double piv = A[p][p];
+    if (!(piv > 0.0)) {  // not positive definite (or NaN)
+      if (tid == 0) atomicExch(status, 1);
+      return;
+    }
+    const double ip = 1.0 / piv;
+    // scaled pivot row and the pivot column as it was before this step
+    for (int j = tid; j < m; j += 256) {
+      prow[j] = (j == p) ? ip : A[p][j] * ip;
+      pcol[j] = A[j][p];
+    }
+    __syncthreads();
+    // eliminate column p from every other row
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = e / m, j = e % m;
+      if (i == p) continue;
+      const double f = pcol[i];
+      if (j == p) A[i][j] = -f * ip;
+      else A[i][j] -= f * prow[j];
+    }
+    __syncthreads();
+    for (int j = tid; j < m; j += 256) A[p][j] = prow[j];
+    __syncthreads();
+  }
+  for (int e = tid; e < m * m; e += 256) M[(size_t)(e / m) * ldm + (e % m)] = A[e / m][e % m];
+}
+
+// C(mxn) = alpha * op(A) op(B) + beta * C, row-major, FP64, 64x64 tiles.
+// op(A) is m x k: transA=0 -> A[i*lda + l], 1 -> A[l*lda + i].
+// op(B) is k x n: transB=0 -> B[l*ldb + j], 1 -> B[j*ldb + l].
+__global__ void __launch_bounds__(256) k_gemm_f64(int m, int n, int k, double alpha,
+                                                  const double* __restrict__ A, int lda, int ta,
+                                                  const double* __restrict__ B, int ldb, int tb,
+                                                  double beta, double* __restrict__ C, int ldc) {
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  double acc[4][4] = {};
+  for (int l0 = 0; l0 < k; l0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int ll = e / 64, c = e % 64;
+      const int gi = i0 + c, gl = l0 + ll;
+      double va = 0.0;
+      if (gi < m && gl < k) va = ta ? A[(size_t)gl * lda + gi] : A[(size_t)gi * lda + gl];
+      As[ll][c] = va;
+      const int gj = j0 + c;
+      double vb = 0.0;
+      if (gj < n && gl < k) vb = tb ? B[(size_t)gj * ldb + gl] : B[(size_t)gl * ldb + gj];
+      Bs[ll][c] = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ll = 0; ll < 16; ++ll) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = As[ll][ty * 4 + q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = Bs[ll][tx * 4 + q];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gi = i0 + ty * 4 + p, gj = j0 + tx * 4 + q;
+      if (gi < m && gj < n) {
+        const size_t o = (size_t)gi * ldc + gj;
+        C[o] = alpha * acc[p][q] + (beta == 0.0 ? 0.0 : beta * C[o]);
+      }
+    }
+}
+
+// Dst(n2 x n1) = Src(n1 x n2)^T
+__global__ void k_transpose(const double* __restrict__ S, int lds_, double* __restrict__ D,
+                            int ldd, int r, int c) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)r * c) return;
+  const int i = (int)(idx / c), j = (int)(idx % c);
+  D[(size_t)j * ldd + i] = S[(size_t)i * lds_ + j];
+}
+
+static hipError_t gemm(int m, int n, int k, double alpha, const double* A, int lda, int ta,
+                       const double* B, int ldb, int tb, double beta, double* C, int ldc,
+                       hipStream_t st) {
+  dim3 grid((n + 63) / 64, (m + 63) / 64);
+  hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, st, m, n, k, alpha, A, lda, ta, B, ldb, tb,
+                     beta, C, ldc);
+  return hipGetLastError();
+}
+
+// M (n x n, ld) is overwritten by its inverse; work holds >= n*n doubles.
+static hipError_t spd_inv_rec(double* M, int ld, int n, double* work, int* d_status,
+                              hipStream_t st) {
+  if (n <= LEAF) {
+    hipLaunchKernelGGL(k_spd_leaf_inv, dim3(1), dim3(256), 0, st, M, ld, n, d_status);
+    return hipGetLastError();
+  }
+  const int n1 = LEAF * ((n / LEAF + 1) / 2);  // multiple of 64, about n/2
+  const int n2 = n - n1;
+  double* A = M;
+  double* B = M + n1;                  // n1 x n2
+  double* Cm = M + (size_t)n1 * ld + n1;  // n2 x n2
+  double* Lo = M + (size_t)n1 * ld;    // n2 x n1 (lower-left block)
+  double* T = work;                    // n1 x n2, ld n2
+  double* wrk = work + (size_t)n1 * n2;
+  hipError_t e;
+  if ((e = spd_inv_rec(A, ld, n1, wrk, d_status, st)) != hipSuccess) return e;
+  // T = A^-1 B
+  if ((e = gemm(n1, n2, n1, 1.0, A, ld, 0, B, ld, 0, 0.0, T, n2, st)) != hipSuccess) return e;
+  // C -= B^T T
+  if ((e = gemm(n2, n2, n1, -1.0, B, ld, 1, T, n2, 0, 1.0, Cm, ld, st)) != hipSuccess) return e;
+  if ((e = spd_inv_rec(Cm, ld, n2, wrk, d_status, st)) != hipSuccess) return e;
+  // B = -T S^-1
+  if ((e = gemm(n1, n2, n2, -1.0, T, n2, 0, Cm, ld, 0, 0.0, B, ld, st)) != hipSuccess) return e;
+  // A = A^-1 - B T^T  (= A^-1 + T S^-1 T^T)
+  if ((e = gemm(n1, n1, n2, -1.0, B, ld, 0, T, n2, 1, 1.0, A, ld, st)) != hipSuccess) return e;
+  // lower-left = B^T
+  const int64_t tot = (int64_t)n1 * n2;
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, B, ld, Lo,
+                     ld, n1, n2);
+  return hipGetLastError();
+}
+
+hipError_t spd_inverse_inplace(double* M, int n, double* work, int* d_status, hipStream_t st) {
+  return spd_inv_rec(M, n, n, work, d_status, st);
+}
+
+// out = A x, A n x n row-major FP64; one wave per row.
+__global__ void __launch_bounds__(256) k_gemv_rows(const double* __restrict__ A, int n,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ out) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += 64) acc += A[(size_t)row * n + j] * x[j];
+  acc = wave_sum(acc);
+  if (lane == 0) out[row] = acc;
+}
+
+hipError_t launch_gemv_rows(const double* A, int n, const double* x, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gemv_rows, dim3((n + 3) / 4), dim3(256), 0, st, A, n, x, out);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(1024) k_dot(const double* __restrict__ a,
+                                              const double* __restrict__ b, int n,
+                                              double* __restrict__ out) {
+  __shared__ double lds[16];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += a[i] * b[i];
+  acc = block_sum<1024>(acc, lds);
+  if (threadIdx.x == 0) *out = acc;
+}
+
+hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot, dim3(1), dim3(1024), 0, st, a, b, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace dwd

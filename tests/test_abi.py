@@ -1,0 +1,104 @@
+"""The C ABI: the library loads, exports every call include/dwd.h declares,
+and rejects bad arguments on the host before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dwd.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(dwd_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def D():
+    from paper_2305_12019_amd import dwd
+    return dwd
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for must in ("dwd_setup", "dwd_solve", "dwd_solve_batch", "dwd_serve", "dwd_free"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(D):
+    lib = C.CDLL(D.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_default_params(D):
+    p = D.params()
+    assert p.tol == 1e-5 and p.max_iter == 2000 and p.tau == 1.618 and p.mu == 1.0
+    assert p.eps_c < 0 and p.sigma0 == 0.0 and p.rho_residual == 1
+
+
+def test_struct_sizes_match_header_layout(D):
+    # field offsets follow the C declaration order with natural alignment
+    assert C.sizeof(D.Matrix) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4
+    assert C.sizeof(D.Params) == 3 * 8 + 4 + 4 + 4 * 8 + 4 * 4 + 8 + 4 + 4
+    assert C.sizeof(D.Info) == 11 * 8 + 6 * 4 + 3 * 8 + 2 * 4
+
+
+def test_status_strings(D):
+    lib = D.lib()
+    for code, name in D.STATUS.items():
+        assert lib.dwd_status_str(code).decode() == name
+    assert D.version().startswith("libdwd")
+
+
+@pytest.mark.parametrize("y,msg", [([1, 1, 1], "both classes"), ([1, -1, 0.5], "exactly"),
+                                   ([1, -1, np.nan], "exactly")])
+def test_label_validation_on_host(D, y, msg):
+    with pytest.raises(D.DwdError) as ei:
+        D.Problem(np.ones((3, 5)), y, storage="f64")
+    assert ei.value.status == -1 and msg in str(ei.value)
+
+
+def test_matrix_validation_on_host(D):
+    lib = D.lib()
+    h = C.c_void_p()
+    p = D.params()
+    y = np.array([1.0, -1.0])
+    yp = y.ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.dwd_setup(None, yp, C.byref(p), None, C.byref(h)) == -1
+    m = D.Matrix(d=0, n=2, dtype=0, layout=0, values=None)
+    assert lib.dwd_setup(C.byref(m), yp, C.byref(p), None, C.byref(h)) == -1
+    buf = np.ones(4)
+    m = D.Matrix(d=2, n=2, dtype=7, layout=0, values=buf.ctypes.data)
+    assert lib.dwd_setup(C.byref(m), yp, C.byref(p), None, C.byref(h)) == -1
+    m = D.Matrix(d=2, n=2, dtype=0, layout=1, values=buf.ctypes.data, indptr=None, indices=None)
+    assert lib.dwd_setup(C.byref(m), yp, C.byref(p), None, C.byref(h)) == -1
+    p2 = D.params(mu=-1.0)
+    m = D.Matrix(d=2, n=2, dtype=0, layout=0, values=buf.ctypes.data)
+    assert lib.dwd_setup(C.byref(m), yp, C.byref(p2), None, C.byref(h)) == -1
+    assert lib.dwd_setup(C.byref(m), yp, C.byref(p), None, None) == -1
+    assert not h.value
+
+
+def test_null_handles(D):
+    lib = D.lib()
+    p = D.params()
+    w = np.empty(2)
+    dp = w.ctypes.data_as(C.POINTER(C.c_double))
+    nul = C.POINTER(C.c_double)()
+    assert lib.dwd_solve(None, C.byref(p), dp, None, nul, nul, nul, nul, nul) == -1
+    assert lib.dwd_solve_batch(None, 1, C.byref(p), dp, None) == -1
+    lib.dwd_free(None)
+
+
+def test_footprint_scales_with_the_problem(D):
+    a = D.footprint(100_000, 1000, "f32")
+    b = D.footprint(100_000, 1000, "bf16")
+    c = D.footprint(200_000, 1000, "f32")
+    assert 4e8 < a < 8e8 and b > a and c > a
+    assert D.footprint(0, 10) == 0
