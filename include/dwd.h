@@ -83,8 +83,9 @@ typedef struct {
                         0: always redo Step 1c                                  */
   int32_t rho_residual; /* 1: eta_D includes ||Z~ alpha + D rho||/(1+C)         */
   int32_t resync;    /* recompute Z~^T u and Z~^T rho by a pass over Z every
-                        `resync` iterations (1 = two passes per iteration;
-                        0 = only at start and at the final check)               */
+                        `resync` iterations (1 = two passes per iteration);
+                        default 0: only at the start, otherwise carried by exact
+                        n-space recurrences and verified by the final check   */
   int32_t check_every; /* iterations queued between host reads of the stop flag */
   int32_t refine;    /* BF16 storage: continue on FP32 data until tol is met    */
   double lowp_tol;   /* BF16 storage: tolerance of the BF16 phase; <= 0: 30*tol */
@@ -108,8 +109,11 @@ typedef struct {
   int32_t iters_lowp;   /* iterations run on BF16 storage                      */
   int32_t status;       /* dwd_status of this problem                          */
   double setup_ms, solve_ms;
-  double stream_ms;     /* profile=1: summed duration of Z-streaming kernels   */
+  double stream_ms;     /* profile=1: summed duration of the Z~ [s, alpha] passes */
   int32_t stream_launches; /* profile=1: number of such launches               */
+  int32_t resumed;      /* times the loop resumed because the final check failed */
+  double streamT_ms;    /* profile=1: summed duration of the Z~^T [u, rho] passes */
+  int32_t streamT_launches;
   int32_t reserved;
 } dwd_info;
 

@@ -22,7 +22,13 @@ def build(verbose: bool = True) -> str:
     cmd = [hipcc] + FLAGS + ["-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    # the host pass does not know the GPU-only feature flag; drop that note
+    log = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
+    if log.strip():
+        print(log, flush=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed ({res.returncode})")
     os.replace(tmp, OUT)
     return OUT
 

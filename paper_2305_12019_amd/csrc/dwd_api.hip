@@ -321,17 +321,17 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
 hipError_t Problem::alloc_iter_buffers() {
   const int n_ = n;
   hipError_t e;
-  // 18 n-vectors
+  // 24 n-vectors
   double* nb = nullptr;
-  if ((e = alloc((void**)&nb, (size_t)n_ * 8 * 18)) != hipSuccess) return e;
+  if ((e = alloc((void**)&nb, (size_t)n_ * 8 * 24)) != hipSuccess) return e;
   double* q = nb;
   auto take = [&](double*& dst) {
     dst = q;
     q += n_;
   };
   take(ip.r); take(ip.xi); take(ip.alpha); take(ip.Pu); take(ip.Prho); take(ip.t); take(ip.x);
-  take(ip.f); take(ip.s); take(ip.v); take(ip.dr); take(ip.hG); take(ip.hM); take(ip.sp);
-  take(ip.ap);
+  take(ip.f); take(ip.s); take(ip.v); take(ip.dr); take(ip.hG); take(ip.rn); take(ip.s1);
+  take(ip.v1); take(ip.xi0); take(ip.xi1); take(ip.al0); take(ip.al1);
   double* db = nullptr;
   if ((e = alloc((void**)&db, (size_t)ld * 8 * 4)) != hipSuccess) return e;
   ip.u = db;
@@ -341,10 +341,11 @@ hipError_t Problem::alloc_iter_buffers() {
   nchunks = (int)(ld / kLdAlign);
   if ((e = alloc((void**)&ip.partT, (size_t)nchunks * 2 * n_ * 8)) != hipSuccess) return e;
   const int npb = std::max(pass2_blocks(DWD_FP64, ld), 1);  // FP64 has the most blocks
-  if ((e = alloc((void**)&ip.part_g, (size_t)npb * 8)) != hipSuccess) return e;
-  if ((e = alloc((void**)&ip.part_d, (size_t)dspace_blocks(ld) * 5 * 8)) != hipSuccess) return e;
+  if ((e = alloc((void**)&ip.part_g, (size_t)npb * NP2 * 8)) != hipSuccess) return e;
+  if ((e = alloc((void**)&ip.part_d, (size_t)dspace_blocks(ld) * NP2 * 8)) != hipSuccess) return e;
   if ((e = alloc((void**)&ip.part_n1, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
-  if ((e = alloc((void**)&ip.part_n2, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
+  if ((e = alloc((void**)&ip.part_it, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
+  if ((e = alloc((void**)&ip.part_c, (size_t)ngemv_blocks(n_) * NPC * 8)) != hipSuccess) return e;
   if ((e = alloc((void**)&ip.sc, sizeof(Scal))) != hipSuccess) return e;
   ip.y = y;
   ip.my = my;
@@ -397,51 +398,55 @@ double default_sigma0(const dwd_params* p, int n) {
 
 // Queue one iteration of Algorithm 1 for problem P on its stream.
 hipError_t Problem::queue_iteration(const Consts& c, const void* Xit, int st_it, bool fresh,
-                                    bool profile) {
+                                    bool profile, int k) {
   hipError_t e;
   const hipStream_t s = stream;
   if (fresh) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile) {
-      e0 = next_event();
-      e1 = next_event();
+      e0 = next_event(1, k);
+      e1 = next_event(1, k);
       (void)hipEventRecord(e0, s);
     }
     if ((e = launch_gemvT(Xit, st_it, ld, n, ip.u, ip.rho, ip.partT, ip.sc, s)) != hipSuccess)
       return e;
     if (profile) (void)hipEventRecord(e1, s);
   }
-  if ((e = launch_rhs(c, ip, nchunks, fresh ? 1 : 0, s)) != hipSuccess) return e;
-  const int nb = ngemv_blocks(n);
-  if ((e = launch_ngemv(n, ip.Minv, ip.x, ip.f, nullptr, nullptr, nullptr, ip.y, ip.part_n1, ip.sc,
-                        s)) != hipSuccess)
-    return e;
-  if ((e = launch_step1b(c, ip, nb, s)) != hipSuccess) return e;
-  if ((e = launch_ngemv(n, ip.G, ip.dr, ip.hG, ip.Minv, ip.dr, ip.hM, ip.dr, ip.part_n2, ip.sc,
-                        s)) != hipSuccess)
-    return e;
-  if ((e = launch_step1c(c, ip, nb, s)) != hipSuccess) return e;
+  // Without a fresh pass, t and x were formed by the previous tail kernel.
+  if (fresh && (e = launch_rhs(c, ip, nchunks, 1, s)) != hipSuccess) return e;
+  if ((e = launch_step1ab(c, ip, s)) != hipSuccess) return e;
+  if ((e = launch_step1c_rows(c, ip, s)) != hipSuccess) return e;
   {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile) {
-      e0 = next_event();
-      e1 = next_event();
+      e0 = next_event(0, k);
+      e1 = next_event(0, k);
       (void)hipEventRecord(e0, s);
     }
     if ((e = launch_pass2(Xit, st_it, c, ip, s)) != hipSuccess) return e;
     if (profile) (void)hipEventRecord(e1, s);
   }
-  if ((e = launch_dspace(c, ip, pass2_blocks(st_it, ld), s)) != hipSuccess) return e;
-  if ((e = launch_tail(c, ip, dspace_blocks(ld), s)) != hipSuccess) return e;
+  if (st_it == DWD_BF16) {
+    if ((e = launch_dspace(c, ip, pass2_blocks(st_it, ld), s)) != hipSuccess) return e;
+    if ((e = launch_tail(c, ip, dspace_blocks(ld), 0, s)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_tail(c, ip, pass2_blocks(st_it, ld), 1, s)) != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
-hipEvent_t Problem::next_event() {
+hipEvent_t Problem::next_event(int kind, int k) {
   if (ev_used >= (int)ev_pool.size()) {
     hipEvent_t ev;
     if (hipEventCreate(&ev) != hipSuccess) return nullptr;
     ev_pool.push_back(ev);
+    ev_kind.push_back(kind);
+    ev_iter.push_back(k);
+    ev_live.push_back(1);
   }
+  ev_kind[ev_used] = kind;
+  ev_iter[ev_used] = k;
+  ev_live[ev_used] = 1;
   return ev_pool[ev_used++];
 }
 
@@ -450,6 +455,7 @@ hipEvent_t Problem::next_event() {
 hipError_t Problem::run_loop(const Consts& c, const void* Xit, int st_it, int resync,
                              int check_every, bool profile, int k_start) {
   const int chunk = std::max(1, check_every);
+  const int ev_first = ev_used;
   int queued = 0;
   int pending = -1;  // index of the chunk whose flag is in flight
   volatile int32_t* hf = (volatile int32_t*)h_flags;
@@ -458,7 +464,7 @@ hipError_t Problem::run_loop(const Consts& c, const void* Xit, int st_it, int re
     for (int j = 0; j < chunk && k_start + queued < c.max_iter; ++j, ++queued) {
       const int k = k_start + queued;
       const bool fresh = (queued == 0) || (resync > 0 && (k % resync) == 0);
-      if ((e = queue_iteration(c, Xit, st_it, fresh, profile)) != hipSuccess) return e;
+      if ((e = queue_iteration(c, Xit, st_it, fresh, profile, k)) != hipSuccess) return e;
     }
     // flag copy for this chunk
     const int slot = cidx & 1;
@@ -473,7 +479,15 @@ hipError_t Problem::run_loop(const Consts& c, const void* Xit, int st_it, int re
     }
     pending = cidx;
   }
-  return hipStreamSynchronize(stream);
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
+  if (profile) {
+    // launches queued past the iteration that set the stop flag returned at once
+    int32_t kdone = 0;
+    if ((e = hipMemcpy(&kdone, &ip.sc->k, 4, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+    for (int j = ev_first; j < ev_used; ++j)
+      if (ev_iter[j] >= kdone) ev_live[j] = 0;
+  }
+  return hipSuccess;
 }
 
 __global__ void k_reset_done(Scal* sc) {
@@ -513,15 +527,28 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
   } else {
     HIP_TRY(P->run_loop(c, P->X_rec, P->st_rec, p->resync, check_every, profile, 0));
   }
-  // Final check over the data of record.
-  HIP_TRY(launch_gemvT(P->X_rec, P->st_rec, P->ld, P->n, P->ip.w, P->ip.rho, P->ip.partT, nullptr,
-                       st));
-  HIP_TRY(launch_ngemv(P->n, P->G, P->ip.alpha, P->ip.hG, nullptr, nullptr, nullptr, nullptr,
-                       nullptr, nullptr, st));
-  HIP_TRY(launch_check(c, P->ip, P->nchunks, st));
-  HIP_TRY(hipEventRecord(P->ev_b, st));
+  // Final check over the data of record.  If the loop stopped on its
+  // in-loop residuals but the explicit FP64 check misses the tolerance
+  // (rounding drift of the n-space recurrences), resume with a fresh pass
+  // every iteration; at most twice.
   Scal hs;
-  HIP_TRY(hipMemcpyAsync(&hs, P->ip.sc, sizeof(Scal), hipMemcpyDeviceToHost, st));
+  int resumed = 0;
+  for (;;) {
+    HIP_TRY(launch_gemvT(P->X_rec, P->st_rec, P->ld, P->n, P->ip.w, P->ip.rho, P->ip.partT,
+                         nullptr, st));
+    HIP_TRY(launch_ngemv(P->n, P->G, P->ip.alpha, P->ip.hG, nullptr, nullptr, nullptr, nullptr,
+                         nullptr, nullptr, st));
+    HIP_TRY(launch_check(c, P->ip, P->nchunks, st));
+    HIP_TRY(hipMemcpyAsync(&hs, P->ip.sc, sizeof(Scal), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double chk = std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]);
+    if (!hs.converged || chk < p->tol || resumed >= 2 || hs.k >= p->max_iter) break;
+    ++resumed;
+    hipLaunchKernelGGL(k_reset_done, dim3(1), dim3(1), 0, st, P->ip.sc);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(P->run_loop(c, P->X_rec, P->st_rec, 1, check_every, profile, hs.k));
+  }
+  HIP_TRY(hipEventRecord(P->ev_b, st));
   std::vector<double> hw;
   const bool want_w = w || u || rho;
   if (want_w) hw.resize(P->ld);
@@ -539,14 +566,16 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
   if (xi) HIP_TRY(hipMemcpy(xi, P->ip.xi, P->n * 8, hipMemcpyDeviceToHost));
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, P->ev_a, P->ev_b));
-  double stream_ms = 0.0;
-  int launches = 0;
+  double stream_ms[2] = {0.0, 0.0};
+  int launches[2] = {0, 0};
   if (profile) {
     for (int j = 0; j + 1 < P->ev_used; j += 2) {
       float t = 0.0f;
+      if (!P->ev_live[j]) continue;
       if (hipEventElapsedTime(&t, P->ev_pool[j], P->ev_pool[j + 1]) == hipSuccess) {
-        stream_ms += t;
-        ++launches;
+        const int kd = P->ev_kind[j] ? 1 : 0;
+        stream_ms[kd] += t;
+        ++launches[kd];
       }
     }
   }
@@ -570,8 +599,11 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
     info->iters_lowp = iters_lowp;
     info->setup_ms = P->setup_ms;
     info->solve_ms = ms;
-    info->stream_ms = stream_ms;
-    info->stream_launches = launches;
+    info->stream_ms = stream_ms[0];
+    info->stream_launches = launches[0];
+    info->streamT_ms = stream_ms[1];
+    info->streamT_launches = launches[1];
+    info->resumed = resumed;
     info->status = hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
   }
   return hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
@@ -603,7 +635,7 @@ void dwd_default_params(dwd_params* p) {
   p->sigma0 = 0.0;
   p->eps_c = -1.0;
   p->rho_residual = 1;
-  p->resync = 1;
+  p->resync = 0;
   p->check_every = 8;
   p->refine = 1;
   p->lowp_tol = 0.0;

@@ -22,6 +22,9 @@ namespace dwd {
 constexpr int kLdAlign = 1024;   // elements; every Z-streaming tile divides it
 constexpr int kWave = 64;        // CDNA wavefront size
 constexpr int kMaxEta = 24;
+constexpr int NPO = 11;          // Step 1c partials per outcome: 9 sums + s^T G s + Pu^T s
+constexpr int NPC = 1 + 2 * NPO; // Step 1c partials per block
+constexpr int NP2 = 6;           // pass partials per block
 
 // Indices into Scal::red / Scal::eta.
 enum RedIdx {
@@ -55,6 +58,8 @@ struct Scal {
   double beta_bar;
   double gamma;        // Step 2 ball scaling min(1, R/||g||)
   double ytdr;         // y^T (r^{k+1} - r^k)
+  double beta1;        // beta of the Step 1c re-solve
+  double u2;           // ||u||^2 of the current u
   int32_t k;           // iterations completed
   int32_t done;        // stop flag read by every kernel
   int32_t converged;
@@ -84,13 +89,14 @@ struct IterPtrs {
   const double* my;     // M^-1 y
   const double* Minv;
   const double* G;
-  double *r, *xi, *alpha, *Pu, *Prho, *t, *x, *f, *s, *v, *dr, *hG, *hM;
-  double *sp, *ap;      // y .* s / Z_scale, y .* alpha / Z_scale
-  double *u, *rho, *w, *za;   // d-space, length ld
-  double *part_g;       // pass-2 partials of ||g||^2 (one per block)
-  double *part_d;       // d-space partials (4 per block)
-  double *part_n1;      // n-gemv partial dots (one per block)
-  double *part_n2;
+  double *r, *xi, *alpha, *Pu, *Prho, *t, *x, *f, *s, *v, *dr, *hG, *rn;
+  double *s1, *v1, *xi0, *xi1, *al0, *al1;  // the two outcomes of Step 1c
+  double *u, *rho, *w, *za;  // d-space, length ld (za: BF16 phase only)
+  double *part_g;       // pass partials (NP2 per block)
+  double *part_d;       // d-space step partials (NP2 per block; BF16 phase)
+  double *part_n1;      // Step 1b block partials of y^T dr
+  double *part_it;      // Step 1b block maxima of Newton steps
+  double *part_c;       // Step 1c block partials (NPC per block)
   double *partT;        // GEMV-T partials: [chunks][2][n]
   Scal* sc;
 };
@@ -104,33 +110,37 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum K values over a block of NT threads; the result is valid in every thread.
-// lds must hold (NT/64)*K doubles.
+// Sum K values over a block of NT threads; the result is valid in every
+// thread.  Two levels (wave shuffles, then K threads over the waves), fixed
+// order; the staging buffer is a block-level LDS array of this instantiation.
 template <int NT, int K>
-__device__ __forceinline__ void block_sum_k(double (&v)[K], double* lds) {
+__device__ __forceinline__ void block_sum_k(double (&v)[K]) {
   constexpr int NW = NT / kWave;
+  __shared__ double buf[NW * K + K];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
 #pragma unroll
   for (int j = 0; j < K; ++j) v[j] = wave_sum(v[j]);
   if (lane == 0) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) lds[wid * K + j] = v[j];
+    for (int j = 0; j < K; ++j) buf[wid * K + j] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int ww = 0; ww < NW; ++ww) s += buf[ww * K + threadIdx.x];
+    buf[NW * K + threadIdx.x] = s;
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < K; ++j) {
-    double s = 0.0;
-    for (int ww = 0; ww < NW; ++ww) s += lds[ww * K + j];
-    v[j] = s;
-  }
+  for (int j = 0; j < K; ++j) v[j] = buf[NW * K + j];
   __syncthreads();
 }
 
 template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* lds) {
+__device__ __forceinline__ double block_sum(double v) {
   double a[1] = {v};
-  block_sum_k<NT, 1>(a, lds);
+  block_sum_k<NT, 1>(a);
   return a[0];
 }
 

@@ -18,15 +18,15 @@ hipError_t launch_rhs(const Consts& c, const IterPtrs& p, int nchunks, int fresh
 hipError_t launch_ngemv(int n, const double* A1, const double* x1, double* o1, const double* A2,
                         const double* x2, double* o2, const double* wdot, double* part,
                         const Scal* sc, hipStream_t st);
-int ngemv_blocks(int n);
-hipError_t launch_step1b(const Consts& c, const IterPtrs& p, int nblk, hipStream_t st);
-hipError_t launch_step1c(const Consts& c, const IterPtrs& p, int nblk, hipStream_t st);
+__host__ __device__ int ngemv_blocks(int n);
+hipError_t launch_step1ab(const Consts& c, const IterPtrs& p, hipStream_t st);
+hipError_t launch_step1c_rows(const Consts& c, const IterPtrs& p, hipStream_t st);
 hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterPtrs& p,
                         hipStream_t st);
 int pass2_blocks(int storage, int64_t ld);
 hipError_t launch_dspace(const Consts& c, const IterPtrs& p, int nblk_p2, hipStream_t st);
 int dspace_blocks(int64_t ld);
-hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, hipStream_t st);
+hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, int fused, hipStream_t st);
 hipError_t launch_check(const Consts& c, const IterPtrs& p, int nchunks, hipStream_t st);
 bool iter_ptrs_ok(const IterPtrs& p);
 hipError_t launch_norm2(const double* v, int64_t m, double* out, hipStream_t st);
@@ -56,6 +56,9 @@ struct Problem {
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   hipEvent_t ev_chunk[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;    // 0: Z~ [s, alpha] pass, 1: Z~^T [u, rho] pass
+  std::vector<int> ev_iter;    // iteration index of the timed launch
+  std::vector<char> ev_live;   // 0 if the launch came after the stop flag was set
   int ev_used = 0;
   std::vector<void*> allocs;
   std::vector<int64_t> csr_indptr_h;
@@ -64,10 +67,10 @@ struct Problem {
   hipError_t alloc(void** ptr, size_t bytes);
   hipError_t alloc_iter_buffers();
   hipError_t queue_iteration(const Consts& c, const void* Xit, int st_it, bool fresh,
-                             bool profile);
+                             bool profile, int k);
   hipError_t run_loop(const Consts& c, const void* Xit, int st_it, int resync, int check_every,
                       bool profile, int k_start);
-  hipEvent_t next_event();
+  hipEvent_t next_event(int kind, int k);
 };
 
 dwd_status fail(dwd_status s, const std::string& msg);

@@ -21,6 +21,9 @@
 
 namespace dwd {
 
+// Blocks of the one-wave-per-row n x n kernels (4 rows per block).
+__host__ __device__ int ngemv_blocks(int n) { return (n + 3) / 4; }
+
 // ---------------------------------------------------------------------------
 // Vector loads of the stored data, converted to FP64.
 // ---------------------------------------------------------------------------
@@ -126,8 +129,9 @@ static hipError_t gemvT_t(const void* X, int64_t ld, int n, const double* v1, co
 // launchers refuse to launch otherwise.
 bool iter_ptrs_ok(const IterPtrs& p) {
   const void* req[] = {p.y, p.my, p.Minv, p.G, p.r, p.xi, p.alpha, p.Pu, p.Prho, p.t, p.x,
-                       p.f, p.s, p.v, p.dr, p.hG, p.hM, p.sp, p.ap, p.u, p.rho, p.w, p.za,
-                       p.part_g, p.part_d, p.part_n1, p.part_n2, p.partT, p.sc};
+                       p.f, p.s, p.v, p.dr, p.hG, p.rn, p.s1, p.v1, p.xi0, p.xi1, p.al0,
+                       p.al1, p.u, p.rho, p.w, p.za, p.part_g, p.part_d, p.part_n1, p.part_it,
+                       p.part_c, p.partT, p.sc};
   for (const void* q : req)
     if (!q) return false;
   return true;
@@ -174,6 +178,7 @@ __global__ void k_init(Consts c, IterPtrs p, double sigma0) {
     s->doubled = 0;
     s->status = 0;
     s->frozen_iter = 0;
+    s->u2 = 0.0;
     for (int j = 0; j < R_COUNT; ++j) s->red[j] = 0.0;
     for (int j = 0; j < E_COUNT; ++j) s->eta[j] = 0.0;
   }
@@ -236,7 +241,6 @@ __global__ void __launch_bounds__(256) k_ngemv(int n, const double* __restrict__
                                                double* __restrict__ part,
                                                const Scal* __restrict__ sc) {
   if (sc && sc->done) return;
-  __shared__ double lds[4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int row = blockIdx.x * 4 + wid;
   double contrib = 0.0;
@@ -269,12 +273,12 @@ __global__ void __launch_bounds__(256) k_ngemv(int n, const double* __restrict__
       if (lane == 0) o2[row] = acc2;
     }
   }
-  if (lane == 0) lds[wid] = contrib;
+  __shared__ double wpart[4];
+  if (lane == 0) wpart[wid] = contrib;
   __syncthreads();
-  if (threadIdx.x == 0 && part) part[blockIdx.x] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  if (threadIdx.x == 0 && part) part[blockIdx.x] = (wpart[0] + wpart[1]) + (wpart[2] + wpart[3]);
 }
 
-int ngemv_blocks(int n) { return (n + 3) / 4; }
 
 hipError_t launch_ngemv(int n, const double* A1, const double* x1, double* o1, const double* A2,
                         const double* x2, double* o2, const double* wdot, double* part,
@@ -347,160 +351,335 @@ __device__ __forceinline__ double eps_k(const Consts& c, int k) {
   return c.eps_c / (k1 * sqrt(k1));
 }
 
-// ---------------------------------------------------------------------------
-// Step 1a (finish) and Step 1b.  One block.
-//   beta_bar = -y^T f / y^T M^-1 y, s_bar = f + beta_bar M^-1 y, v_bar = s_bar - t,
-//   c = v_bar + xi - alpha/sigma, r^{k+1} = prox(c), dr = r^{k+1} - r^k.
-// ---------------------------------------------------------------------------
-constexpr int NT1 = 1024;
+// Sum one double over a block of NT threads; every thread gets the result.
+template <int NT>
+__device__ __forceinline__ double bsum(double v) {
+  return block_sum<NT>(v);
+}
 
-__global__ void __launch_bounds__(NT1) k_step1b(Consts c, IterPtrs p, int nblk_gemv) {
+// Dot products of one row of an n x n FP64 matrix with x by one wave, with
+// CH loads per lane in flight before the reduction.
+constexpr int CH = 16;
+
+__device__ __forceinline__ double wave_row_dot(const double* __restrict__ a,
+                                               const double* __restrict__ x, int n, int lane) {
+  double acc = 0.0;
+  for (int base = 0; base < n; base += 64 * CH) {
+    double av[CH], xv[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int j = base + q * 64 + lane;
+      av[q] = j < n ? a[j] : 0.0;
+      xv[q] = j < n ? x[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) acc = fma(av[q], xv[q], acc);
+  }
+  return wave_sum(acc);
+}
+
+__device__ __forceinline__ void wave_row_dot2(const double* __restrict__ a,
+                                              const double* __restrict__ b,
+                                              const double* __restrict__ x, int n, int lane,
+                                              double& ra, double& rb) {
+  double sa = 0.0, sb = 0.0;
+  for (int base = 0; base < n; base += 64 * CH) {
+    double av[CH], bv[CH], xv[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int j = base + q * 64 + lane;
+      av[q] = j < n ? a[j] : 0.0;
+      bv[q] = j < n ? b[j] : 0.0;
+      xv[q] = j < n ? x[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      sa = fma(av[q], xv[q], sa);
+      sb = fma(bv[q], xv[q], sb);
+    }
+  }
+  ra = wave_sum(sa);
+  rb = wave_sum(sb);
+}
+
+// ---------------------------------------------------------------------------
+// Step 1a (solve) fused with Step 1b (prox).  One wave per row i:
+//   f_i = (M^-1 x)_i,  beta_bar = -y^T M^-1 x / y^T M^-1 y = -(M^-1 y)^T x / y^T M^-1 y
+// (M^-1 is symmetric, so every block forms beta_bar from x directly, in the
+// same order), s_bar = f + beta_bar M^-1 y, v_bar = s_bar - t,
+// c = v_bar + xi - alpha/sigma, r^{k+1}_i = prox(c_i), dr = r^{k+1} - r^k.
+// Block partials: y^T dr and the most Newton steps.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_step1ab(Consts c, IterPtrs p) {
   Scal* sc = p.sc;
   if (sc->done) return;
-  __shared__ double lds[(NT1 / 64) * 2];
-  __shared__ int smax;
-  if (threadIdx.x == 0) smax = 0;
-  double yf = 0.0;
-  for (int b = threadIdx.x; b < nblk_gemv; b += NT1) yf += p.part_n1[b];
-  yf = block_sum<NT1>(yf, lds);
-  const double beta_bar = -yf / c.ymy;
+  __shared__ double wy[4];
+  __shared__ int ws[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int row = blockIdx.x * 4 + wid;
+  const bool mine = row < c.n && lane == 0;
+  // per-row operands, loaded before the reductions
+  double myr = 0.0, tr = 0.0, xir = 0.0, alr = 0.0, r0 = 1.0, yr = 0.0;
+  if (mine) {
+    myr = p.my[row];
+    tr = p.t[row];
+    xir = p.xi[row];
+    alr = p.alpha[row];
+    r0 = p.r[row];
+    yr = p.y[row];
+  }
   const double sigma = sc->sigma;
-  const double tolN = eps_k(c, sc->k) / sqrt((double)c.n);
-  double ytdr = 0.0;
-  int mx = 0;
-  for (int i = threadIdx.x; i < c.n; i += NT1) {
-    const double s = p.f[i] + beta_bar * p.my[i];
-    const double v = s - p.t[i];
-    const double cc = v + p.xi[i] - p.alpha[i] / sigma;
-    const double r0 = p.r[i];
-    int steps;
+  const int kk = sc->k;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < c.n; j += 256) acc = fma(p.my[j], p.x[j], acc);
+  double f = 0.0;
+  if (row < c.n) f = wave_row_dot(p.Minv + (size_t)row * c.n, p.x, c.n, lane);
+  const double beta_bar = -bsum<256>(acc) / c.ymy;
+  double ydr = 0.0;
+  int steps = 0;
+  if (mine) {
+    const double tolN = eps_k(c, kk) / sqrt((double)c.n);
+    const double s = f + beta_bar * myr;
+    const double v = s - tr;
+    const double cc = v + xir - alr / sigma;
     const double rn = prox_newton(cc, sigma, r0, tolN, c, steps);
-    mx = max(mx, steps);
-    p.s[i] = s;
-    p.v[i] = v;
-    p.x[i] = rn;  // x is free after the M^-1 product; it now holds r^{k+1}
     const double dr = rn - r0;
-    p.dr[i] = dr;
-    ytdr += p.y[i] * dr;
+    p.f[row] = f;
+    p.s[row] = s;
+    p.v[row] = v;
+    p.rn[row] = rn;
+    p.dr[row] = dr;
+    ydr = yr * dr;
   }
-  atomicMax(&smax, mx);
-  ytdr = block_sum<NT1>(ytdr, lds);
+  if (lane == 0) {
+    wy[wid] = ydr;
+    ws[wid] = steps;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    sc->beta_bar = beta_bar;
-    sc->ytdr = ytdr;
-    if (smax > sc->newton_max) sc->newton_max = smax;
+    p.part_n1[blockIdx.x] = (wy[0] + wy[1]) + (wy[2] + wy[3]);
+    p.part_it[blockIdx.x] = (double)max(max(ws[0], ws[1]), max(ws[2], ws[3]));
+    if (blockIdx.x == 0) sc->beta_bar = beta_bar;
   }
 }
 
-hipError_t launch_step1b(const Consts& c, const IterPtrs& p, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_step1b, dim3(1), dim3(NT1), 0, st, c, p, nblk);
+hipError_t launch_step1ab(const Consts& c, const IterPtrs& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_step1ab, dim3(ngemv_blocks(c.n)), dim3(256), 0, st, c, p);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Step 1c test and solve, then the n-space parts of Steps 2 and 3 and the
-// n-space residuals of Section 4.3.  One block.
+// Step 1c, row-parallel.  One wave per row i forms (G~ dr)_i and (M^-1 dr)_i.
+// The test ||h - A [wbar; betabar]||^2 = dr^T G~ dr + (y^T dr)^2 <= (5 eps_k)^2
+// needs a global sum, so each row prepares both outcomes:
+//   0: keep Step 1a's solution:  s0 = s_bar = M^-1 (x + beta_bar y), v0 = v_bar;
+//   1: solve again with r^{k+1}: s1 = M^-1 (x - dr + beta1 y) with
+//      beta1 = beta_bar + (M^-1 y)^T dr / y^T M^-1 y,  v1 = s1 - (t - dr);
+// and, for each, Step 2 (xi) and Step 3 (alpha) in n-space:
+//   xi_o = max(0, r^{k+1} - v_o + (alpha - C)/sigma),
+//   alpha_o = alpha - tau sigma (v_o + xi_o - r^{k+1}),
+// the nine n-space sums of Section 4.3, and the two terms of
+//   ||g||^2 = ||u||^2 - 2/mu (Z~^T u)^T s_o + s_o^T G~ s_o / mu^2
+// (g = w - rho/(sigma sqrt(mu)) = u - Z~ s_o / mu), where
+// G~ s_o = mu (x_o + beta_o y - s_o) because G~ M^-1 = mu (I - M^-1).
+// The consumers take the decision from the same fixed-order sums.
+// part_c[b*NPC + 0] = block sum of dr_i (G~ dr)_i; [1 + o*NPO + j] outcome o.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(NT1) k_step1c(Consts c, IterPtrs p, int nblk_gemv) {
+__device__ __forceinline__ void nspace_sums(const Consts& c, double rq, double rq1, double a1,
+                                            double xi, double pres, double yi, double* acc) {
+  const double comp = a1 - c.q / rq1;
+  acc[0] = pres * pres;
+  acc[1] = fmin(0.0, a1) * fmin(0.0, a1);
+  acc[2] = fmax(0.0, a1 - c.C) * fmax(0.0, a1 - c.C);
+  acc[3] = yi * a1;
+  acc[4] = xi * (c.C - a1);
+  acc[5] = comp * comp;
+  acc[6] = 1.0 / rq;
+  acc[7] = xi;
+  acc[8] = a1 > 0.0 ? pow(a1, c.qexp) : 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_step1c_rows(Consts c, IterPtrs p) {
   Scal* sc = p.sc;
   if (sc->done) return;
-  __shared__ double lds[(NT1 / 64) * 9];
-  double dGd = 0.0;
-  for (int b = threadIdx.x; b < nblk_gemv; b += NT1) dGd += p.part_n2[b];
-  dGd = block_sum<NT1>(dGd, lds);
-  const double ek = eps_k(c, sc->k);
-  const double res2 = dGd + sc->ytdr * sc->ytdr;
-  const bool dbl = sqrt(fmax(res2, 0.0)) > 5.0 * ek;
+  __shared__ double wsum[4][NPC];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int row = blockIdx.x * 4 + wid;
+  const bool mine = row < c.n && lane == 0;
+  double dr = 0.0, rn = 1.0, a0 = 0.0, yi = 0.0, xr = 0.0, pu = 0.0, s0 = 0.0, v0 = 0.0;
+  double f0 = 0.0, my0 = 0.0, t0 = 0.0;
+  if (mine) {
+    dr = p.dr[row];
+    rn = p.rn[row];
+    a0 = p.alpha[row];
+    yi = p.y[row];
+    xr = p.x[row];
+    pu = p.Pu[row];
+    s0 = p.s[row];
+    v0 = p.v[row];
+    f0 = p.f[row];
+    my0 = p.my[row];
+    t0 = p.t[row];
+  }
   const double sigma = sc->sigma;
-  double beta = sc->beta_bar;
-  if (dbl) {
-    double yf = 0.0;
-    for (int i = threadIdx.x; i < c.n; i += NT1) {
-      const double f = p.f[i] - p.hM[i];
-      p.f[i] = f;
-      yf += p.y[i] * f;
-    }
-    yf = block_sum<NT1>(yf, lds);
-    beta = -yf / c.ymy;
-  }
-  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int i = threadIdx.x; i < c.n; i += NT1) {
-    const double rn = p.x[i];
-    double s, v;
-    if (dbl) {
-      s = p.f[i] + beta * p.my[i];
-      v = s - (p.t[i] - p.dr[i]);
-      p.s[i] = s;
-      p.v[i] = v;
-    } else {
-      s = p.s[i];
-      v = p.v[i];
-    }
-    const double a0 = p.alpha[i];
-    const double yi = p.y[i];
-    // Step 2 (xi) and Step 3 (alpha)
-    const double xi = fmax(0.0, rn - v + (a0 - c.C) / sigma);
-    const double pres = v + xi - rn;
-    const double a1 = a0 - c.tau * sigma * pres;
-    p.xi[i] = xi;
-    p.alpha[i] = a1;
-    p.r[i] = rn;
-    p.sp[i] = yi * s * c.inv_zs;
-    p.ap[i] = yi * a1 * c.inv_zs;
+  const double beta_bar = sc->beta_bar;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < c.n; j += 256) acc = fma(p.my[j], p.dr[j], acc);
+  double hg = 0.0, hm = 0.0;
+  if (row < c.n)
+    wave_row_dot2(p.G + (size_t)row * c.n, p.Minv + (size_t)row * c.n, p.dr, c.n, lane, hg, hm);
+  const double mdr = bsum<256>(acc);
+  const double beta1 = beta_bar + mdr / c.ymy;
+  double out[NPC];
+#pragma unroll
+  for (int j = 0; j < NPC; ++j) out[j] = 0.0;
+  if (mine) {
     const double rq1 = pow_qp1(rn, c);
-    const double comp = a1 - c.q / rq1;
-    acc[0] += pres * pres;
-    acc[1] += fmin(0.0, a1) * fmin(0.0, a1);
-    acc[2] += fmax(0.0, a1 - c.C) * fmax(0.0, a1 - c.C);
-    acc[3] += yi * a1;
-    acc[4] += xi * (c.C - a1);
-    acc[5] += comp * comp;
-    acc[6] += 1.0 / pow_q(rn, c);
-    acc[7] += xi;
-    acc[8] += a1 > 0.0 ? pow(a1, c.qexp) : 0.0;
+    const double rq = pow_q(rn, c);
+    out[0] = dr * hg;
+    {  // outcome 0
+      const double s = s0;
+      const double v = v0;
+      const double xi = fmax(0.0, rn - v + (a0 - c.C) / sigma);
+      const double pres = v + xi - rn;
+      const double a1 = a0 - c.tau * sigma * pres;
+      p.xi0[row] = xi;
+      p.al0[row] = a1;
+      nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1);
+      out[1 + 9] = s * (c.mu * (xr + beta_bar * yi - s));
+      out[1 + 10] = pu * s;
+    }
+    {  // outcome 1
+      const double s = f0 - hm + beta1 * my0;
+      const double v = s - (t0 - dr);
+      const double xi = fmax(0.0, rn - v + (a0 - c.C) / sigma);
+      const double pres = v + xi - rn;
+      const double a1 = a0 - c.tau * sigma * pres;
+      p.s1[row] = s;
+      p.v1[row] = v;
+      p.xi1[row] = xi;
+      p.al1[row] = a1;
+      nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1 + NPO);
+      out[1 + NPO + 9] = s * (c.mu * (xr - dr + beta1 * yi - s));
+      out[1 + NPO + 10] = pu * s;
+    }
+    p.hG[row] = hg;
   }
-  block_sum_k<NT1, 9>(acc, lds);
-  if (threadIdx.x == 0) {
-    sc->beta = beta;
-    sc->doubled = dbl ? 1 : 0;
-    if (dbl) sc->n_double += 1;
-    for (int j = 0; j < 9; ++j) sc->red[R_PRES2 + j] = acc[j];
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NPC; ++j) wsum[wid][j] = out[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < NPC) {
+    const int j = threadIdx.x;
+    p.part_c[(size_t)blockIdx.x * NPC + j] = (wsum[0][j] + wsum[1][j]) + (wsum[2][j] + wsum[3][j]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->beta1 = beta1;
+}
+
+hipError_t launch_step1c_rows(const Consts& c, const IterPtrs& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_step1c_rows, dim3(ngemv_blocks(c.n)), dim3(256), 0, st, c, p);
+  return hipGetLastError();
+}
+
+// The Step 1c decision and the Step 2 ball scaling gamma = min(1, R/||g||),
+// from the block partials of both row kernels summed in a fixed order
+// (identical in every caller).
+struct Step2Plan {
+  int redo;
+  double gamma;
+};
+
+// a[0..5] are the summed plan partials (see plan_part); k and u2 the
+// iteration index and ||u||^2.
+__device__ __forceinline__ Step2Plan step2_plan_finish(const Consts& c, const double* a, int k,
+                                                       double u2) {
+  Step2Plan pl;
+  const double res2 = a[0] + a[1] * a[1];
+  pl.redo = sqrt(fmax(res2, 0.0)) > 5.0 * eps_k(c, k) ? 1 : 0;
+  const double sGs = pl.redo ? a[4] : a[2];
+  const double pus = pl.redo ? a[5] : a[3];
+  const double g2 = fmax(u2 - 2.0 / c.mu * pus + sGs / (c.mu * c.mu), 0.0);
+  const double ng = sqrt(g2);
+  pl.gamma = (ng <= c.R) ? 1.0 : c.R / ng;
+  return pl;
+}
+
+// Block partials that decide Step 1c and size the Step 2 ball scaling:
+// 0: dr^T G~ dr, 1: y^T dr, 2/3: s^T G~ s and (Z~^T u)^T s of outcome 0,
+// 4/5: the same for outcome 1.
+__device__ __forceinline__ double plan_part(const IterPtrs& p, int q, int b) {
+  const double* r = p.part_c + (size_t)b * NPC;
+  switch (q) {
+    case 0: return r[0];
+    case 1: return p.part_n1[b];
+    case 2: return r[1 + 9];
+    case 3: return r[1 + 10];
+    case 4: return r[1 + NPO + 9];
+    default: return r[1 + NPO + 10];
   }
 }
 
-hipError_t launch_step1c(const Consts& c, const IterPtrs& p, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_step1c, dim3(1), dim3(NT1), 0, st, c, p, nblk);
-  return hipGetLastError();
+// Every thread loads its share of the partials first (one round trip), then
+// one block reduction.
+template <int NT>
+__device__ __forceinline__ void plan_sums(const IterPtrs& p, int nb, double (&a)[6]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) a[j] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += NT) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a[j] += plan_part(p, j, b);
+  }
+  block_sum_k<NT, 6>(a);
+}
+
+template <int NT>
+__device__ __forceinline__ Step2Plan step2_plan(const Consts& c, const IterPtrs& p) {
+  const int k = p.sc->k;
+  const double u2 = p.sc->u2;
+  double a[6];
+  plan_sums<NT>(p, ngemv_blocks(c.n), a);
+  return step2_plan_finish(c, a, k, u2);
 }
 
 // ---------------------------------------------------------------------------
 // Pass over Z: zs = Z~ s and za = Z~ alpha^{k+1} row by row (the label signs
-// and 1/Z_scale are in sp, ap), fused with the Step 2 prologue:
+// and 1/Z_scale are applied to s and alpha while they are staged in LDS),
+// fused with Steps 2 and 3 in d-space:
 //   w = (b - zs)/mu,  b = mu u + sqrt(mu) rho / sigma,  g = w - rho/(sigma sqrt(mu)),
-// and a block partial of ||g||^2.  Block = NW waves over the same 64*V rows,
+//   u <- gamma g,  rho <- rho - tau sigma sqrt(mu) (w - u),
+// and block partials of ||w-u||^2, ||w||^2, ||za + sqrt(mu) rho||^2,
+// ||za||^2, ||rho||^2, ||u||^2.  Block = NW waves over the same 64*V rows,
 // wave j walks its share of the columns; partial row sums meet in LDS.
 // ---------------------------------------------------------------------------
 constexpr int PANEL = 2048;
 
-template <typename T, int NW>
+// FUSED = true when the streamed data is the data of record, so that the
+// n-space prediction of ||g|| is exact; the BF16 phase (FUSED = false)
+// writes w and Z~ alpha and leaves Steps 2-3 to k_dspace, which takes ||g||
+// from the pass itself.
+template <typename T, int NW, bool FUSED>
 __global__ void __launch_bounds__(NW * 64) k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
   if (p.sc->done) return;
   constexpr int V = Vec<T>::N;
   constexpr int ROWS = 64 * V;
   __shared__ double sv[2][PANEL];
   __shared__ double red[NW][2][ROWS];
-  __shared__ double lds[NW];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t rbase = (int64_t)blockIdx.x * ROWS;
   const T* xrow = X + rbase + lane * V;
+  const Step2Plan pl = step2_plan<NW * 64>(c, p);
+  const double* sv_s = pl.redo ? p.s1 : p.s;
+  const double* sv_a = pl.redo ? p.al1 : p.al0;
   double as[V], aa[V];
 #pragma unroll
   for (int e = 0; e < V; ++e) as[e] = aa[e] = 0.0;
   for (int pc = 0; pc < c.n; pc += PANEL) {
     const int pn = min(PANEL, c.n - pc);
     for (int i = threadIdx.x; i < pn; i += NW * 64) {
-      sv[0][i] = p.sp[pc + i];
-      sv[1][i] = p.ap[pc + i];
+      const double yz = p.y[pc + i] * c.inv_zs;
+      sv[0][i] = yz * sv_s[pc + i];
+      sv[1][i] = yz * sv_a[pc + i];
     }
     __syncthreads();
     const int per = (pn + NW - 1) / NW;
@@ -542,8 +721,10 @@ __global__ void __launch_bounds__(NW * 64) k_pass2(const T* __restrict__ X, Cons
   }
   __syncthreads();
   const double sigma = p.sc->sigma;
-  const double bu = c.mu, br = c.sqmu / sigma, gr = 1.0 / (sigma * c.sqmu);
-  double g2 = 0.0;
+  const double gamma = pl.gamma;
+  const double br = c.sqmu / sigma, gr = 1.0 / (sigma * c.sqmu);
+  const double rs = c.tau * sigma * c.sqmu;
+  double acc[NP2] = {0, 0, 0, 0, 0, 0};
   for (int rr = threadIdx.x; rr < ROWS; rr += NW * 64) {
     double zs = 0.0, za = 0.0;
 #pragma unroll
@@ -553,61 +734,45 @@ __global__ void __launch_bounds__(NW * 64) k_pass2(const T* __restrict__ X, Cons
     }
     const int64_t k = rbase + rr;
     const double rho = p.rho[k];
-    const double b = bu * p.u[k] + br * rho;
+    const double b = c.mu * p.u[k] + br * rho;
     const double w = (b - zs) / c.mu;
-    const double g = w - gr * rho;
     p.w[k] = w;
-    p.za[k] = za;
-    g2 += g * g;
+    if constexpr (FUSED) {
+      const double u = gamma * (w - gr * rho);
+      const double rn = rho - rs * (w - u);
+      p.u[k] = u;
+      p.rho[k] = rn;
+      const double dres = za + c.sqmu * rn;
+      acc[0] += (w - u) * (w - u);
+      acc[1] += w * w;
+      acc[2] += dres * dres;
+      acc[3] += za * za;
+      acc[4] += rn * rn;
+      acc[5] += u * u;
+    } else {
+      const double g = w - gr * rho;
+      p.za[k] = za;
+      acc[0] += g * g;
+    }
   }
-  g2 = block_sum<NW * 64>(g2, lds);
-  if (threadIdx.x == 0) p.part_g[blockIdx.x] = g2;
+  block_sum_k<NW * 64, NP2>(acc);
+  if (threadIdx.x < NP2) p.part_g[(size_t)blockIdx.x * NP2 + threadIdx.x] = acc[threadIdx.x];
 }
 
-template <typename T>
-static constexpr int pass2_waves() {
-  return sizeof(T) == 2 ? 4 : 8;
-}
-
-int pass2_blocks(int storage, int64_t ld) {
-  const int rows = storage == DWD_FP64 ? 128 : (storage == DWD_FP32 ? 256 : 512);
-  return (int)(ld / rows);
-}
-
-hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterPtrs& p,
-                        hipStream_t st) {
-  if (!X || !iter_ptrs_ok(p) || c.ld % kLdAlign != 0) return hipErrorInvalidValue;
-  const int nb = pass2_blocks(storage, c.ld);
-  if (storage == DWD_FP64)
-    hipLaunchKernelGGL((k_pass2<double, 8>), dim3(nb), dim3(512), 0, st, (const double*)X, c, p);
-  else if (storage == DWD_FP32)
-    hipLaunchKernelGGL((k_pass2<float, 8>), dim3(nb), dim3(512), 0, st, (const float*)X, c, p);
-  else
-    hipLaunchKernelGGL((k_pass2<uint16_t, 4>), dim3(nb), dim3(256), 0, st, (const uint16_t*)X, c,
-                       p);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Step 2 (u: projection onto the ball of radius Z_scale) and Step 3 (rho),
-// with the d-space partial sums ||w-u||^2, ||w||^2, ||Z~a + sqrt(mu) rho||^2,
-// ||Z~a||^2, ||rho||^2 (5 per block).
-// ---------------------------------------------------------------------------
-constexpr int ND = 5;
-
+// Steps 2 and 3 in d-space for the BF16 phase: gamma from the pass's own
+// ||g||^2, then u, rho and the same NP2 partials as the fused pass.
 __global__ void __launch_bounds__(256) k_dspace(Consts c, IterPtrs p, int nblk_p2) {
   Scal* sc = p.sc;
   if (sc->done) return;
-  __shared__ double lds[4 * ND];
   double g2 = 0.0;
-  for (int b = threadIdx.x; b < nblk_p2; b += 256) g2 += p.part_g[b];
-  g2 = block_sum<256>(g2, lds);
+  for (int b = threadIdx.x; b < nblk_p2; b += 256) g2 += p.part_g[(size_t)b * NP2];
+  g2 = block_sum<256>(g2);
   const double ng = sqrt(g2);
   const double gamma = (ng <= c.R) ? 1.0 : c.R / ng;
   const double sigma = sc->sigma;
   const double gr = 1.0 / (sigma * c.sqmu);
   const double rs = c.tau * sigma * c.sqmu;
-  double acc[ND] = {0, 0, 0, 0, 0};
+  double acc[NP2] = {0, 0, 0, 0, 0, 0};
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < c.ld;
        k += (int64_t)gridDim.x * 256) {
     const double w = p.w[k];
@@ -623,15 +788,11 @@ __global__ void __launch_bounds__(256) k_dspace(Consts c, IterPtrs p, int nblk_p
     acc[2] += dres * dres;
     acc[3] += za * za;
     acc[4] += rn * rn;
+    acc[5] += u * u;
   }
-  block_sum_k<256, ND>(acc, lds);
-  if (threadIdx.x == 0) {
-    for (int j = 0; j < ND; ++j) p.part_d[blockIdx.x * ND + j] = acc[j];
-    if (blockIdx.x == 0) {
-      sc->gamma = gamma;
-      sc->red[R_G2] = g2;
-    }
-  }
+  block_sum_k<256, NP2>(acc);
+  if (threadIdx.x < NP2) p.part_d[(size_t)blockIdx.x * NP2 + threadIdx.x] = acc[threadIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->gamma = gamma;
 }
 
 int dspace_blocks(int64_t ld) {
@@ -644,16 +805,37 @@ hipError_t launch_dspace(const Consts& c, const IterPtrs& p, int nblk_p2, hipStr
   return hipGetLastError();
 }
 
+int pass2_blocks(int storage, int64_t ld) {
+  const int rows = storage == DWD_FP64 ? 128 : (storage == DWD_FP32 ? 256 : 512);
+  return (int)(ld / rows);
+}
+
+hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterPtrs& p,
+                        hipStream_t st) {
+  if (!X || !iter_ptrs_ok(p) || c.ld % kLdAlign != 0) return hipErrorInvalidValue;
+  const int nb = pass2_blocks(storage, c.ld);
+  if (storage == DWD_FP64)
+    hipLaunchKernelGGL((k_pass2<double, 8, true>), dim3(nb), dim3(512), 0, st, (const double*)X,
+                       c, p);
+  else if (storage == DWD_FP32)
+    hipLaunchKernelGGL((k_pass2<float, 8, true>), dim3(nb), dim3(512), 0, st, (const float*)X, c,
+                       p);
+  else
+    hipLaunchKernelGGL((k_pass2<uint16_t, 4, false>), dim3(nb), dim3(256), 0, st,
+                       (const uint16_t*)X, c, p);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
-// Residuals of Section 4.3, stopping rule, sigma rule of Section 4.4, and the
-// recurrences Z~^T u^{k+1} = gamma (Z~^T w - Z~^T rho^k / (sigma sqrt(mu))),
-// Z~^T rho^{k+1} = Z~^T rho^k - tau sigma sqrt(mu) (Z~^T w - Z~^T u^{k+1}),
-// with Z~^T w = v - beta y.  One block.
+// Residuals of Section 4.3, stopping rule, sigma rule of Section 4.4; commit
+// of the Step 1c outcome; recurrences Z~^T u^{k+1} = gamma (Z~^T w - Z~^T rho^k
+// / (sigma sqrt(mu))) and Z~^T rho^{k+1} = Z~^T rho^k - tau sigma sqrt(mu)
+// (Z~^T w - Z~^T u^{k+1}) with Z~^T w = v - beta y; and the next iteration's
+// t = xi - r - alpha/sigma, x = t + Z~^T b / mu.  One block.
 // ---------------------------------------------------------------------------
-__device__ void finish_etas(const Consts& c, Scal* sc) {
+// Residuals of Section 4.3 from the reduced sums r[], computed in registers.
+__device__ __forceinline__ void finish_etas(const Consts& c, const double* r, double* e) {
   const double den = c.opC;
-  double* e = sc->eta;
-  const double* r = sc->red;
   e[E_P1] = sqrt(r[R_PRES2]) / den;
   e[E_P2] = c.sqmu * sqrt(r[R_WU2]) / den;
   e[E_P3] = fmax(sqrt(r[R_W2]) - c.R, 0.0) / den;
@@ -673,37 +855,82 @@ __device__ void finish_etas(const Consts& c, Scal* sc) {
   e[E_C] = fmax(e[E_C1], fmax(e[E_C2], e[E_C3]));
 }
 
-__global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d) {
+constexpr int NT1 = 512;
+
+// fused = 1: d-space partials and gamma come from the fused pass (part_g,
+// step2_plan); fused = 0: from k_dspace (part_d, sc->gamma).
+__global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d, int fused) {
   Scal* sc = p.sc;
   if (sc->done) return;
-  __shared__ double lds[(NT1 / 64) * ND];
-  double acc[ND] = {0, 0, 0, 0, 0};
+  __shared__ double s_sigma;
+  const int nb = ngemv_blocks(c.n);
+  // every device scalar this kernel needs, loaded at once
+  const int k0 = sc->k;
+  const double u2 = sc->u2;
+  const double sigma = sc->sigma;
+  const double gamma_d = sc->gamma;
+  const double beta_bar = sc->beta_bar;
+  const double beta_1 = sc->beta1;
+  const int nd = sc->n_double;
+  const int nm = sc->newton_max;
+  // The plan sums decide the outcome; then that outcome's nine n-space sums,
+  // the d-space sums and the largest Newton step count.
+  double pa[6];
+  plan_sums<NT1>(p, nb, pa);
+  const Step2Plan pl = step2_plan_finish(c, pa, k0, u2);
+  const int o = pl.redo;
+  constexpr int K = 9 + NP2;
+  double acc[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) acc[j] = 0.0;
+  double nmax = 0.0;
+  const double* pd_src = fused ? p.part_g : p.part_d;
+  for (int b = threadIdx.x; b < nb; b += NT1) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc[j] += p.part_c[(size_t)b * NPC + 1 + o * NPO + j];
+    nmax = fmax(nmax, p.part_it[b]);
+  }
   for (int b = threadIdx.x; b < nblk_d; b += NT1)
 #pragma unroll
-    for (int j = 0; j < ND; ++j) acc[j] += p.part_d[b * ND + j];
-  block_sum_k<NT1, ND>(acc, lds);
-  const double sigma = sc->sigma;
-  const double gamma = sc->gamma;
-  const double beta = sc->beta;
-  const double gr = 1.0 / (sigma * c.sqmu);
-  const double rs = c.tau * sigma * c.sqmu;
-  for (int i = threadIdx.x; i < c.n; i += NT1) {
-    const double ztw = p.v[i] - beta * p.y[i];
-    const double pr = p.Prho[i];
-    const double pu = gamma * (ztw - gr * pr);
-    p.Pu[i] = pu;
-    p.Prho[i] = pr - rs * (ztw - pu);
+    for (int j = 0; j < NP2; ++j) acc[9 + j] += pd_src[(size_t)b * NP2 + j];
+  block_sum_k<NT1, K>(acc);
+  {
+    __shared__ double smax[NT1 / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nmax = fmax(nmax, __shfl_xor(nmax, off, 64));
+    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = nmax;
+    __syncthreads();
+    double m = smax[0];
+    for (int w = 1; w < NT1 / 64; ++w) m = fmax(m, smax[w]);
+    nmax = m;
   }
+
+  const double gamma = fused ? pl.gamma : gamma_d;
+  const double beta = o ? beta_1 : beta_bar;
   if (threadIdx.x == 0) {
-    sc->red[R_WU2] = acc[0];
-    sc->red[R_W2] = acc[1];
-    sc->red[R_DRES2] = acc[2];
-    sc->red[R_ZA2] = acc[3];
-    sc->red[R_RHO2] = acc[4];
-    finish_etas(c, sc);
-    const double* e = sc->eta;
-    const int k1 = sc->k + 1;
+    const double m = nmax;
+    double red[R_COUNT];
+    for (int j = 0; j < 9; ++j) red[R_PRES2 + j] = acc[j];
+    red[R_WU2] = acc[9];
+    red[R_W2] = acc[10];
+    red[R_DRES2] = acc[11];
+    red[R_ZA2] = acc[12];
+    red[R_G2] = 0.0;
+    red[R_RHO2] = acc[13];
+    double e[E_COUNT];
+    e[E_PCHK] = e[E_DCHK] = 0.0;
+    finish_etas(c, red, e);
+    for (int j = 0; j < R_COUNT; ++j) sc->red[j] = red[j];
+    for (int j = 0; j < E_COUNT; ++j) sc->eta[j] = e[j];
+    sc->u2 = acc[14];
+    sc->gamma = gamma;
+    sc->beta = beta;
+    sc->doubled = o;
+    sc->n_double = nd + o;
+    if ((int)m > nm) sc->newton_max = (int)m;
+    const int k1 = k0 + 1;
     sc->k = k1;
+    double sig = sigma;
     const double pd = fmax(e[E_P], e[E_D]);
     const double cg_min = fmin(e[E_C], e[E_GAP]), cg_max = fmax(e[E_C], e[E_GAP]);
     if (pd < c.tol && cg_min < sqrt(c.tol) && cg_max < 0.05) {
@@ -714,17 +941,50 @@ __global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d) 
       const double ep = e[E_P], ed = e[E_D];
       if (ep >= 1e-300 && ed >= 1e-300) {
         const double chi = ep / ed;
-        const double m = fmax(chi, 1.0 / chi);
-        const double zeta = m > 500.0 ? 2.2 : (m > 50.0 ? 1.65 : 1.1);
-        if (chi > 5.0) sc->sigma = sigma * zeta;
-        else if (1.0 / chi > 5.0) sc->sigma = sigma / zeta;
+        const double mm = fmax(chi, 1.0 / chi);
+        const double zeta = mm > 500.0 ? 2.2 : (mm > 50.0 ? 1.65 : 1.1);
+        if (chi > 5.0) sig = sigma * zeta;
+        else if (1.0 / chi > 5.0) sig = sigma / zeta;
       }
     }
+    sc->sigma = sig;
+    s_sigma = sig;
+  }
+  __syncthreads();
+  const double sig1 = s_sigma;
+  const double gr = 1.0 / (sigma * c.sqmu);
+  const double rs = c.tau * sigma * c.sqmu;
+  const double* xs = o ? p.xi1 : p.xi0;
+  const double* as = o ? p.al1 : p.al0;
+  const double* ss = o ? p.s1 : p.s;
+  const double* vs = o ? p.v1 : p.v;
+  for (int i = threadIdx.x; i < c.n; i += NT1) {
+    const double rn = p.rn[i];
+    const double xi = xs[i];
+    const double al = as[i];
+    const double v = vs[i];
+    p.r[i] = rn;
+    p.xi[i] = xi;
+    p.alpha[i] = al;
+    if (o) {
+      p.s[i] = ss[i];
+      p.v[i] = v;
+    }
+    const double ztw = v - beta * p.y[i];
+    const double pr = p.Prho[i];
+    const double pu = gamma * (ztw - gr * pr);
+    const double prn = pr - rs * (ztw - pu);
+    p.Pu[i] = pu;
+    p.Prho[i] = prn;
+    const double t = xi - rn - al / sig1;
+    p.t[i] = t;
+    p.x[i] = t + (c.mu * pu + c.sqmu * prn / sig1) / c.mu;
   }
 }
 
-hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, hipStream_t st) {
-  hipLaunchKernelGGL(k_tail, dim3(1), dim3(NT1), 0, st, c, p, nblk_d);
+hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, int fused,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_tail, dim3(1), dim3(NT1), 0, st, c, p, nblk_d, fused);
   return hipGetLastError();
 }
 
@@ -736,7 +996,6 @@ hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, hipStream
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(NT1) k_check(Consts c, IterPtrs p, int nchunks) {
   Scal* sc = p.sc;
-  __shared__ double lds[(NT1 / 64) * 3];
   double acc[3] = {0, 0, 0};
   for (int i = threadIdx.x; i < c.n; i += NT1) {
     double sw = 0.0, sr = 0.0;
@@ -753,7 +1012,7 @@ __global__ void __launch_bounds__(NT1) k_check(Consts c, IterPtrs p, int nchunks
     acc[1] += a * p.hG[i];
     acc[2] += a * ztr;
   }
-  block_sum_k<NT1, 3>(acc, lds);
+  block_sum_k<NT1, 3>(acc);
   if (threadIdx.x == 0) {
     const double den = c.opC;
     const double* e = sc->eta;
@@ -775,10 +1034,9 @@ hipError_t launch_check(const Consts& c, const IterPtrs& p, int nchunks, hipStre
 // ||v||^2 over ld entries into out[0] (one block, fixed order).
 __global__ void __launch_bounds__(1024) k_norm2(const double* __restrict__ v, int64_t m,
                                                 double* __restrict__ out) {
-  __shared__ double lds[16];
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < m; i += 1024) acc += v[i] * v[i];
-  acc = block_sum<1024>(acc, lds);
+  acc = block_sum<1024>(acc);
   if (threadIdx.x == 0) out[0] = acc;
 }
 

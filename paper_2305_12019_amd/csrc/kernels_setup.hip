@@ -26,7 +26,6 @@ __global__ void __launch_bounds__(256) k_frob_copy(const Tin* __restrict__ X, in
                                                    void* __restrict__ Xs, int storage, int64_t ld,
                                                    uint16_t* __restrict__ X16,
                                                    double* __restrict__ part) {
-  __shared__ double lds[4];
   const int col = blockIdx.x;
   const int64_t per = (ld + gridDim.y - 1) / gridDim.y;
   const int64_t r0 = (int64_t)blockIdx.y * per;
@@ -45,7 +44,7 @@ __global__ void __launch_bounds__(256) k_frob_copy(const Tin* __restrict__ X, in
       if (X16) X16[o] = f32_to_bf16_rne(f);
     }
   }
-  acc = block_sum<256>(acc, lds);
+  acc = block_sum<256>(acc);
   if (threadIdx.x == 0) part[(int64_t)blockIdx.y * n + col] = acc;
 }
 
@@ -72,10 +71,9 @@ hipError_t launch_frob_copy(const void* X, int in_dtype, int64_t d, int n, void*
 // Deterministic sum of `count` doubles by one block.
 __global__ void __launch_bounds__(1024) k_sum(const double* __restrict__ part, int count,
                                               double* __restrict__ out) {
-  __shared__ double lds[16];
   double acc = 0.0;
   for (int i = threadIdx.x; i < count; i += blockDim.x) acc += part[i];
-  acc = block_sum<1024>(acc, lds);
+  acc = block_sum<1024>(acc);
   if (threadIdx.x == 0) *out = acc;
 }
 
@@ -93,12 +91,37 @@ hipError_t launch_sum(const double* part, int count, double* out, hipStream_t st
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 64;   // tile edge
-constexpr int GK = 16;   // k-depth per LDS stage
+constexpr int GK = 32;   // k-depth per LDS stage (divides the padded ld)
 
+// Stage GK x 64 of the columns c0.. of the stored data into LDS as FP64,
+// with 16-byte loads along k (the contiguous direction).
 template <typename T>
-__device__ __forceinline__ double load_el(const void* Xs, int64_t o) {
-  if constexpr (sizeof(T) == 8) return ((const double*)Xs)[o];
-  else return (double)((const float*)Xs)[o];
+__device__ __forceinline__ void gram_stage(const void* Xs, int64_t ld, int n, int c0, int64_t kb,
+                                           double (*S)[GT + 1]) {
+  constexpr int V = 16 / sizeof(T);             // elements per 16-byte load
+  constexpr int PER_COL = GK / V;
+  for (int e = threadIdx.x; e < GT * PER_COL; e += 256) {
+    const int c = e / PER_COL, kq = (e % PER_COL) * V;
+    const int gc = c0 + c;
+    if (gc < n) {
+      if constexpr (sizeof(T) == 8) {
+        const double2 v = *reinterpret_cast<const double2*>((const double*)Xs + (int64_t)gc * ld +
+                                                           kb + kq);
+        S[kq][c] = v.x;
+        S[kq + 1][c] = v.y;
+      } else {
+        const float4 v = *reinterpret_cast<const float4*>((const float*)Xs + (int64_t)gc * ld +
+                                                         kb + kq);
+        S[kq][c] = v.x;
+        S[kq + 1][c] = v.y;
+        S[kq + 2][c] = v.z;
+        S[kq + 3][c] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < V; ++q) S[kq + q][c] = 0.0;
+    }
+  }
 }
 
 template <typename T>
@@ -132,14 +155,8 @@ __global__ void __launch_bounds__(256) k_gram_mfma(const void* __restrict__ Xs, 
     for (int b = 0; b < 2; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
 
   for (int64_t kb = k0; kb < k1; kb += GK) {
-    // load GK x 64 of columns i0.. and j0.. (column-major: k contiguous)
-    for (int e = tid; e < GK * GT; e += 256) {
-      const int c = e / GK, kk = e % GK;
-      const int64_t k = kb + kk;
-      const int gi = i0 + c, gj = j0 + c;
-      As[kk][c] = (gi < n && k < k1) ? load_el<T>(Xs, (int64_t)gi * ld + k) : 0.0;
-      Bs[kk][c] = (gj < n && k < k1) ? load_el<T>(Xs, (int64_t)gj * ld + k) : 0.0;
-    }
+    gram_stage<T>(Xs, ld, n, i0, kb, As);
+    gram_stage<T>(Xs, ld, n, j0, kb, Bs);
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 4) {
@@ -237,38 +254,55 @@ constexpr int LEAF = 64;
 
 __global__ void __launch_bounds__(256) k_spd_leaf_inv(double* __restrict__ M, int ldm, int m,
                                                       int* __restrict__ status) {
-  __shared__ double A[LEAF][LEAF + 1];
+  // Thread t holds row i = t/4, columns [16*(t%4), 16*(t%4) + 16) in
+  // registers; the block beyond m x m is the identity, which the
+  // elimination leaves unchanged.
   __shared__ double prow[LEAF];
   __shared__ double pcol[LEAF];
   const int tid = threadIdx.x;
-  for (int e = tid; e < m * m; e += 256) A[e / m][e % m] = M[(size_t)(e / m) * ldm + (e % m)];
-  __syncthreads();
+  const int i = tid >> 2;
+  const int j0 = (tid & 3) * 16;
+  double a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int j = j0 + q;
+    a[q] = (i < m && j < m) ? M[(size_t)i * ldm + j] : (i == j ? 1.0 : 0.0);
+  }
   for (int p = 0; p < m; ++p) {
-    const double piv = A[p][p];
-    if (!(piv > 0.0)) {  // not positive definite (or NaN)
+    if (i == p) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) prow[j0 + q] = a[q];
+    }
+    if (p >= j0 && p < j0 + 16) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (j0 + q == p) pcol[i] = a[q];
+    }
+    __syncthreads();
+    const double piv = prow[p];
+    if (!(piv > 0.0)) {  // not positive definite (or NaN): same branch in every thread
       if (tid == 0) atomicExch(status, 1);
       return;
     }
     const double ip = 1.0 / piv;
-    // scaled pivot row and the pivot column as it was before this step
-    for (int j = tid; j < m; j += 256) {
-      prow[j] = (j == p) ? ip : A[p][j] * ip;
-      pcol[j] = A[j][p];
-    }
-    __syncthreads();
-    // eliminate column p from every other row
-    for (int e = tid; e < m * m; e += 256) {
-      const int i = e / m, j = e % m;
-      if (i == p) continue;
+    if (i == p) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] = (j0 + q == p) ? ip : a[q] * ip;
+    } else {
       const double f = pcol[i];
-      if (j == p) A[i][j] = -f * ip;
-      else A[i][j] -= f * prow[j];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int j = j0 + q;
+        a[q] = (j == p) ? -f * ip : fma(-f * ip, prow[j], a[q]);
+      }
     }
-    __syncthreads();
-    for (int j = tid; j < m; j += 256) A[p][j] = prow[j];
     __syncthreads();
   }
-  for (int e = tid; e < m * m; e += 256) M[(size_t)(e / m) * ldm + (e % m)] = A[e / m][e % m];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int j = j0 + q;
+    if (i < m && j < m) M[(size_t)i * ldm + j] = a[q];
+  }
 }
 
 // C(mxn) = alpha * op(A) op(B) + beta * C, row-major, FP64, 64x64 tiles.
@@ -284,13 +318,19 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int m, int n, int k, double al
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   double acc[4][4] = {};
   for (int l0 = 0; l0 < k; l0 += 16) {
+    // consecutive threads read consecutive addresses of the stored layout
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      const int ll = e / 64, c = e % 64;
+      int ll, c;
+      if (ta) { ll = e >> 6; c = e & 63; } else { c = e >> 4; ll = e & 15; }
       const int gi = i0 + c, gl = l0 + ll;
       double va = 0.0;
       if (gi < m && gl < k) va = ta ? A[(size_t)gl * lda + gi] : A[(size_t)gi * lda + gl];
       As[ll][c] = va;
-      const int gj = j0 + c;
+    }
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      int ll, c;
+      if (tb) { c = e >> 4; ll = e & 15; } else { ll = e >> 6; c = e & 63; }
+      const int gj = j0 + c, gl = l0 + ll;
       double vb = 0.0;
       if (gj < n && gl < k) vb = tb ? B[(size_t)gj * ldb + gl] : B[(size_t)gl * ldb + gj];
       Bs[ll][c] = vb;
@@ -398,10 +438,9 @@ hipError_t launch_gemv_rows(const double* A, int n, const double* x, double* out
 __global__ void __launch_bounds__(1024) k_dot(const double* __restrict__ a,
                                               const double* __restrict__ b, int n,
                                               double* __restrict__ out) {
-  __shared__ double lds[16];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) acc += a[i] * b[i];
-  acc = block_sum<1024>(acc, lds);
+  acc = block_sum<1024>(acc);
   if (threadIdx.x == 0) *out = acc;
 }
 

@@ -55,7 +55,9 @@ class Info(C.Structure):
                 ("iters", C.c_int32), ("n_double", C.c_int32), ("newton_max", C.c_int32),
                 ("converged", C.c_int32), ("iters_lowp", C.c_int32), ("status", C.c_int32),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("stream_ms", C.c_double),
-                ("stream_launches", C.c_int32), ("reserved", C.c_int32)]
+                ("stream_launches", C.c_int32), ("resumed", C.c_int32),
+                ("streamT_ms", C.c_double), ("streamT_launches", C.c_int32),
+                ("reserved", C.c_int32)]
 
     def to_dict(self) -> Dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
