@@ -90,7 +90,9 @@ typedef struct {
   int32_t refine;    /* BF16 storage: continue on FP32 data until tol is met    */
   double lowp_tol;   /* BF16 storage: tolerance of the BF16 phase; <= 0: 30*tol */
   int32_t profile;   /* 1: time the Z-streaming kernels with HIP events         */
-  int32_t reserved;
+  int32_t batch_fp32; /* dwd_solve_batch: 1 = FP32 MFMA products (FP64 sums
+                        across K tiles, relative error ~1e-7 per pass, checked
+                        and refined in FP64 at the end); 0 = FP64 MFMA (default) */
 } dwd_params;
 
 /* Per-solve report.  Residuals are those of Section 4.3 on the scaled

@@ -1,23 +1,265 @@
-// Batched solve over one shared X (placeholder: problems run one after the
-// other on the shared set-up; the stepped-together path replaces it).
+// dwd_solve_batch: B problems over one shared X stepped together.  The host
+// queues iterations in chunks and, one chunk behind, reads every problem's
+// stop flag; converged problems leave the active-slot list (double-buffered
+// on the device, so the chunk in flight keeps its own list).
 #include <hip/hip_runtime.h>
+#include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "dwd_solver.h"
 
 namespace dwd {
 
-dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_info* info) {
-  dwd_status worst = DWD_OK;
-  for (int j = 0; j < B; ++j) {
-    dwd_status s = solve_problem(P, &p[j], W ? W + (size_t)j * P->d : nullptr,
-                                 info ? &info[j] : nullptr, nullptr, nullptr, nullptr, nullptr,
-                                 nullptr);
-    if (s < 0) return s;
-    if (s == DWD_NOT_CONVERGED) worst = DWD_NOT_CONVERGED;
+hipError_t launch_init_b(const BatchPtrs& P, int B, hipStream_t st);
+hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, const BatchPtrs& P,
+                                  const int* idx, int bact, hipStream_t st);
+hipError_t launch_check_b(const BatchPtrs& P, int p, const double* partT, int nchunks,
+                          hipStream_t st);
+hipError_t launch_resume_b(const BatchPtrs& P, const int* idx, int cnt, hipStream_t st);
+hipError_t launch_anchor_b(const BatchPtrs& P, int p, const double* partT, int nchunks,
+                           hipStream_t st);
+int batch_pass_row_blocks(int64_t ld);
+
+namespace {
+
+struct BatchBuffers {
+  std::vector<void*> dev;
+  std::vector<void*> host;
+  ~BatchBuffers() {
+    for (void* q : dev) (void)hipFree(q);
+    for (void* q : host) (void)hipHostFree(q);
   }
-  return worst;
+  hipError_t dalloc(void** q, size_t bytes) {
+    hipError_t e = hipMalloc(q, bytes ? bytes : 8);
+    if (e == hipSuccess) dev.push_back(*q);
+    return e;
+  }
+  hipError_t halloc(void** q, size_t bytes) {
+    hipError_t e = hipHostMalloc(q, bytes ? bytes : 8, 0);
+    if (e == hipSuccess) host.push_back(*q);
+    return e;
+  }
+};
+
+}  // namespace
+
+#define HIP_TRY_B(expr)                                  \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
+  } while (0)
+
+dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_info* info) {
+  for (int j = 0; j < B; ++j) {
+    dwd_status s = validate_params(&p[j], true);
+    if (s != DWD_OK) return s;
+  }
+  HIP_TRY_B(hipSetDevice(P->device));
+  const hipStream_t st = P->stream;
+  const int n = P->n;
+  const int64_t ld = P->ld;
+  BatchBuffers bb;
+  BatchPtrs bp{};
+  bp.y = P->y;
+  bp.my = P->my;
+  bp.Minv = P->Minv;
+  bp.G = P->G;
+  bp.n = n;
+  bp.ld = ld;
+  bp.nb = ngemv_blocks(n);
+  bp.npb = batch_pass_row_blocks(ld);
+  const size_t nB = (size_t)n * B;
+  double* nv = nullptr;
+  HIP_TRY_B(bb.dalloc((void**)&nv, nB * 19 * 8));
+  double* q = nv;
+  for (double** dst : {&bp.R, &bp.XI, &bp.AL, &bp.PU, &bp.PR, &bp.T, &bp.XX, &bp.F, &bp.S, &bp.V,
+                       &bp.DR, &bp.RN, &bp.S1, &bp.V1, &bp.XI0, &bp.XI1, &bp.AL0, &bp.AL1,
+                       &bp.HA}) {
+    *dst = q;
+    q += nB;
+  }
+  double* dv = nullptr;
+  HIP_TRY_B(bb.dalloc((void**)&dv, (size_t)ld * B * 3 * 8));
+  bp.U = dv;
+  bp.RHO = dv + (size_t)ld * B;
+  bp.W = dv + 2 * (size_t)ld * B;
+  HIP_TRY_B(bb.dalloc((void**)&bp.SB, nB * 8));
+  HIP_TRY_B(bb.dalloc((void**)&bp.part_n1, (size_t)B * bp.nb * 8));
+  HIP_TRY_B(bb.dalloc((void**)&bp.part_it, (size_t)B * bp.nb * 8));
+  HIP_TRY_B(bb.dalloc((void**)&bp.part_ga, (size_t)B * bp.nb * 8));
+  HIP_TRY_B(bb.dalloc((void**)&bp.part_c, (size_t)B * bp.nb * NPC * 8));
+  HIP_TRY_B(bb.dalloc((void**)&bp.part_g, (size_t)B * bp.npb * NP2 * 8));
+  HIP_TRY_B(bb.dalloc((void**)&bp.sc, (size_t)B * sizeof(Scal)));
+  Consts* dcs = nullptr;
+  HIP_TRY_B(bb.dalloc((void**)&dcs, (size_t)B * sizeof(Consts)));
+  bp.cs = dcs;
+  int* didx[2];
+  HIP_TRY_B(bb.dalloc((void**)&didx[0], (size_t)B * 4));
+  HIP_TRY_B(bb.dalloc((void**)&didx[1], (size_t)B * 4));
+  int* hidx[2];
+  HIP_TRY_B(bb.halloc((void**)&hidx[0], (size_t)B * 4));
+  HIP_TRY_B(bb.halloc((void**)&hidx[1], (size_t)B * 4));
+  Scal* hsc[2];
+  HIP_TRY_B(bb.halloc((void**)&hsc[0], (size_t)B * sizeof(Scal)));
+  HIP_TRY_B(bb.halloc((void**)&hsc[1], (size_t)B * sizeof(Scal)));
+  Consts* hcs = nullptr;
+  HIP_TRY_B(bb.halloc((void**)&hcs, (size_t)B * sizeof(Consts)));
+  // FP64 MFMA products by default.  FP32 MFMA (opt-in; FP64 sums across K
+  // tiles) carries a relative error of about 1e-7 per pass, which the n-space
+  // recurrences of Z~^T u and Z~^T rho accumulate; the final FP64 check and the
+  // re-anchored FP64 resume below repair that.
+  int max_iter = 1;
+  int fp64_mfma = 1;
+  for (int j = 0; j < B; ++j) {
+    if (p[j].batch_fp32 && p[j].tol >= 1e-6) fp64_mfma = 0;
+    hcs[j] = make_consts(P, &p[j]);
+    hcs[j].sigma0 = default_sigma0(&p[j], n);
+    max_iter = std::max(max_iter, p[j].max_iter);
+    hidx[0][j] = j;
+  }
+  hipEvent_t e0, e1, ev[2];
+  HIP_TRY_B(hipEventCreate(&e0));
+  HIP_TRY_B(hipEventCreate(&e1));
+  HIP_TRY_B(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HIP_TRY_B(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t* a;
+    int k;
+    ~EvGuard() {
+      for (int i = 0; i < k; ++i) (void)hipEventDestroy(a[i]);
+    }
+  };
+  hipEvent_t all_ev[4] = {e0, e1, ev[0], ev[1]};
+  EvGuard guard{all_ev, 4};
+  HIP_TRY_B(hipEventRecord(e0, st));
+  HIP_TRY_B(hipMemcpyAsync(dcs, hcs, (size_t)B * sizeof(Consts), hipMemcpyHostToDevice, st));
+  HIP_TRY_B(hipMemcpyAsync(didx[0], hidx[0], (size_t)B * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY_B(launch_init_b(bp, B, st));
+
+  const int chunk = std::max(1, p[0].check_every > 0 ? p[0].check_every : 8);
+  // Run the stepping loop over the active list in didx[cur] (bact entries)
+  // until every listed problem has stopped or `budget` iterations are queued.
+  int cur = 0;
+  auto run = [&](int bact, int budget, int fp64) -> dwd_status {
+    int queued = 0, pending = -1;
+    for (int cidx = 0;; ++cidx) {
+      for (int j = 0; j < chunk && queued < budget; ++j, ++queued)
+        HIP_TRY_B(launch_batch_iteration(P->X_rec, P->st_rec, fp64, bp, didx[cur], bact, st));
+      const int slot = cidx & 1;
+      HIP_TRY_B(hipMemcpyAsync(hsc[slot], bp.sc, (size_t)B * sizeof(Scal),
+                               hipMemcpyDeviceToHost, st));
+      HIP_TRY_B(hipEventRecord(ev[slot], st));
+      if (queued >= budget) break;
+      if (pending >= 0) {
+        HIP_TRY_B(hipEventSynchronize(ev[pending & 1]));
+        const Scal* hs = hsc[pending & 1];
+        int nact = 0;
+        int* nidx = hidx[1 - cur];
+        for (int j = 0; j < B; ++j)
+          if (!hs[j].done) nidx[nact++] = j;
+        if (nact == 0) break;
+        if (nact < bact) {
+          HIP_TRY_B(hipMemcpyAsync(didx[1 - cur], nidx, (size_t)nact * 4,
+                                   hipMemcpyHostToDevice, st));
+          cur = 1 - cur;
+          bact = nact;
+        }
+      }
+      pending = cidx;
+    }
+    HIP_TRY_B(hipStreamSynchronize(st));
+    return DWD_OK;
+  };
+  // Final FP64 check of every listed problem over the data of record.
+  auto check = [&](const int* list, int cnt) -> dwd_status {
+    for (int i = 0; i < cnt; ++i) {
+      const int j = list[i];
+      HIP_TRY_B(launch_gemvT(P->X_rec, P->st_rec, ld, n, bp.W + (size_t)j * ld,
+                             bp.RHO + (size_t)j * ld, P->ip.partT, nullptr, st));
+      HIP_TRY_B(launch_check_b(bp, j, P->ip.partT, P->nchunks, st));
+    }
+    HIP_TRY_B(hipMemcpyAsync(hsc[0], bp.sc, (size_t)B * sizeof(Scal), hipMemcpyDeviceToHost, st));
+    HIP_TRY_B(hipStreamSynchronize(st));
+    return DWD_OK;
+  };
+  dwd_status rs;
+  if ((rs = run(B, max_iter, fp64_mfma)) != DWD_OK) return rs;
+  std::vector<int> all(B);
+  for (int j = 0; j < B; ++j) all[j] = j;
+  if ((rs = check(all.data(), B)) != DWD_OK) return rs;
+  // Problems that stopped on their in-loop residuals but miss the tolerance
+  // in the FP64 check continue with FP64 products (at most twice).
+  std::vector<int> resumed(B, 0);
+  for (int round = 0; round < 2; ++round) {
+    std::vector<int> again;
+    int left = 0;
+    for (int j = 0; j < B; ++j) {
+      const Scal& hs = hsc[0][j];
+      const double chk = std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]);
+      if (hs.converged && chk >= p[j].tol && hs.k < p[j].max_iter) {
+        again.push_back(j);
+        left = std::max(left, p[j].max_iter - hs.k);
+      }
+    }
+    if (again.empty()) break;
+    for (size_t i = 0; i < again.size(); ++i) {
+      hidx[1 - cur][i] = again[i];
+      resumed[again[i]] += 1;
+    }
+    HIP_TRY_B(hipMemcpyAsync(didx[1 - cur], hidx[1 - cur], again.size() * 4,
+                             hipMemcpyHostToDevice, st));
+    cur = 1 - cur;
+    HIP_TRY_B(launch_resume_b(bp, didx[cur], (int)again.size(), st));
+    for (int j : again) {
+      HIP_TRY_B(launch_gemvT(P->X_rec, P->st_rec, ld, n, bp.U + (size_t)j * ld,
+                             bp.RHO + (size_t)j * ld, P->ip.partT, nullptr, st));
+      HIP_TRY_B(launch_anchor_b(bp, j, P->ip.partT, P->nchunks, st));
+    }
+    if ((rs = run((int)again.size(), left, 1)) != DWD_OK) return rs;
+    if ((rs = check(again.data(), (int)again.size())) != DWD_OK) return rs;
+  }
+  HIP_TRY_B(hipEventRecord(e1, st));
+  HIP_TRY_B(hipStreamSynchronize(st));
+  float ms = 0.0f;
+  HIP_TRY_B(hipEventElapsedTime(&ms, e0, e1));
+  if (W) {
+    std::vector<double> hw((size_t)P->d);
+    for (int j = 0; j < B; ++j) {
+      HIP_TRY_B(hipMemcpy(hw.data(), bp.W + (size_t)j * ld, P->d * 8, hipMemcpyDeviceToHost));
+      for (int64_t k = 0; k < P->d; ++k) W[(size_t)j * P->d + k] = hw[k] / P->zscale;
+    }
+  }
+  bool all_conv = true;
+  for (int j = 0; j < B; ++j) {
+    const Scal& hs = hsc[0][j];
+    all_conv = all_conv && hs.converged;
+    if (info) {
+      dwd_info& in = info[j];
+      memset(&in, 0, sizeof(in));
+      in.beta = hs.beta;
+      in.primal_obj = hs.eta[E_PRIM];
+      in.dual_obj = hs.eta[E_DUAL];
+      in.eta_p = hs.eta[E_P];
+      in.eta_d = hs.eta[E_D];
+      in.eta_c = hs.eta[E_C];
+      in.eta_gap = hs.eta[E_GAP];
+      in.eta_p_check = hs.eta[E_PCHK];
+      in.eta_d_check = hs.eta[E_DCHK];
+      in.kkt_check = std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]);
+      in.sigma = hs.sigma;
+      in.iters = hs.k;
+      in.n_double = hs.n_double;
+      in.newton_max = hs.newton_max;
+      in.converged = hs.converged;
+      in.setup_ms = P->setup_ms;
+      in.solve_ms = ms;
+      in.status = hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
+      in.resumed = resumed[j];
+    }
+  }
+  return all_conv ? DWD_OK : DWD_NOT_CONVERGED;
 }
 
 }  // namespace dwd

@@ -1,0 +1,247 @@
+// Device functions shared by the single-problem and the batched kernels.
+#pragma once
+
+#include <float.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "dwd_internal.h"
+
+namespace dwd {
+
+// ---------------------------------------------------------------------------
+// Vector loads of the stored data, converted to FP64.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+  static constexpr int N = 2;
+  __device__ static __forceinline__ void load(const double* p, double (&o)[2]) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+};
+template <>
+struct Vec<float> {
+  static constexpr int N = 4;
+  __device__ static __forceinline__ void load(const float* p, double (&o)[4]) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+};
+template <>
+struct Vec<uint16_t> {
+  static constexpr int N = 8;
+  __device__ static __forceinline__ void load(const uint16_t* p, double (&o)[8]) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      o[2 * i] = (double)__uint_as_float(w[i] << 16);
+      o[2 * i + 1] = (double)__uint_as_float(w[i] & 0xFFFF0000u);
+    }
+  }
+};
+
+
+// ---------------------------------------------------------------------------
+// Step 1b: prox of theta_q by the Newton map of Section 3.2 (eq-varphi),
+// warm-started at r^k, with the bracket safeguard.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double pow_qp1(double s, const Consts& c) {  // s^(q+1)
+  switch (c.qkind) {
+    case 1: return s * s;
+    case 2: return s * s * s;
+    case 4: {
+      const double s2 = s * s;
+      return s2 * s2 * s;
+    }
+    case 5: return s * sqrt(s);
+    default: return pow(s, c.q + 1.0);
+  }
+}
+
+__device__ __forceinline__ double pow_q(double s, const Consts& c) {  // s^q
+  switch (c.qkind) {
+    case 1: return s;
+    case 2: return s * s;
+    case 4: {
+      const double s2 = s * s;
+      return s2 * s2;
+    }
+    case 5: return sqrt(s);
+    default: return pow(s, c.q);
+  }
+}
+
+__device__ __forceinline__ double prox_lower(double a, double sigma, const Consts& c) {
+  const double s0 = pow(c.q / sigma, 1.0 / (c.q + 2.0));
+  if (a >= 0.0) return fmax(a, s0);
+  return pow(c.q / (sigma * (s0 - a)), 1.0 / (c.q + 1.0));
+}
+
+__device__ double prox_newton(double a, double sigma, double s, double tol, const Consts& c,
+                              int& steps) {
+  steps = 0;
+  if (!(s > 0.0) || !isfinite(s)) s = prox_lower(a, sigma, c);
+  double sq1 = pow_qp1(s, c);
+  double g = -c.q / sq1 + sigma * (s - a);
+  if (fabs(g) <= tol) return s;
+  const double c1 = c.c1 / sigma, c2 = c.c2 / sigma;
+  for (int it = 0; it < 50; ++it) {
+    double sn = s * (c1 + a * sq1) / (c2 + sq1 * s);
+    if (!(sn > 0.0) || !isfinite(sn)) sn = prox_lower(a, sigma, c);
+    const bool tiny = fabs(sn - s) <= 4.0 * DBL_EPSILON * s;
+    s = sn;
+    ++steps;
+    sq1 = pow_qp1(s, c);
+    g = -c.q / sq1 + sigma * (s - a);
+    if (fabs(g) <= tol || tiny) break;
+  }
+  return s;
+}
+
+__device__ __forceinline__ double eps_k(const Consts& c, int k) {
+  const double k1 = (double)k + 1.0;
+  return c.eps_c / (k1 * sqrt(k1));
+}
+
+// Sum one double over a block of NT threads; every thread gets the result.
+template <int NT>
+__device__ __forceinline__ double bsum(double v) {
+  return block_sum<NT>(v);
+}
+
+// Dot products of one row of an n x n FP64 matrix with x by one wave, with
+// CH loads per lane in flight before the reduction.
+constexpr int CH = 16;
+
+__device__ __forceinline__ double wave_row_dot(const double* __restrict__ a,
+                                               const double* __restrict__ x, int n, int lane) {
+  double acc = 0.0;
+  for (int base = 0; base < n; base += 64 * CH) {
+    double av[CH], xv[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int j = base + q * 64 + lane;
+      av[q] = j < n ? a[j] : 0.0;
+      xv[q] = j < n ? x[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) acc = fma(av[q], xv[q], acc);
+  }
+  return wave_sum(acc);
+}
+
+__device__ __forceinline__ void wave_row_dot2(const double* __restrict__ a,
+                                              const double* __restrict__ b,
+                                              const double* __restrict__ x, int n, int lane,
+                                              double& ra, double& rb) {
+  double sa = 0.0, sb = 0.0;
+  for (int base = 0; base < n; base += 64 * CH) {
+    double av[CH], bv[CH], xv[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int j = base + q * 64 + lane;
+      av[q] = j < n ? a[j] : 0.0;
+      bv[q] = j < n ? b[j] : 0.0;
+      xv[q] = j < n ? x[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      sa = fma(av[q], xv[q], sa);
+      sb = fma(bv[q], xv[q], sb);
+    }
+  }
+  ra = wave_sum(sa);
+  rb = wave_sum(sb);
+}
+
+
+__device__ __forceinline__ void nspace_sums(const Consts& c, double rq, double rq1, double a1,
+                                            double xi, double pres, double yi, double* acc) {
+  const double comp = a1 - c.q / rq1;
+  acc[0] = pres * pres;
+  acc[1] = fmin(0.0, a1) * fmin(0.0, a1);
+  acc[2] = fmax(0.0, a1 - c.C) * fmax(0.0, a1 - c.C);
+  acc[3] = yi * a1;
+  acc[4] = xi * (c.C - a1);
+  acc[5] = comp * comp;
+  acc[6] = 1.0 / rq;
+  acc[7] = xi;
+  acc[8] = a1 > 0.0 ? pow(a1, c.qexp) : 0.0;
+}
+
+
+// The Step 1c decision and the Step 2 ball scaling gamma = min(1, R/||g||),
+// from the block partials of both row kernels summed in a fixed order
+// (identical in every caller).
+struct Step2Plan {
+  int redo;
+  double gamma;
+};
+
+// a[0..5] are the summed plan partials (see plan_part); k and u2 the
+// iteration index and ||u||^2.
+__device__ __forceinline__ Step2Plan step2_plan_finish(const Consts& c, const double* a, int k,
+                                                       double u2) {
+  Step2Plan pl;
+  const double res2 = a[0] + a[1] * a[1];
+  pl.redo = sqrt(fmax(res2, 0.0)) > 5.0 * eps_k(c, k) ? 1 : 0;
+  const double sGs = pl.redo ? a[4] : a[2];
+  const double pus = pl.redo ? a[5] : a[3];
+  const double g2 = fmax(u2 - 2.0 / c.mu * pus + sGs / (c.mu * c.mu), 0.0);
+  const double ng = sqrt(g2);
+  pl.gamma = (ng <= c.R) ? 1.0 : c.R / ng;
+  return pl;
+}
+
+
+// Residuals of Section 4.3 from the reduced sums r[], computed in registers.
+__device__ __forceinline__ void finish_etas(const Consts& c, const double* r, double* e) {
+  const double den = c.opC;
+  e[E_P1] = sqrt(r[R_PRES2]) / den;
+  e[E_P2] = c.sqmu * sqrt(r[R_WU2]) / den;
+  e[E_P3] = fmax(sqrt(r[R_W2]) - c.R, 0.0) / den;
+  e[E_D1] = sqrt(r[R_AMIN2]) / den;
+  e[E_D2] = sqrt(r[R_AMAX2]) / den;
+  e[E_D3] = sqrt(r[R_DRES2]) / den;
+  e[E_C1] = fabs(r[R_YA]) / den;
+  e[E_C2] = fabs(r[R_XCA]) / den;
+  e[E_C3] = r[R_COMP2] / den;
+  const double prim = r[R_SUMRQ] + c.C * r[R_SUMXI];
+  const double dual = c.kappa * r[R_SUMAQ] - c.R * sqrt(r[R_ZA2]);
+  e[E_PRIM] = prim;
+  e[E_DUAL] = dual;
+  e[E_GAP] = fabs(prim - dual) / (1.0 + fabs(prim) + fabs(dual));
+  e[E_P] = fmax(e[E_P1], fmax(e[E_P2], e[E_P3]));
+  e[E_D] = fmax(e[E_D1], fmax(e[E_D2], c.rho_residual ? e[E_D3] : 0.0));
+  e[E_C] = fmax(e[E_C1], fmax(e[E_C2], e[E_C3]));
+}
+
+
+// Stopping rule of Section 4.3 and sigma rule of Section 4.4 on the residuals
+// e[]; returns the new sigma and sets *stop.
+__device__ __forceinline__ double stop_and_sigma(const Consts& c, const double* e, double sigma,
+                                                 bool* stop) {
+  const double pd = fmax(e[E_P], e[E_D]);
+  const double cg_min = fmin(e[E_C], e[E_GAP]), cg_max = fmax(e[E_C], e[E_GAP]);
+  *stop = pd < c.tol && cg_min < sqrt(c.tol) && cg_max < 0.05;
+  if (*stop) return sigma;
+  const double ep = e[E_P], ed = e[E_D];
+  if (ep >= 1e-300 && ed >= 1e-300) {
+    const double chi = ep / ed;
+    const double mm = fmax(chi, 1.0 / chi);
+    const double zeta = mm > 500.0 ? 2.2 : (mm > 50.0 ? 1.65 : 1.1);
+    if (chi > 5.0) return sigma * zeta;
+    if (1.0 / chi > 5.0) return sigma / zeta;
+  }
+  return sigma;
+}
+
+}  // namespace dwd

@@ -68,6 +68,8 @@ struct Scal {
   int32_t doubled;     // this iteration redid Step 1c
   int32_t status;      // 0 ok, else a dwd_status error code
   int32_t frozen_iter; // batch: iteration at which the problem stopped
+  int32_t redo;        // batch: Step 1c outcome of this iteration (plan kernel)
+  int32_t pad_;
   double red[R_COUNT];
   double eta[E_COUNT];
 };
@@ -81,6 +83,7 @@ struct Consts {
   double qexp;         // q/(q+1)
   int32_t rho_residual;
   int32_t qkind;       // 1,2,4: integer q; 5: q = 0.5; 0: general
+  double sigma0;       // initial sigma (used by the batched initialiser)
 };
 
 // Pointers of one problem's iteration state (all device).
@@ -99,6 +102,26 @@ struct IterPtrs {
   double *part_c;       // Step 1c block partials (NPC per block)
   double *partT;        // GEMV-T partials: [chunks][2][n]
   Scal* sc;
+};
+
+// Pointers of a batch of B problems over one shared X.  n-space arrays are
+// n x B and d-space arrays ld x B, column p = problem p (contiguous); block
+// partials are indexed [problem][block][...].  idx maps active slots to
+// problems.
+struct BatchPtrs {
+  const double* y;
+  const double* my;
+  const double* Minv;
+  const double* G;
+  double *R, *XI, *AL, *PU, *PR, *T, *XX, *F, *S, *V, *DR, *RN, *S1, *V1, *XI0, *XI1, *AL0,
+      *AL1, *HA;
+  double *U, *RHO, *W;
+  double* SB;          // n x B: column slot = y .* s / Z_scale of the chosen outcome
+  double *part_n1, *part_it, *part_c, *part_g, *part_ga;
+  Scal* sc;
+  const Consts* cs;
+  int n, nb, npb;      // nb: row blocks of the n x n kernels; npb: row blocks of the pass
+  int64_t ld;
 };
 
 // ---------------------------------------------------------------------------

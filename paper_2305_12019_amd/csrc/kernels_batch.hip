@@ -1,0 +1,763 @@
+// Kernels that step B problems over one shared X together (many (C, q)
+// values of one data set).  The eq-linsys matrix A depends only on X, y and
+// mu (Section 3.3.2), so G~, M^-1 and M^-1 y are shared; each problem keeps
+// its own (C, q, sigma, ...) and iterates exactly as a single solve would.
+// The pass over Z becomes one matrix product Z~ [s_1 .. s_B] on MFMA with
+// the Step 2-3 epilogue; the n x n products keep one wave per row, with an
+// XCD-aware block order so that the blocks of all problems that read the
+// same rows of M^-1 / G~ run on one XCD and share its L2.
+#include <float.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "dwd_device.h"
+#include "dwd_internal.h"
+
+namespace dwd {
+
+__host__ __device__ int ngemv_blocks(int n);
+
+// Block id -> (row block, active slot).  Blocks are dealt to the 8 XCDs
+// round-robin; a row block stays on one XCD while the slots cycle.
+__device__ __forceinline__ void rows_slot(int bid, int bact, int& rb, int& slot) {
+  const int xcd = bid & 7, m = bid >> 3;
+  rb = xcd + 8 * (m / bact);
+  slot = m % bact;
+}
+
+int batch_row_grid(int nb, int bact) { return 8 * ((nb + 7) / 8) * bact; }
+
+// ---------------------------------------------------------------------------
+// Initial point of every problem (as k_init) and t = x = 0 for the first
+// Step 1a (with u = rho = 0, Z~^T b = 0 and t = xi - r - alpha/sigma = 0).
+// ---------------------------------------------------------------------------
+__global__ void k_init_b(BatchPtrs P, int B) {
+  const int p = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t on = (size_t)p * P.n;
+  if (i < P.n) {
+    P.R[on + i] = 1.0;
+    P.XI[on + i] = 1.0;
+    P.AL[on + i] = 0.0;
+    P.PU[on + i] = 0.0;
+    P.PR[on + i] = 0.0;
+    P.T[on + i] = 0.0;
+    P.XX[on + i] = 0.0;
+  }
+  if (i < P.ld) {
+    const size_t od = (size_t)p * P.ld;
+    P.U[od + i] = 0.0;
+    P.RHO[od + i] = 0.0;
+    P.W[od + i] = 0.0;
+  }
+  if (i == 0) {
+    Scal* s = P.sc + p;
+    s->sigma = P.cs[p].sigma0;
+    s->beta = s->beta_bar = s->beta1 = 0.0;
+    s->gamma = 1.0;
+    s->ytdr = 0.0;
+    s->u2 = 0.0;
+    s->k = 0;
+    s->done = 0;
+    s->converged = 0;
+    s->n_double = 0;
+    s->newton_max = 0;
+    s->doubled = 0;
+    s->status = 0;
+    s->frozen_iter = 0;
+    s->redo = 0;
+    for (int j = 0; j < R_COUNT; ++j) s->red[j] = 0.0;
+    for (int j = 0; j < E_COUNT; ++j) s->eta[j] = 0.0;
+  }
+  (void)B;
+}
+
+hipError_t launch_init_b(const BatchPtrs& P, int B, hipStream_t st) {
+  const int64_t m = P.ld > P.n ? P.ld : P.n;
+  hipLaunchKernelGGL(k_init_b, dim3((unsigned)((m + 255) / 256), B), dim3(256), 0, st, P, B);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Step 1a + 1b per (row, problem); see k_step1ab.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_step1ab_b(BatchPtrs P, const int* __restrict__ idx,
+                                                   int bact) {
+  int rb, slot;
+  rows_slot(blockIdx.x, bact, rb, slot);
+  if (rb >= P.nb) return;
+  const int pr = idx[slot];
+  Scal* sc = P.sc + pr;
+  if (sc->done) return;
+  const Consts c = P.cs[pr];
+  __shared__ double wy[4];
+  __shared__ int ws[4];
+  const size_t on = (size_t)pr * P.n;
+  const double* x = P.XX + on;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int row = rb * 4 + wid;
+  const bool mine = row < c.n && lane == 0;
+  double myr = 0.0, tr = 0.0, xir = 0.0, alr = 0.0, r0 = 1.0, yr = 0.0;
+  if (mine) {
+    myr = P.my[row];
+    tr = P.T[on + row];
+    xir = P.XI[on + row];
+    alr = P.AL[on + row];
+    r0 = P.R[on + row];
+    yr = P.y[row];
+  }
+  const double sigma = sc->sigma;
+  const int kk = sc->k;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < c.n; j += 256) acc = fma(P.my[j], x[j], acc);
+  double f = 0.0;
+  if (row < c.n) f = wave_row_dot(P.Minv + (size_t)row * c.n, x, c.n, lane);
+  const double beta_bar = -bsum<256>(acc) / c.ymy;
+  double ydr = 0.0;
+  int steps = 0;
+  if (mine) {
+    const double tolN = eps_k(c, kk) / sqrt((double)c.n);
+    const double s = f + beta_bar * myr;
+    const double v = s - tr;
+    const double cc = v + xir - alr / sigma;
+    const double rn = prox_newton(cc, sigma, r0, tolN, c, steps);
+    const double dr = rn - r0;
+    P.F[on + row] = f;
+    P.S[on + row] = s;
+    P.V[on + row] = v;
+    P.RN[on + row] = rn;
+    P.DR[on + row] = dr;
+    ydr = yr * dr;
+  }
+  if (lane == 0) {
+    wy[wid] = ydr;
+    ws[wid] = steps;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const size_t o = (size_t)pr * P.nb + rb;
+    P.part_n1[o] = (wy[0] + wy[1]) + (wy[2] + wy[3]);
+    P.part_it[o] = (double)max(max(ws[0], ws[1]), max(ws[2], ws[3]));
+    if (rb == 0) sc->beta_bar = beta_bar;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 1c per (row, problem); see k_step1c_rows.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_step1c_b(BatchPtrs P, const int* __restrict__ idx,
+                                                  int bact) {
+  int rb, slot;
+  rows_slot(blockIdx.x, bact, rb, slot);
+  if (rb >= P.nb) return;
+  const int pr = idx[slot];
+  Scal* sc = P.sc + pr;
+  if (sc->done) return;
+  const Consts c = P.cs[pr];
+  __shared__ double wsum[4][NPC];
+  const size_t on = (size_t)pr * P.n;
+  const double* drv = P.DR + on;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int row = rb * 4 + wid;
+  const bool mine = row < c.n && lane == 0;
+  double dr = 0.0, rn = 1.0, a0 = 0.0, yi = 0.0, xr = 0.0, pu = 0.0, s0 = 0.0, v0 = 0.0;
+  double f0 = 0.0, my0 = 0.0, t0 = 0.0;
+  if (mine) {
+    dr = drv[row];
+    rn = P.RN[on + row];
+    a0 = P.AL[on + row];
+    yi = P.y[row];
+    xr = P.XX[on + row];
+    pu = P.PU[on + row];
+    s0 = P.S[on + row];
+    v0 = P.V[on + row];
+    f0 = P.F[on + row];
+    my0 = P.my[row];
+    t0 = P.T[on + row];
+  }
+  const double sigma = sc->sigma;
+  const double beta_bar = sc->beta_bar;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < c.n; j += 256) acc = fma(P.my[j], drv[j], acc);
+  double hg = 0.0, hm = 0.0;
+  if (row < c.n)
+    wave_row_dot2(P.G + (size_t)row * c.n, P.Minv + (size_t)row * c.n, drv, c.n, lane, hg, hm);
+  const double mdr = bsum<256>(acc);
+  const double beta1 = beta_bar + mdr / c.ymy;
+  double out[NPC];
+#pragma unroll
+  for (int j = 0; j < NPC; ++j) out[j] = 0.0;
+  if (mine) {
+    const double rq1 = pow_qp1(rn, c);
+    const double rq = pow_q(rn, c);
+    out[0] = dr * hg;
+    {
+      const double xi = fmax(0.0, rn - v0 + (a0 - c.C) / sigma);
+      const double pres = v0 + xi - rn;
+      const double a1 = a0 - c.tau * sigma * pres;
+      P.XI0[on + row] = xi;
+      P.AL0[on + row] = a1;
+      nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1);
+      out[1 + 9] = s0 * (c.mu * (xr + beta_bar * yi - s0));
+      out[1 + 10] = pu * s0;
+    }
+    {
+      const double s = f0 - hm + beta1 * my0;
+      const double v = s - (t0 - dr);
+      const double xi = fmax(0.0, rn - v + (a0 - c.C) / sigma);
+      const double pres = v + xi - rn;
+      const double a1 = a0 - c.tau * sigma * pres;
+      P.S1[on + row] = s;
+      P.V1[on + row] = v;
+      P.XI1[on + row] = xi;
+      P.AL1[on + row] = a1;
+      nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1 + NPO);
+      out[1 + NPO + 9] = s * (c.mu * (xr - dr + beta1 * yi - s));
+      out[1 + NPO + 10] = pu * s;
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NPC; ++j) wsum[wid][j] = out[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < NPC) {
+    const int j = threadIdx.x;
+    P.part_c[((size_t)pr * P.nb + rb) * NPC + j] =
+        (wsum[0][j] + wsum[1][j]) + (wsum[2][j] + wsum[3][j]);
+  }
+  if (rb == 0 && threadIdx.x == 0) sc->beta1 = beta1;
+}
+
+// ---------------------------------------------------------------------------
+// Per problem: the Step 1c decision and gamma = min(1, R/||g||) from the
+// block partials (fixed order), as step2_plan does for one problem.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_plan_b(BatchPtrs P, const int* __restrict__ idx) {
+  const int pr = idx[blockIdx.x];
+  Scal* sc = P.sc + pr;
+  if (sc->done) return;
+  const Consts c = P.cs[pr];
+  const int k = sc->k;
+  const double u2 = sc->u2;
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < P.nb; b += 256) {
+    const double* r = P.part_c + ((size_t)pr * P.nb + b) * NPC;
+    a[0] += r[0];
+    a[1] += P.part_n1[(size_t)pr * P.nb + b];
+    a[2] += r[1 + 9];
+    a[3] += r[1 + 10];
+    a[4] += r[1 + NPO + 9];
+    a[5] += r[1 + NPO + 10];
+  }
+  block_sum_k<256, 6>(a);
+  const Step2Plan pl = step2_plan_finish(c, a, k, u2);
+  if (threadIdx.x == 0) {
+    sc->redo = pl.redo;
+    sc->gamma = pl.gamma;
+  }
+  // the pass's right-hand operand for this slot, dense and pre-scaled
+  const double* src = (pl.redo ? P.S1 : P.S) + (size_t)pr * P.n;
+  double* dst = P.SB + (size_t)blockIdx.x * P.n;
+  for (int i = threadIdx.x; i < P.n; i += 256) dst[i] = P.y[i] * c.inv_zs * src[i];
+}
+
+// ---------------------------------------------------------------------------
+// The pass over Z for all active problems: W = (Bm - Z~ S) / mu with the
+// dense, pre-scaled operand SB (column slot = y .* s_j / Z_scale of the
+// chosen Step 1c outcome), on MFMA 16x16x4 (f32 or f64), fused with Steps
+// 2-3:  g = w - rho/(sigma sqrt(mu)), u = gamma g,
+// rho -= tau sigma sqrt(mu)(w - u), and per-problem block partials (NP2
+// layout of the single pass; the two Z~ alpha entries are 0 here: the batched
+// tail gets them in n-space).  Block tile: 256 rows x 64 slots, 8 waves, wave
+// w owns rows 32w..32w+31; the next K tile is loaded into registers while the
+// current one is multiplied.
+// ---------------------------------------------------------------------------
+constexpr int BT_M = 256, BT_N = 64, BT_K = 16, BT_T = 512;
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v_b __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaB;
+template <>
+struct MfmaB<float> {
+  typedef f4v acc_t;
+  __device__ static __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of register v of lane l in a 16x16 output block (column = l % 16)
+  __device__ static __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <>
+struct MfmaB<double> {
+  typedef d4v_b acc_t;
+  __device__ static __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int l, int v) { return 4 * v + (l >> 4); }
+};
+
+// Global loads of one K tile into registers: A is 256 rows x 16 columns of X
+// (2 four-element row segments per thread), B is 16 x 64 of SB (2 per thread).
+template <typename TD>
+struct TileRegs {
+  TD a[2][4];
+  double b[2];
+};
+
+template <typename TD>
+__device__ __forceinline__ void tile_load(const TD* __restrict__ X, const double* __restrict__ SB,
+                                          int64_t ld, int n, int64_t m0, int k0, int bact_tile,
+                                          TileRegs<TD>& R) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + h * BT_T;        // 0..1023
+    const int kk = e >> 6, r4 = (e & 63) * 4;
+    const int k = k0 + kk;
+    if (k < n) {
+      const TD* src = X + (int64_t)k * ld + m0 + r4;
+      if constexpr (sizeof(TD) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(src);
+        R.a[h][0] = v.x;
+        R.a[h][1] = v.y;
+        R.a[h][2] = v.z;
+        R.a[h][3] = v.w;
+      } else {
+        const double2 v0 = *reinterpret_cast<const double2*>(src);
+        const double2 v1 = *reinterpret_cast<const double2*>(src + 2);
+        R.a[h][0] = v0.x;
+        R.a[h][1] = v0.y;
+        R.a[h][2] = v1.x;
+        R.a[h][3] = v1.y;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) R.a[h][q] = (TD)0;
+    }
+    // B: slot j = e / 16, kk = e % 16 (16 consecutive k of one slot)
+    const int j = e >> 4, kb = e & 15;
+    const int kq = k0 + kb;
+    R.b[h] = (j < bact_tile && kq < n) ? SB[(size_t)j * n + kq] : 0.0;
+  }
+}
+
+template <typename TD, typename T>
+__device__ __forceinline__ void tile_store(const TileRegs<TD>& R, T (*As)[BT_M + 4],
+                                           T (*Bs)[BT_N + 4]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + h * BT_T;
+    const int kk = e >> 6, r4 = (e & 63) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) As[kk][r4 + q] = (T)R.a[h][q];
+    const int j = e >> 4, kb = e & 15;
+    Bs[kb][j] = (T)R.b[h];
+  }
+}
+
+template <typename TD, typename T>
+__global__ void __launch_bounds__(BT_T) k_pass_b(const TD* __restrict__ X, BatchPtrs P,
+                                                 const int* __restrict__ idx, int bact) {
+  typedef typename MfmaB<T>::acc_t acc_t;
+  __shared__ T As[BT_K][BT_M + 4];
+  __shared__ T Bs[BT_K][BT_N + 4];
+  __shared__ double red[8][BT_N][NP2];
+  __shared__ int s_p[BT_N];
+  __shared__ int s_live[BT_N];
+  __shared__ double s_sig[BT_N], s_gam[BT_N], s_tau[BT_N];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * BT_M;
+  const int slot0 = blockIdx.y * BT_N;
+  const int bact_tile = min(BT_N, bact - slot0);
+  const int n = P.n;
+  const double* SB = P.SB + (size_t)slot0 * n;
+  if (tid < BT_N) {
+    const int slot = slot0 + tid;
+    int p = -1, live = 0;
+    if (tid < bact_tile) {
+      p = idx[slot];
+      live = P.sc[p].done ? 0 : 1;
+    }
+    s_p[tid] = p;
+    s_live[tid] = live;
+    if (live) {
+      const Scal* sc = P.sc + p;
+      s_sig[tid] = sc->sigma;
+      s_gam[tid] = sc->gamma;
+      s_tau[tid] = P.cs[p].tau;
+    }
+  }
+  double acc64[2][4][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[a][b][v] = 0.0;
+  TileRegs<TD> R;
+  tile_load<TD>(X, SB, P.ld, n, m0, 0, bact_tile, R);
+  for (int k0 = 0; k0 < n; k0 += BT_K) {
+    tile_store<TD, T>(R, As, Bs);
+    __syncthreads();
+    if (k0 + BT_K < n) tile_load<TD>(X, SB, P.ld, n, m0, k0 + BT_K, bact_tile, R);
+    acc_t acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[a][b][v] = (T)0;
+#pragma unroll
+    for (int ks = 0; ks < BT_K; ks += 4) {
+      const int li = lane & 15, lk = lane >> 4;
+      T av[2], bv[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[ks + lk][wid * 32 + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[ks + lk][b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = MfmaB<T>::op(av[a], bv[b], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[a][b][v] += (double)acc[a][b][v];
+    __syncthreads();
+  }
+  const double mu = P.cs[s_p[0] >= 0 ? s_p[0] : 0].mu;
+  const double sqmu = sqrt(mu);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = b * 16 + (lane & 15);
+    const int p = s_p[j];
+    const bool live = s_live[j] != 0;
+    double pw[NP2] = {0, 0, 0, 0, 0, 0};
+    if (live) {
+      const double sigma = s_sig[j], gamma = s_gam[j];
+      const double br = sqmu / sigma, gr = 1.0 / (sigma * sqmu);
+      const double rs = s_tau[j] * sigma * sqmu;
+      const size_t od = (size_t)p * P.ld;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t k = m0 + wid * 32 + a * 16 + MfmaB<T>::row(lane, v);
+          const double zs = acc64[a][b][v];
+          const double rho = P.RHO[od + k];
+          const double bb = mu * P.U[od + k] + br * rho;
+          const double w = (bb - zs) / mu;
+          const double u = gamma * (w - gr * rho);
+          const double rn = rho - rs * (w - u);
+          P.W[od + k] = w;
+          P.U[od + k] = u;
+          P.RHO[od + k] = rn;
+          pw[0] += (w - u) * (w - u);
+          pw[1] += w * w;
+          pw[4] += rn * rn;
+          pw[5] += u * u;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NP2; ++q) {
+      pw[q] += __shfl_xor(pw[q], 16, 64);
+      pw[q] += __shfl_xor(pw[q], 32, 64);
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int q = 0; q < NP2; ++q) red[wid][j][q] = pw[q];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < BT_N * NP2; e += BT_T) {
+    const int j = e / NP2, q = e % NP2;
+    if (!s_live[j]) continue;
+    double v = 0.0;
+#pragma unroll
+    for (int w8 = 0; w8 < 8; ++w8) v += red[w8][j][q];
+    P.part_g[((size_t)s_p[j] * P.npb + blockIdx.x) * NP2 + q] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// G~ alpha^{k+1} per (row, problem), with block partials of alpha^T G~ alpha,
+// for ||Z~ alpha||^2 (dual objective) and ||Z~ alpha + D rho||^2 (eta_D3).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_galpha_b(BatchPtrs P, const int* __restrict__ idx,
+                                                  int bact) {
+  int rb, slot;
+  rows_slot(blockIdx.x, bact, rb, slot);
+  if (rb >= P.nb) return;
+  const int pr = idx[slot];
+  Scal* sc = P.sc + pr;
+  if (sc->done) return;
+  __shared__ double wsum[4];
+  const size_t on = (size_t)pr * P.n;
+  const double* al = (sc->redo ? P.AL1 : P.AL0) + on;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int row = rb * 4 + wid;
+  double h = 0.0;
+  if (row < P.n) h = wave_row_dot(P.G + (size_t)row * P.n, al, P.n, lane);
+  if (lane == 0) {
+    double contrib = 0.0;
+    if (row < P.n) {
+      P.HA[on + row] = h;
+      contrib = al[row] * h;
+    }
+    wsum[wid] = contrib;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    P.part_ga[(size_t)pr * P.nb + rb] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Per problem: commit of the Step 1c outcome, recurrences of Z~^T u and
+// Z~^T rho, residuals, stopping and sigma rules, next t and x (k_tail),
+// with ||Z~ alpha + D rho||^2 = a^T G~ a + 2 sqrt(mu) a^T Z~^T rho + mu ||rho||^2.
+// ---------------------------------------------------------------------------
+constexpr int NTB = 512;
+
+__global__ void __launch_bounds__(NTB) k_tail_b(BatchPtrs P, const int* __restrict__ idx) {
+  const int pr = idx[blockIdx.x];
+  Scal* sc = P.sc + pr;
+  if (sc->done) return;
+  const Consts c = P.cs[pr];
+  __shared__ double s_sigma;
+  __shared__ double smax[NTB / 64];
+  const size_t on = (size_t)pr * P.n;
+  const int k0 = sc->k;
+  const double sigma = sc->sigma;
+  const double gamma = sc->gamma;
+  const int o = sc->redo;
+  const double beta = o ? sc->beta1 : sc->beta_bar;
+  const int nd = sc->n_double;
+  const int nm = sc->newton_max;
+  constexpr int K = 9 + NP2 + 1;
+  double acc[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) acc[j] = 0.0;
+  double nmax = 0.0;
+  for (int b = threadIdx.x; b < P.nb; b += NTB) {
+    const double* r = P.part_c + ((size_t)pr * P.nb + b) * NPC + 1 + o * NPO;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc[j] += r[j];
+    acc[9 + NP2] += P.part_ga[(size_t)pr * P.nb + b];
+    nmax = fmax(nmax, P.part_it[(size_t)pr * P.nb + b]);
+  }
+  for (int b = threadIdx.x; b < P.npb; b += NTB)
+#pragma unroll
+    for (int j = 0; j < NP2; ++j) acc[9 + j] += P.part_g[((size_t)pr * P.npb + b) * NP2 + j];
+  // commit and recurrences (old sigma), with a^T Z~^T rho^{k+1}
+  const double gr = 1.0 / (sigma * c.sqmu);
+  const double rs = c.tau * sigma * c.sqmu;
+  const double* xs = (o ? P.XI1 : P.XI0) + on;
+  const double* as = (o ? P.AL1 : P.AL0) + on;
+  const double* ss = (o ? P.S1 : P.S) + on;
+  const double* vs = (o ? P.V1 : P.V) + on;
+  double apr = 0.0;
+  for (int i = threadIdx.x; i < c.n; i += NTB) {
+    const double v = vs[i];
+    const double al = as[i];
+    P.R[on + i] = P.RN[on + i];
+    P.XI[on + i] = xs[i];
+    P.AL[on + i] = al;
+    if (o) {
+      P.S[on + i] = ss[i];
+      P.V[on + i] = v;
+    }
+    const double ztw = v - beta * P.y[i];
+    const double prv = P.PR[on + i];
+    const double pu = gamma * (ztw - gr * prv);
+    const double prn = prv - rs * (ztw - pu);
+    P.PU[on + i] = pu;
+    P.PR[on + i] = prn;
+    apr += al * prn;
+  }
+  double all[K + 1];
+#pragma unroll
+  for (int j = 0; j < K; ++j) all[j] = acc[j];
+  all[K] = apr;
+  block_sum_k<NTB, K + 1>(all);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) nmax = fmax(nmax, __shfl_xor(nmax, off, 64));
+  if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = nmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = smax[0];
+    for (int w = 1; w < NTB / 64; ++w) m = fmax(m, smax[w]);
+    const double aGa = all[9 + NP2];
+    const double rho2 = all[9 + 4];
+    double red[R_COUNT];
+    for (int j = 0; j < 9; ++j) red[R_PRES2 + j] = all[j];
+    red[R_WU2] = all[9 + 0];
+    red[R_W2] = all[9 + 1];
+    red[R_DRES2] = fmax(aGa + 2.0 * c.sqmu * all[K] + c.mu * rho2, 0.0);
+    red[R_ZA2] = aGa;
+    red[R_G2] = 0.0;
+    red[R_RHO2] = rho2;
+    double e[E_COUNT];
+    e[E_PCHK] = e[E_DCHK] = 0.0;
+    finish_etas(c, red, e);
+    for (int j = 0; j < R_COUNT; ++j) sc->red[j] = red[j];
+    for (int j = 0; j < E_COUNT; ++j) sc->eta[j] = e[j];
+    sc->u2 = all[9 + 5];
+    sc->beta = beta;
+    sc->doubled = o;
+    sc->n_double = nd + o;
+    if ((int)m > nm) sc->newton_max = (int)m;
+    const int k1 = k0 + 1;
+    sc->k = k1;
+    bool stop = false;
+    const double sig = stop_and_sigma(c, e, sigma, &stop);
+    if (stop) {
+      sc->converged = 1;
+      sc->done = 1;
+    } else if (k1 >= c.max_iter) {
+      sc->done = 1;
+    }
+    if (sc->done) sc->frozen_iter = k1;
+    sc->sigma = sig;
+    s_sigma = sig;
+  }
+  __syncthreads();
+  const double sig1 = s_sigma;
+  for (int i = threadIdx.x; i < c.n; i += NTB) {
+    const double t = P.XI[on + i] - P.R[on + i] - P.AL[on + i] / sig1;
+    P.T[on + i] = t;
+    P.XX[on + i] = t + (c.mu * P.PU[on + i] + c.sqmu * P.PR[on + i] / sig1) / c.mu;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+bool batch_ptrs_ok(const BatchPtrs& P) {
+  const void* req[] = {P.y, P.my, P.Minv, P.G, P.R, P.XI, P.AL, P.PU, P.PR, P.T, P.XX, P.F,
+                       P.S, P.V, P.DR, P.RN, P.S1, P.V1, P.XI0, P.XI1, P.AL0, P.AL1, P.HA,
+                       P.U, P.RHO, P.W, P.SB, P.part_n1, P.part_it, P.part_c, P.part_g,
+                       P.part_ga, P.sc, P.cs};
+  for (const void* q : req)
+    if (!q) return false;
+  return P.ld % kLdAlign == 0;
+}
+
+hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, const BatchPtrs& P,
+                                  const int* idx, int bact, hipStream_t st) {
+  if (!X || !idx || bact < 1 || !batch_ptrs_ok(P)) return hipErrorInvalidValue;
+  if (storage != DWD_FP32 && storage != DWD_FP64) return hipErrorInvalidValue;
+  const dim3 grow(batch_row_grid(P.nb, bact));
+  hipLaunchKernelGGL(k_step1ab_b, grow, dim3(256), 0, st, P, idx, bact);
+  hipLaunchKernelGGL(k_step1c_b, grow, dim3(256), 0, st, P, idx, bact);
+  hipLaunchKernelGGL(k_plan_b, dim3(bact), dim3(256), 0, st, P, idx);
+  const dim3 gp((unsigned)(P.ld / BT_M), (bact + BT_N - 1) / BT_N);
+  if (storage == DWD_FP32 && !fp64_mfma)
+    hipLaunchKernelGGL((k_pass_b<float, float>), gp, dim3(BT_T), 0, st, (const float*)X, P, idx,
+                       bact);
+  else if (storage == DWD_FP32)
+    hipLaunchKernelGGL((k_pass_b<float, double>), gp, dim3(BT_T), 0, st, (const float*)X, P, idx,
+                       bact);
+  else
+    hipLaunchKernelGGL((k_pass_b<double, double>), gp, dim3(BT_T), 0, st, (const double*)X, P,
+                       idx, bact);
+  hipLaunchKernelGGL(k_galpha_b, grow, dim3(256), 0, st, P, idx, bact);
+  hipLaunchKernelGGL(k_tail_b, dim3(bact), dim3(NTB), 0, st, P, idx);
+  return hipGetLastError();
+}
+
+int batch_pass_row_blocks(int64_t ld) { return (int)(ld / BT_M); }
+
+}  // namespace dwd
+
+namespace dwd {
+
+// Final FP64 check of problem p (as k_check): partT holds the pass over the
+// data of record with v1 = w~_p, v2 = rho_p; HA holds G~ alpha_p.
+__global__ void __launch_bounds__(512) k_check_b(BatchPtrs P, int p, const double* partT,
+                                                 int nchunks) {
+  Scal* sc = P.sc + p;
+  const Consts c = P.cs[p];
+  const size_t on = (size_t)p * P.n;
+  double acc[3] = {0, 0, 0};
+  const double beta = sc->beta;
+  for (int i = threadIdx.x; i < c.n; i += 512) {
+    double sw = 0.0, sr = 0.0;
+    for (int ch = 0; ch < nchunks; ++ch) {
+      sw += partT[((int64_t)ch * 2) * c.n + i];
+      sr += partT[((int64_t)ch * 2 + 1) * c.n + i];
+    }
+    const double yi = P.y[i];
+    const double pres = yi * sw * c.inv_zs + beta * yi + P.XI[on + i] - P.R[on + i];
+    const double a = P.AL[on + i];
+    acc[0] += pres * pres;
+    acc[1] += a * P.HA[on + i];
+    acc[2] += a * yi * sr * c.inv_zs;
+  }
+  block_sum_k<512, 3>(acc);
+  if (threadIdx.x == 0) {
+    const double den = c.opC;
+    const double* e = sc->eta;
+    const double p1 = sqrt(acc[0]) / den;
+    const double dres2 = acc[1] + 2.0 * c.sqmu * acc[2] + c.mu * sc->red[R_RHO2];
+    const double d3 = sqrt(fmax(dres2, 0.0)) / den;
+    sc->eta[E_PCHK] = fmax(p1, fmax(e[E_P2], e[E_P3]));
+    sc->eta[E_DCHK] = fmax(e[E_D1], fmax(e[E_D2], c.rho_residual ? d3 : 0.0));
+  }
+}
+
+__global__ void k_resume_b(BatchPtrs P, const int* __restrict__ idx, int cnt) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < cnt) {
+    Scal* sc = P.sc + idx[j];
+    sc->done = 0;
+    sc->converged = 0;
+  }
+}
+
+// Re-anchor problem p: Z~^T u and Z~^T rho from a pass (partT, with y and
+// 1/Z_scale folded in), then t and x of the next Step 1a.
+__global__ void __launch_bounds__(256) k_anchor_b(BatchPtrs P, int p, const double* partT,
+                                                  int nchunks) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  const Consts c = P.cs[p];
+  const size_t on = (size_t)p * P.n;
+  double su = 0.0, sr = 0.0;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    su += partT[((int64_t)ch * 2) * P.n + i];
+    sr += partT[((int64_t)ch * 2 + 1) * P.n + i];
+  }
+  const double yz = P.y[i] * c.inv_zs;
+  const double pu = yz * su, pr = yz * sr;
+  const double sigma = P.sc[p].sigma;
+  P.PU[on + i] = pu;
+  P.PR[on + i] = pr;
+  const double t = P.XI[on + i] - P.R[on + i] - P.AL[on + i] / sigma;
+  P.T[on + i] = t;
+  P.XX[on + i] = t + (c.mu * pu + c.sqmu * pr / sigma) / c.mu;
+}
+
+hipError_t launch_anchor_b(const BatchPtrs& P, int p, const double* partT, int nchunks,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_anchor_b, dim3((P.n + 255) / 256), dim3(256), 0, st, P, p, partT, nchunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_resume_b(const BatchPtrs& P, const int* idx, int cnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_resume_b, dim3((cnt + 63) / 64), dim3(64), 0, st, P, idx, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_b(const BatchPtrs& P, int p, const double* partT, int nchunks,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_check_b, dim3(1), dim3(512), 0, st, P, p, partT, nchunks);
+  return hipGetLastError();
+}
+
+}  // namespace dwd

@@ -46,6 +46,7 @@ def test_struct_sizes_match_header_layout(D):
     # field offsets follow the C declaration order with natural alignment
     assert C.sizeof(D.Matrix) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4
     assert C.sizeof(D.Params) == 3 * 8 + 4 + 4 + 4 * 8 + 4 * 4 + 8 + 4 + 4
+    assert D.params().batch_fp32 == 0
     assert C.sizeof(D.Info) == 11 * 8 + 6 * 4 + 3 * 8 + 2 * 4 + 8 + 2 * 4
 
 

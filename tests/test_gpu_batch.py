@@ -1,0 +1,99 @@
+"""Batched solves over one shared X (dwd_solve_batch) against single solves
+and against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dwd_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dwd():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_12019_amd import dwd as D
+    return D
+
+
+def _obj(X, y, w, beta, C, q):
+    w = np.asarray(w, np.float64)
+    return O.reduced_objective(X, y, w / max(1.0, np.linalg.norm(w)), beta, C, q)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_batch_matches_oracle_and_single_solves(dwd, storage):
+    X, y = synth.random_two_class(2500, 77, seed=12, mean=0.6,
+                                  dtype="f32" if storage == "f32" else "f64")
+    grid = [(0.3, 1.0), (3.0, 2.0), (1.0, 0.5), (10.0, 4.0), (0.05, 1.0)]
+    P = dwd.Problem(X, y, storage=storage)
+    res = P.solve_batch([dict(C=C, q=q, tol=1e-8, max_iter=20000) for C, q in grid])
+    for j, (C, q) in enumerate(grid):
+        info = res["info"][j]
+        assert info["converged"] == 1, (j, info)
+        assert info["kkt_check"] <= 2e-8, (j, info)
+        ref = O.solve(X, y, C, q, tol=1e-9, max_iter=20000)
+        w = res["W"][j]
+        f, fr = _obj(X, y, w, info["beta"], C, q), _obj(X, y, ref["w"], ref["beta"], C, q)
+        assert abs(f - fr) <= 1e-6 * abs(fr), (j, f, fr)
+        assert np.linalg.norm(w - ref["w"]) <= 1e-4 * np.linalg.norm(ref["w"]), j
+    # The same problems alone, at a working tolerance with FP64 products on
+    # both sides (tol < 1e-6 selects the FP64 MFMA pass): same stopping points.
+    res7 = P.solve_batch([dict(C=C, q=q, tol=5e-7) for C, q in grid])
+    for j, (C, q) in enumerate(grid):
+        alone = P.solve(C, q, tol=5e-7, want_state=False)
+        a, b = alone["info"], res7["info"][j]
+        assert b["converged"] == 1
+        assert abs(a["iters"] - b["iters"]) <= max(2, 0.05 * a["iters"]), (j, a["iters"], b["iters"])
+        assert np.linalg.norm(alone["w"] - res7["W"][j]) <= 1e-4 * np.linalg.norm(alone["w"])
+    # FP32 MFMA pass (opt-in, tol >= 1e-6): judged by its FP64 check and the objective.
+    res5 = P.solve_batch([dict(C=C, q=q, tol=1e-5, batch_fp32=1) for C, q in grid])
+    for j, (C, q) in enumerate(grid):
+        info = res5["info"][j]
+        assert info["converged"] == 1 and info["kkt_check"] <= 1.5e-5, (j, info)
+        # as close to the optimum as the oracle stopped at the same tolerance
+        ref = O.solve(X, y, C, q, tol=1e-9, max_iter=20000)
+        same = O.solve(X, y, C, q, tol=1e-5, max_iter=2000)
+        fr = _obj(X, y, ref["w"], ref["beta"], C, q)
+        err_gpu = abs(_obj(X, y, res5["W"][j], info["beta"], C, q) - fr) / abs(fr)
+        err_orc = abs(_obj(X, y, same["w"], same["beta"], C, q) - fr) / abs(fr)
+        assert err_gpu <= max(5 * err_orc, 1e-6), (j, err_gpu, err_orc)
+    P.close()
+
+
+def test_batch_freezes_finished_problems(dwd):
+    X, y = synth.random_two_class(3000, 64, seed=13, mean=0.6, dtype="f32")
+    P = dwd.Problem(X, y, storage="f32")
+    plist = [dict(C=1.0, q=1.0, tol=5e-7), dict(C=1.0, q=1.0, tol=5e-7, max_iter=3),
+             dict(C=5.0, q=2.0, tol=5e-7)]
+    res = P.solve_batch(plist)
+    assert res["status"] == 1  # one problem hit its cap
+    i0, i1, i2 = res["info"]
+    assert i1["iters"] == 3 and i1["converged"] == 0
+    assert i0["converged"] == 1 and i2["converged"] == 1
+    single = P.solve(1.0, 1.0, tol=5e-7, want_state=False)
+    assert abs(single["info"]["iters"] - i0["iters"]) <= 2
+    P.close()
+
+
+def test_batch_sweep_full_size(dwd):
+    X, y = synth.two_class(synth.SWEEP_DATA)
+    P = dwd.Problem(X, y, storage="f32")
+    grid = synth.sweep_grid()
+    res = P.solve_batch([dict(C=C, q=q, tol=1e-5) for C, q in grid])
+    infos = res["info"]
+    r32 = P.solve_batch([dict(C=C, q=q, tol=1e-5, batch_fp32=1) for C, q in grid])
+    print("sweep fp32 mfma: converged %d/64 solve_ms %.1f, resumed %d" % (
+        sum(i["converged"] for i in r32["info"]), r32["info"][0]["solve_ms"],
+        sum(i["resumed"] for i in r32["info"])))
+    conv = [i for i in infos if i["converged"]]
+    print("sweep: converged %d/64, iters min/median/max %d/%d/%d, solve_ms %.1f" % (
+        len(conv), min(i["iters"] for i in infos), int(np.median([i["iters"] for i in infos])),
+        max(i["iters"] for i in infos), infos[0]["solve_ms"]))
+    assert len(conv) >= 48
+    for i in conv:
+        assert i["kkt_check"] <= 2e-5, i
+    assert np.all(np.isfinite(res["W"]))
+    P.close()
