@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdwd.so")
-SOURCES = ["dwd_api.hip", "kernels_setup.hip", "kernels_iter.hip", "kernels_batch.hip", "dwd_batch.hip",
+SOURCES = ["dwd_api.hip", "kernels_setup.hip", "kernels_iter.hip", "kernels_batch.hip", "kernels_csr.hip",
+           "dwd_batch.hip",
            "dwd_serve.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -47,7 +47,7 @@ static size_t storage_bytes(int storage, int64_t ld, int n) {
 int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz) {
   const int64_t ld = padded_ld(d);
   int64_t b = (int64_t)storage_bytes(storage, ld, n);
-  if (layout == DWD_CSR) b = (int64_t)storage_bytes(DWD_FP32, ld, n) + nnz * 24;
+  if (layout == DWD_CSR) b = 2 * nnz * (4 + (storage == DWD_FP64 ? 8 : 4)) + (n + d + 2) * 8;
   const int64_t nn = (int64_t)n * n * 8;
   b += 2 * nn;                                          // G~, M^-1
   b += (int64_t)n * 8 * 24 + ld * 8 * 4;                // vectors
@@ -129,16 +129,6 @@ hipError_t Problem::alloc(void** ptr, size_t bytes) {
 
 static hipError_t alloc_tmp(void** ptr, size_t bytes) { return hipMalloc(ptr, bytes ? bytes : 8); }
 
-// CSR of X^T (host arrays) -> dense d x n column-major host array of dtype.
-template <typename T>
-static void csr_to_dense_host(const dwd_matrix* X, std::vector<T>& out) {
-  out.assign((size_t)X->d * X->n, T(0));
-  const T* vals = (const T*)X->values;
-  for (int64_t i = 0; i < X->n; ++i)
-    for (int64_t e = X->indptr[i]; e < X->indptr[i + 1]; ++e)
-      out[(size_t)i * X->d + X->indices[e]] = vals[e];
-}
-
 dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params* p,
                          hipStream_t st, Problem** out) {
   dwd_status s;
@@ -162,63 +152,83 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   const void* Xdev = X->values;
   void* Xtmp = nullptr;
   const size_t in_el = X->dtype == DWD_FP64 ? 8 : 4;
+  std::vector<int64_t> ipT_h, ipX_h;
+  std::vector<int32_t> ixT_h, ixX_h;
+  std::vector<double> valT_h, valX_h;
   if (X->layout == DWD_CSR) {
-    // Validate the CSR structure on the host.
-    std::vector<int64_t> ip(n + 1);
-    std::vector<int32_t> ix;
-    std::vector<char> vals;
+    // Validate on the host; sort each sample row by feature index; build
+    // the by-feature transpose (rows stay sorted by sample index).
+    ipT_h.resize(n + 1);
     if (X->on_device) {
-      HIP_TRY(hipMemcpy(ip.data(), X->indptr, (n + 1) * 8, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(ipT_h.data(), X->indptr, (n + 1) * 8, hipMemcpyDeviceToHost));
     } else {
-      memcpy(ip.data(), X->indptr, (n + 1) * 8);
+      memcpy(ipT_h.data(), X->indptr, (n + 1) * 8);
     }
-    if (ip[0] != 0 || ip[n] != X->nnz) {
+    if (ipT_h[0] != 0 || ipT_h[n] != X->nnz) {
       delete P;
       return fail(DWD_E_INVALID, "CSR indptr must start at 0 and end at nnz");
     }
     for (int i = 0; i < n; ++i)
-      if (ip[i + 1] < ip[i]) {
+      if (ipT_h[i + 1] < ipT_h[i]) {
         delete P;
         return fail(DWD_E_INVALID, "CSR indptr must be non-decreasing");
       }
-    ix.resize(X->nnz);
-    vals.resize(X->nnz * in_el);
+    const int64_t nnz = X->nnz;
+    ixT_h.resize(nnz);
+    valT_h.resize(nnz);
+    std::vector<char> raw(nnz * in_el);
     if (X->on_device) {
-      HIP_TRY(hipMemcpy(ix.data(), X->indices, X->nnz * 4, hipMemcpyDeviceToHost));
-      HIP_TRY(hipMemcpy(vals.data(), X->values, X->nnz * in_el, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(ixT_h.data(), X->indices, nnz * 4, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(raw.data(), X->values, nnz * in_el, hipMemcpyDeviceToHost));
     } else {
-      memcpy(ix.data(), X->indices, X->nnz * 4);
-      memcpy(vals.data(), X->values, X->nnz * in_el);
+      memcpy(ixT_h.data(), X->indices, nnz * 4);
+      memcpy(raw.data(), X->values, nnz * in_el);
     }
-    for (int64_t e = 0; e < X->nnz; ++e)
-      if (ix[e] < 0 || ix[e] >= d) {
-        delete P;
-        return fail(DWD_E_INVALID, "CSR column index out of range");
+    for (int64_t e = 0; e < nnz; ++e)
+      valT_h[e] = X->dtype == DWD_FP64 ? ((const double*)raw.data())[e]
+                                        : (double)((const float*)raw.data())[e];
+    std::vector<int64_t> ord;
+    for (int i = 0; i < n; ++i) {
+      const int64_t a = ipT_h[i], b = ipT_h[i + 1];
+      ord.resize(b - a);
+      for (int64_t e = a; e < b; ++e) ord[e - a] = e;
+      std::sort(ord.begin(), ord.end(), [&](int64_t u, int64_t v) { return ixT_h[u] < ixT_h[v]; });
+      std::vector<int32_t> ci(b - a);
+      std::vector<double> cv(b - a);
+      for (int64_t e = a; e < b; ++e) {
+        ci[e - a] = ixT_h[ord[e - a]];
+        cv[e - a] = valT_h[ord[e - a]];
       }
-    dwd_matrix H = *X;
-    H.indptr = ip.data();
-    H.indices = ix.data();
-    H.values = vals.data();
-    size_t bytes = (size_t)d * n * in_el;
-    hipError_t e = alloc_tmp(&Xtmp, bytes);
-    if (e != hipSuccess) { delete P; return hip_fail(e, "hipMalloc(X staging)"); }
-    if (X->dtype == DWD_FP64) {
-      std::vector<double> dense;
-      csr_to_dense_host<double>(&H, dense);
-      e = hipMemcpyAsync(Xtmp, dense.data(), bytes, hipMemcpyHostToDevice, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-    } else {
-      std::vector<float> dense;
-      csr_to_dense_host<float>(&H, dense);
-      e = hipMemcpyAsync(Xtmp, dense.data(), bytes, hipMemcpyHostToDevice, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      for (int64_t e = a; e < b; ++e) {
+        ixT_h[e] = ci[e - a];
+        valT_h[e] = cv[e - a];
+        if (ixT_h[e] < 0 || ixT_h[e] >= d) {
+          delete P;
+          return fail(DWD_E_INVALID, "CSR column index out of range");
+        }
+        if (e > a && ixT_h[e] == ixT_h[e - 1]) {
+          delete P;
+          return fail(DWD_E_INVALID, "duplicate column index in a CSR row");
+        }
+        if (!std::isfinite(valT_h[e])) {
+          delete P;
+          return fail(DWD_E_INVALID, "X has non-finite entries");
+        }
+      }
     }
-    if (e != hipSuccess) { (void)hipFree(Xtmp); delete P; return hip_fail(e, "CSR staging"); }
-    Xdev = Xtmp;
-    // keep the sparse structure for the sparse passes
-    P->csr_indptr_h = ip;
-    P->csr_indices_h = ix;
-    P->nnz = X->nnz;
+    ipX_h.assign(d + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) ipX_h[ixT_h[e] + 1] += 1;
+    for (int64_t k = 0; k < d; ++k) ipX_h[k + 1] += ipX_h[k];
+    ixX_h.resize(nnz);
+    valX_h.resize(nnz);
+    std::vector<int64_t> fill(ipX_h.begin(), ipX_h.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int64_t e = ipT_h[i]; e < ipT_h[i + 1]; ++e) {
+        const int64_t o = fill[ixT_h[e]]++;
+        ixX_h[o] = i;
+        valX_h[o] = valT_h[e];
+      }
+    P->nnz = nnz;
   } else if (!X->on_device) {
     size_t bytes = (size_t)d * n * in_el;
     hipError_t e = alloc_tmp(&Xtmp, bytes);
@@ -236,13 +246,49 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   };
 
   hipError_t e;
-  // Storage of Z (X itself; signs and 1/Z_scale are applied in n-space).
-  if ((e = P->alloc(&P->Xs, storage_bytes(P->storage, ld, n))) != hipSuccess)
-    return cleanup(hip_fail(e, "hipMalloc(Z storage)"));
-  P->X_rec = P->Xs;
-  P->st_rec = P->storage == DWD_FP64 ? DWD_FP64 : DWD_FP32;
-  if (P->storage == DWD_BF16) {
-    P->X_lowp = (char*)P->Xs + (size_t)ld * n * 4;
+  const bool csr = X->layout == DWD_CSR;
+  if (csr) {
+    // CSR storage: values FP64 for FP64 storage, else FP32 (no BF16 phase).
+    if (P->storage == DWD_BF16) P->storage = DWD_FP32;
+    P->csr_dtype = P->storage == DWD_FP64 ? DWD_FP64 : DWD_FP32;
+    const size_t vb = P->csr_dtype == DWD_FP64 ? 8 : 4;
+    const int64_t nnz = P->nnz;
+    void *ipT, *ixT, *vT, *ipX, *ixX, *vX;
+    if ((e = P->alloc(&ipT, (n + 1) * 8)) != hipSuccess ||
+        (e = P->alloc(&ixT, nnz * 4)) != hipSuccess || (e = P->alloc(&vT, nnz * vb)) != hipSuccess ||
+        (e = P->alloc(&ipX, (d + 1) * 8)) != hipSuccess ||
+        (e = P->alloc(&ixX, nnz * 4)) != hipSuccess || (e = P->alloc(&vX, nnz * vb)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMalloc(CSR)"));
+    std::vector<float> f32;
+    auto up = [&](void* dst, const std::vector<double>& src) -> hipError_t {
+      if (vb == 8) return hipMemcpy(dst, src.data(), nnz * 8, hipMemcpyHostToDevice);
+      f32.resize(nnz);
+      for (int64_t q = 0; q < nnz; ++q) f32[q] = (float)src[q];
+      return hipMemcpy(dst, f32.data(), nnz * 4, hipMemcpyHostToDevice);
+    };
+    if ((e = hipMemcpy(ipT, ipT_h.data(), (n + 1) * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(ixT, ixT_h.data(), nnz * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = up(vT, valT_h)) != hipSuccess ||
+        (e = hipMemcpy(ipX, ipX_h.data(), (d + 1) * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(ixX, ixX_h.data(), nnz * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = up(vX, valX_h)) != hipSuccess)
+      return cleanup(hip_fail(e, "H2D CSR"));
+    P->ipT = (const int64_t*)ipT;
+    P->ixT = (const int32_t*)ixT;
+    P->valT = vT;
+    P->ipX = (const int64_t*)ipX;
+    P->ixX = (const int32_t*)ixX;
+    P->valX = vX;
+    P->st_rec = P->csr_dtype;
+  } else {
+    // Storage of Z (X itself; signs and 1/Z_scale are applied in n-space).
+    if ((e = P->alloc(&P->Xs, storage_bytes(P->storage, ld, n))) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMalloc(Z storage)"));
+    P->X_rec = P->Xs;
+    P->st_rec = P->storage == DWD_FP64 ? DWD_FP64 : DWD_FP32;
+    if (P->storage == DWD_BF16) {
+      P->X_lowp = (char*)P->Xs + (size_t)ld * n * 4;
+    }
   }
   // scalars + y
   double* dscal = nullptr;
@@ -254,11 +300,17 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
 
   // a0: copy + ||X||_F^2
   const int ychunks = (int)std::max<int64_t>(1, std::min<int64_t>(64, ld / 8192));
+  const int nfb = 256;  // blocks of the CSR norm
   double* part = nullptr;
-  if ((e = alloc_tmp((void**)&part, (size_t)n * ychunks * 8)) != hipSuccess)
+  if ((e = alloc_tmp((void**)&part, (size_t)std::max(n * ychunks, nfb) * 8)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMalloc(part)"));
-  e = launch_frob_copy(Xdev, X->dtype, d, n, P->Xs, P->storage, ld, part, ychunks, st);
-  if (e == hipSuccess) e = launch_sum(part, n * ychunks, dscal, st);
+  if (csr) {
+    e = launch_csr_frob(P->valT, P->csr_dtype, P->nnz, part, nfb, st);
+    if (e == hipSuccess) e = launch_sum(part, nfb, dscal, st);
+  } else {
+    e = launch_frob_copy(Xdev, X->dtype, d, n, P->Xs, P->storage, ld, part, ychunks, st);
+    if (e == hipSuccess) e = launch_sum(part, n * ychunks, dscal, st);
+  }
   double frob2 = 0.0;
   if (e == hipSuccess) e = hipMemcpyAsync(&frob2, dscal, 8, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -276,11 +328,14 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   const size_t nn = (size_t)n * n;
   if ((e = P->alloc((void**)&P->G, nn * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(G)"));
   if ((e = P->alloc((void**)&P->Minv, nn * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(Minv)"));
-  const int splits = gram_splits(ld, n);
+  const int splits = csr ? 1 : gram_splits(ld, n);
   double* Gpart = nullptr;
   if ((e = alloc_tmp((void**)&Gpart, std::max(nn * splits, nn) * 8)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMalloc(Gram partials)"));
-  e = launch_gram(P->X_rec, P->st_rec, ld, n, Gpart, splits, st);
+  if (csr)
+    e = launch_csr_gram(P->ipT, P->ixT, P->valT, P->csr_dtype, n, Gpart, st);
+  else
+    e = launch_gram(P->X_rec, P->st_rec, ld, n, Gpart, splits, st);
   if (e == hipSuccess)
     e = launch_gram_finish(Gpart, splits, n, P->y, 1.0 / (P->zscale * P->zscale), P->mu, P->G,
                            P->Minv, st);
@@ -305,6 +360,7 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
 
   // Iteration buffers.
   if ((e = P->alloc_iter_buffers()) != hipSuccess) return cleanup(hip_fail(e, "iteration buffers"));
+  if (csr) P->nchunks = 1;  // the sparse Z~^T pass writes one chunk
   if ((e = hipHostMalloc((void**)&P->h_flags, 4096, 0)) != hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc"));
   if ((e = hipEventCreate(&P->ev_a)) != hipSuccess) return cleanup(hip_fail(e, "event"));
@@ -408,8 +464,11 @@ hipError_t Problem::queue_iteration(const Consts& c, const void* Xit, int st_it,
       e1 = next_event(1, k);
       (void)hipEventRecord(e0, s);
     }
-    if ((e = launch_gemvT(Xit, st_it, ld, n, ip.u, ip.rho, ip.partT, ip.sc, s)) != hipSuccess)
-      return e;
+    if (layout == DWD_CSR)
+      e = launch_csr_gemvT(ipT, ixT, valT, csr_dtype, n, ip.u, ip.rho, ip.partT, ip.sc, s);
+    else
+      e = launch_gemvT(Xit, st_it, ld, n, ip.u, ip.rho, ip.partT, ip.sc, s);
+    if (e != hipSuccess) return e;
     if (profile) (void)hipEventRecord(e1, s);
   }
   // Without a fresh pass, t and x were formed by the previous tail kernel.
@@ -423,16 +482,28 @@ hipError_t Problem::queue_iteration(const Consts& c, const void* Xit, int st_it,
       e1 = next_event(0, k);
       (void)hipEventRecord(e0, s);
     }
-    if ((e = launch_pass2(Xit, st_it, c, ip, s)) != hipSuccess) return e;
+    if (layout == DWD_CSR)
+      e = launch_csr_pass(ipX, ixX, valX, csr_dtype, d, c, ip, s);
+    else
+      e = launch_pass2(Xit, st_it, c, ip, s);
+    if (e != hipSuccess) return e;
     if (profile) (void)hipEventRecord(e1, s);
   }
-  if (st_it == DWD_BF16) {
+  if (layout == DWD_CSR) {
+    if ((e = launch_tail(c, ip, csr_pass_blocks(ld), 1, s)) != hipSuccess) return e;
+  } else if (st_it == DWD_BF16) {
     if ((e = launch_dspace(c, ip, pass2_blocks(st_it, ld), s)) != hipSuccess) return e;
     if ((e = launch_tail(c, ip, dspace_blocks(ld), 0, s)) != hipSuccess) return e;
   } else {
     if ((e = launch_tail(c, ip, pass2_blocks(st_it, ld), 1, s)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t Problem::pass_T(const double* v1, const double* v2, const Scal* sc) {
+  if (layout == DWD_CSR)
+    return launch_csr_gemvT(ipT, ixT, valT, csr_dtype, n, v1, v2, ip.partT, sc, stream);
+  return launch_gemvT(X_rec, st_rec, ld, n, v1, v2, ip.partT, sc, stream);
 }
 
 hipEvent_t Problem::next_event(int kind, int k) {
@@ -534,8 +605,7 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
   Scal hs;
   int resumed = 0;
   for (;;) {
-    HIP_TRY(launch_gemvT(P->X_rec, P->st_rec, P->ld, P->n, P->ip.w, P->ip.rho, P->ip.partT,
-                         nullptr, st));
+    HIP_TRY(P->pass_T(P->ip.w, P->ip.rho, nullptr));
     HIP_TRY(launch_ngemv(P->n, P->G, P->ip.alpha, P->ip.hG, nullptr, nullptr, nullptr, nullptr,
                          nullptr, nullptr, st));
     HIP_TRY(launch_check(c, P->ip, P->nchunks, st));

@@ -244,4 +244,41 @@ __device__ __forceinline__ double stop_and_sigma(const Consts& c, const double* 
   return sigma;
 }
 
+// Block partials that decide Step 1c and size the Step 2 ball scaling:
+// 0: dr^T G~ dr, 1: y^T dr, 2/3: s^T G~ s and (Z~^T u)^T s of outcome 0,
+// 4/5: the same for outcome 1.
+__device__ __forceinline__ double plan_part(const IterPtrs& p, int q, int b) {
+  const double* r = p.part_c + (size_t)b * NPC;
+  switch (q) {
+    case 0: return r[0];
+    case 1: return p.part_n1[b];
+    case 2: return r[1 + 9];
+    case 3: return r[1 + 10];
+    case 4: return r[1 + NPO + 9];
+    default: return r[1 + NPO + 10];
+  }
+}
+
+// Every thread loads its share of the partials first (one round trip), then
+// one block reduction.
+template <int NT>
+__device__ __forceinline__ void plan_sums(const IterPtrs& p, int nb, double (&a)[6]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) a[j] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += NT) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a[j] += plan_part(p, j, b);
+  }
+  block_sum_k<NT, 6>(a);
+}
+
+template <int NT>
+__device__ __forceinline__ Step2Plan step2_plan(const Consts& c, const IterPtrs& p) {
+  const int k = p.sc->k;
+  const double u2 = p.sc->u2;
+  double a[6];
+  plan_sums<NT>(p, ngemv_blocks(c.n), a);
+  return step2_plan_finish(c, a, k, u2);
+}
+
 }  // namespace dwd

@@ -26,6 +26,9 @@ constexpr int NPO = 11;          // Step 1c partials per outcome: 9 sums + s^T G
 constexpr int NPC = 1 + 2 * NPO; // Step 1c partials per block
 constexpr int NP2 = 6;           // pass partials per block
 
+// Blocks of the one-wave-per-row n x n kernels (4 rows per block).
+__host__ __device__ inline int ngemv_blocks(int n) { return (n + 3) / 4; }
+
 // Indices into Scal::red / Scal::eta.
 enum RedIdx {
   R_PRES2 = 0,     // ||Z~^T w + beta y + xi - r||^2

@@ -18,7 +18,6 @@ hipError_t launch_rhs(const Consts& c, const IterPtrs& p, int nchunks, int fresh
 hipError_t launch_ngemv(int n, const double* A1, const double* x1, double* o1, const double* A2,
                         const double* x2, double* o2, const double* wdot, double* part,
                         const Scal* sc, hipStream_t st);
-__host__ __device__ int ngemv_blocks(int n);
 hipError_t launch_step1ab(const Consts& c, const IterPtrs& p, hipStream_t st);
 hipError_t launch_step1c_rows(const Consts& c, const IterPtrs& p, hipStream_t st);
 hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterPtrs& p,
@@ -29,6 +28,16 @@ int dspace_blocks(int64_t ld);
 hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, int fused, hipStream_t st);
 hipError_t launch_check(const Consts& c, const IterPtrs& p, int nchunks, hipStream_t st);
 bool iter_ptrs_ok(const IterPtrs& p);
+hipError_t launch_csr_frob(const void* val, int dtype, int64_t nnz, double* part, int nblk,
+                           hipStream_t st);
+hipError_t launch_csr_gram(const int64_t* ip, const int32_t* ix, const void* val, int dtype, int n,
+                           double* G, hipStream_t st);
+hipError_t launch_csr_gemvT(const int64_t* ip, const int32_t* ix, const void* val, int dtype,
+                            int n, const double* v1, const double* v2, double* part,
+                            const Scal* sc, hipStream_t st);
+hipError_t launch_csr_pass(const int64_t* ip, const int32_t* ix, const void* val, int dtype,
+                           int64_t d, const Consts& c, const IterPtrs& p, hipStream_t st);
+int csr_pass_blocks(int64_t ld);
 hipError_t launch_norm2(const double* v, int64_t m, double* out, hipStream_t st);
 
 struct Problem {
@@ -61,8 +70,15 @@ struct Problem {
   std::vector<char> ev_live;   // 0 if the launch came after the stop flag was set
   int ev_used = 0;
   std::vector<void*> allocs;
-  std::vector<int64_t> csr_indptr_h;
-  std::vector<int32_t> csr_indices_h;
+  // CSR storage (layout == DWD_CSR): X^T by samples and X by features,
+  // values FP64 (storage FP64) or FP32.
+  const int64_t* ipT = nullptr;
+  const int32_t* ixT = nullptr;
+  const void* valT = nullptr;
+  const int64_t* ipX = nullptr;
+  const int32_t* ixX = nullptr;
+  const void* valX = nullptr;
+  int csr_dtype = DWD_FP32;
 
   hipError_t alloc(void** ptr, size_t bytes);
   hipError_t alloc_iter_buffers();
@@ -70,6 +86,8 @@ struct Problem {
                              bool profile, int k);
   hipError_t run_loop(const Consts& c, const void* Xit, int st_it, int resync, int check_every,
                       bool profile, int k_start);
+  // Z~^T [v1, v2] over the data of record into ip.partT (dense or CSR).
+  hipError_t pass_T(const double* v1, const double* v2, const Scal* sc);
   hipEvent_t next_event(int kind, int k);
 };
 

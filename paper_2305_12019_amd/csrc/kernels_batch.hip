@@ -15,8 +15,6 @@
 
 namespace dwd {
 
-__host__ __device__ int ngemv_blocks(int n);
-
 // Block id -> (row block, active slot).  Blocks are dealt to the 8 XCDs
 // round-robin; a row block stays on one XCD while the slots cycle.
 __device__ __forceinline__ void rows_slot(int bid, int bact, int& rb, int& slot) {

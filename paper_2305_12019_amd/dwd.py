@@ -296,3 +296,42 @@ def footprint(d: int, n: int, storage="f32", layout=DENSE, nnz: int = 0) -> int:
                nnz=nnz, on_device=0)
     p = params(storage=storage)
     return int(_lib.dwd_footprint(C.byref(m), C.byref(p)))
+
+
+def serve(requests: Sequence[Dict], hbm_budget_bytes: float = 0.0, max_slots: int = 0,
+          iters_per_round: int = 0) -> List[Dict]:
+    """Replay a trace with dwd_serve.  Each request is a dict with ``X``
+    (or ``csr=(indptr, indices, values, d)``), ``y``, ``t_arrival`` (s) and
+    ``params`` (keyword overrides of :func:`params`)."""
+    keep: List = []
+    nreq = len(requests)
+    arr = (Request * max(nreq, 1))()
+    resp = (Response * max(nreq, 1))()
+    ws = []
+    for j, rq in enumerate(requests):
+        if "csr" in rq:
+            m = csr_matrix(*rq["csr"], keep)
+        else:
+            m = dense_matrix(rq["X"], keep)
+        yy = np.ascontiguousarray(np.asarray(rq["y"], dtype=np.float64))
+        keep.append(yy)
+        kw = dict(rq.get("params", {}))
+        if "C_" in kw:
+            kw["C"] = kw.pop("C_")
+        arr[j].X = m
+        arr[j].y = yy.ctypes.data
+        arr[j].params = params(**kw)
+        arr[j].t_arrival = float(rq.get("t_arrival", 0.0))
+        w = np.empty(int(m.d))
+        ws.append(w)
+        resp[j].w = w.ctypes.data
+    opts = ServeOpts(hbm_budget_bytes=hbm_budget_bytes, max_slots=max_slots,
+                     iters_per_round=iters_per_round)
+    _check(_lib.dwd_serve(arr, nreq, C.byref(opts), resp))
+    out = []
+    for j in range(nreq):
+        r = resp[j]
+        out.append(dict(status=int(r.status), w=ws[j], beta=r.info.beta, info=r.info.to_dict(),
+                        t_admit=r.t_admit, t_done=r.t_done,
+                        latency=r.t_done - float(requests[j].get("t_arrival", 0.0))))
+    return out

@@ -1,0 +1,152 @@
+"""Sparse (CSR) data and the serving loop (dwd_serve) on the GPU."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dwd_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dwd():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_12019_amd import dwd as D
+    return D
+
+
+def _obj(X, y, w, beta, C, q):
+    w = np.asarray(w, np.float64)
+    return O.reduced_objective(X, y, w / max(1.0, np.linalg.norm(w)), beta, C, q)
+
+
+def _csr_request(d, n, seed, density):
+    req = synth.Request(0, 0.0, d=d, n=n, q=1.0, C=1.0, layout="csr", storage="f32", seed=seed)
+    return synth.request_csr_data(req, density=density)
+
+
+def test_csr_setup_and_solve_match_oracle(dwd):
+    ip, ix, val, y = _csr_request(4000, 150, 77, 5e-3)
+    Xd = synth.csr_to_dense(ip, ix, val, 4000, np.float64)
+    P = dwd.Problem(csr=(ip, ix, val, 4000), y=y, storage="f32")
+    Zt, zs = O.scale_data(Xd, y)
+    assert abs(P.inspect("zscale")[0] - zs) <= 1e-12 * zs
+    G = Zt.T @ Zt
+    assert np.max(np.abs(P.inspect("G") - G)) <= 1e-12 * np.max(np.abs(G))
+    for C, q in ((1.0, 2.0), (0.3, 1.0)):
+        ref = O.solve(Xd, y, C, q, tol=1e-9, max_iter=20000)
+        got = P.solve(C, q, tol=1e-8, max_iter=20000)
+        assert got["info"]["converged"] == 1
+        f, fr = _obj(Xd, y, got["w"], got["beta"], C, q), _obj(Xd, y, ref["w"], ref["beta"], C, q)
+        assert abs(f - fr) <= 1e-6 * abs(fr)
+        assert np.linalg.norm(got["w"] - ref["w"]) <= 1e-4 * np.linalg.norm(ref["w"])
+        e = O.kkt_of_solution(Xd, y, C, q, got)
+        assert max(e["P"], e["D"]) <= 2e-8, e
+    P.close()
+
+
+def test_csr_matches_dense_storage(dwd):
+    ip, ix, val, y = _csr_request(3000, 120, 78, 4e-3)
+    Xd = synth.csr_to_dense(ip, ix, val, 3000, np.float32)
+    Pc = dwd.Problem(csr=(ip, ix, val, 3000), y=y, storage="f32")
+    Pd = dwd.Problem(Xd, y, storage="f32")
+    rc, rd = Pc.solve(1.0, 1.0, tol=1e-6), Pd.solve(1.0, 1.0, tol=1e-6)
+    assert abs(rc["info"]["iters"] - rd["info"]["iters"]) <= 2
+    assert np.linalg.norm(rc["w"] - rd["w"]) <= 1e-6 * np.linalg.norm(rd["w"])
+    Pc.close()
+    Pd.close()
+
+
+def test_csr_rejects_bad_structure(dwd):
+    ip = np.array([0, 2, 3], np.int64)
+    y = np.array([1.0, -1.0])
+    with pytest.raises(dwd.DwdError):
+        dwd.Problem(csr=(ip, np.array([1, 1, 0], np.int32), np.ones(3, np.float32), 5), y=y)
+    with pytest.raises(dwd.DwdError):
+        dwd.Problem(csr=(ip, np.array([0, 7, 0], np.int32), np.ones(3, np.float32), 5), y=y)
+
+
+def _mixed_requests():
+    reqs = []
+    specs = [  # (d, n, q, C, kind, storage)
+        (3000, 200, 1.0, 1.0, "dense", "f32"),
+        (8000, 120, 2.0, 0.5, "dense", "bf16"),
+        (5000, 300, 1.0, 3.0, "csr", "f32"),
+        (1500, 400, 2.0, 1.0, "dense", "f32"),
+        (12000, 90, 1.0, 0.2, "dense", "f32"),
+        (2000, 64, 2.0, 2.0, "csr", "f32"),
+    ]
+    for j, (d, n, q, C, kind, storage) in enumerate(specs):
+        seed = 500 + j
+        if kind == "csr":
+            ip, ix, val, y = _csr_request(d, n, seed, 5e-3)
+            rq = dict(csr=(ip, ix, val, d), y=y)
+        else:
+            X, y = synth.random_two_class(d, n, seed=seed, mean=0.5, dtype="f32")
+            rq = dict(X=X, y=y)
+        rq["params"] = dict(C=C, q=q, tol=1e-5, storage=storage)
+        reqs.append(rq)
+    return reqs
+
+
+def test_serve_result_is_the_same_alone_and_in_the_mix(dwd):
+    reqs = _mixed_requests()
+    for j, r in enumerate(reqs):  # staggered arrivals
+        r["t_arrival"] = 0.002 * j
+    mix = dwd.serve(reqs, iters_per_round=8)
+    for j, r in enumerate(reqs):
+        alone = dwd.serve([dict(r, t_arrival=0.0)], iters_per_round=8)[0]
+        m = mix[j]
+        assert m["status"] == 0 and alone["status"] == 0, (j, m["status"], alone["status"])
+        assert m["info"]["iters"] == alone["info"]["iters"], j
+        assert np.array_equal(m["w"], alone["w"]), j
+        assert m["info"]["kkt_check"] <= 1.5e-5, (j, m["info"])
+    # some requests shared the device
+    iv = [(m["t_admit"], m["t_done"]) for m in mix]
+    assert any(a2 < d1 and a1 < d2 for j, (a1, d1) in enumerate(iv) for (a2, d2) in iv[j + 1:])
+
+
+def test_serve_matches_single_solves_and_oracle(dwd):
+    reqs = _mixed_requests()[:3]
+    res = dwd.serve(reqs)
+    for r, out in zip(reqs, res):
+        p = r["params"]
+        if "csr" in r:
+            ip, ix, val, d = r["csr"]
+            X = synth.csr_to_dense(ip, ix, val, d, np.float64)
+            single = dwd.Problem(csr=r["csr"], y=r["y"], storage=p["storage"]).solve(
+                p["C"], p["q"], tol=p["tol"], want_state=False)
+        else:
+            X = r["X"].astype(np.float64)
+            single = dwd.Problem(r["X"], r["y"], storage=p["storage"]).solve(
+                p["C"], p["q"], tol=p["tol"], want_state=False)
+        assert np.array_equal(single["w"], out["w"])
+        ref = O.solve(X, r["y"], p["C"], p["q"], tol=1e-9, max_iter=20000)
+        same = O.solve(X, r["y"], p["C"], p["q"], tol=p["tol"], max_iter=2000)
+        fr = _obj(X, r["y"], ref["w"], ref["beta"], p["C"], p["q"])
+        err = abs(_obj(X, r["y"], out["w"], out["beta"], p["C"], p["q"]) - fr) / abs(fr)
+        err_o = abs(_obj(X, r["y"], same["w"], same["beta"], p["C"], p["q"]) - fr) / abs(fr)
+        assert err <= max(5 * err_o, 1e-6), (err, err_o)
+
+
+def test_serve_admission_by_memory_budget(dwd):
+    reqs = _mixed_requests()[:4]
+    fps = []
+    for r in reqs:
+        if "X" in r:
+            fps.append(dwd.footprint(r["X"].shape[1], r["X"].shape[0], r["params"]["storage"]))
+        else:
+            ip, _, val, d = r["csr"]
+            fps.append(dwd.footprint(d, len(ip) - 1, r["params"]["storage"], dwd.CSR, len(val)))
+    budget = 1.05 * max(fps)
+    res = dwd.serve(reqs, hbm_budget_bytes=budget)
+    assert all(r["status"] == 0 for r in res)
+    for j, r in enumerate(res):  # resident footprint never exceeds the budget
+        t = r["t_admit"]
+        live = sum(f for f, o in zip(fps, res) if o["t_admit"] <= t < o["t_done"])
+        assert live <= budget, (j, live, budget)
+    big = dict(reqs[0])
+    res = dwd.serve([big], hbm_budget_bytes=0.5 * fps[0])
+    assert res[0]["status"] == -5  # DWD_E_BUSY: can never fit
