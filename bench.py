@@ -1,14 +1,30 @@
 #!/usr/bin/env python
-"""Benchmark: plain generalized-DWD solves on one MI355X.
+"""Benchmark: generalized-DWD solves on one MI355X.
 
-A step is one whole solve of the HDLSS workload (d = 1e5, n = 1e3, FP32 data,
-q = 1, C = 10, relative KKT 1e-5): set-up (scaling, Gram, inverse) plus the
-sGS-ADMM iterations to convergence, with X already resident in HBM.  Prints
-one JSON line; see the design doc for the roofline and baseline definitions.
+A step is one whole plain solve of the HDLSS workload (d = 1e5, n = 1e3,
+FP32 data, q = 1, C = 10, relative KKT 1e-5): set-up (scaling, Gram,
+inverse) plus the sGS-ADMM iterations to convergence, with X already resident
+in HBM.  `value` is plain solves/s over the timed steps.
+
+Beside it, on the same data and to the same tolerance, the line carries
+  batched   the 64 (C, q) problems of the sweep grid solved by dwd_solve_batch
+            against the same 64 problems solved one after another (set-up
+            shared by both), solves/s and the gain;
+  serving   a prefix of the seeded request stream (mixed d, n, q, C, dense
+            FP32/BF16 and CSR) replayed by dwd_serve at 0.75x the measured
+            plain capacity (p50/p99 latency) and with every request queued at
+            t = 0 (solves/s against the plain per-request solves);
+  roofline  the Z~ [s, alpha] pass of the plain solve, timed live with HIP
+            events on the solver's stream, against the HBM peak and against a
+            measured device copy;
+  cpu_baseline  one whole solve of the FP64 oracle on the host cores.
+Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -16,20 +32,63 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6
+FP32_MFMA_PEAK_TFS = 157.3
 METRIC = "solves/s at rel. KKT 1e-5 (d=1e5,n=1e3), batched vs plain; p50/p99 latency"
+PASS_KERNEL_SRCS = [os.path.join(ROOT, "paper_2305_12019_amd", "csrc", f)
+                    for f in ("kernels_iter.hip", "dwd_device.h", "dwd_internal.h")]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pmc_pass2_d1e5_n1e3_f32.md")
 
 
 def pass_bytes(d, ld, n, elem):
     """Algorithmic HBM bytes of one Z~ [s, alpha] pass: the d x n data once,
-    plus u, rho read and w, Z~alpha written (FP64, length ld), plus the two
-    n-vectors."""
-    return d * n * elem + 4 * ld * 8 + 2 * n * 8
+    plus u, rho read and w, u, rho written (FP64, length ld), plus the two
+    n-vectors.  (u and rho are read and written in place: 5 ld-vectors.)"""
+    return d * n * elem + 5 * ld * 8 + 2 * n * 8
 
 
-def cpu_baseline(X, y, wl, iters_needed, sample_iters):
-    """Time the FP64 oracle on the host: its set-up plus `sample_iters`
-    iterations of Algorithm 1 on the same workload, extrapolated to the
-    iteration count the solve needs."""
+def recorded_traffic(bpl):
+    """HBM bytes per pass launch from the committed rocprofv3 counter summary,
+    provided it was taken on the pass kernel's current source (its hash is
+    recorded there); else None."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"source sha256: ([0-9a-f]{64})", text)
+    t = re.search(r"hbm bytes per launch: ([0-9.eE+]+)", text)
+    if not m or not t:
+        return None
+    h = hashlib.sha256()
+    for f in PASS_KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    if h.hexdigest() != m.group(1):
+        return None
+    val = float(t.group(1))
+    return {"bytes_per_launch": val, "ratio_to_algorithmic": val / bpl}
+
+
+def copy_bandwidth(torch, dev, nbytes=2 << 30, reps=10):
+    """Achievable device-to-device copy rate (read + write bytes / time)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / s / 1e9
+
+
+def cpu_baseline(X, y, wl):
+    """One whole solve of the FP64 oracle on the host: set-up plus Algorithm 1
+    to the same tolerance on the same data."""
     import numpy as np
     from oracle import dwd_oracle as O
     try:
@@ -39,19 +98,119 @@ def cpu_baseline(X, y, wl, iters_needed, sample_iters):
         threads = len(os.sched_getaffinity(0))
     Xd = np.asarray(X, dtype=np.float64)
     t0 = time.perf_counter()
-    Zt, zs = O.scale_data(Xd, y)
-    O.SMWFactor(Zt, y, 1.0)
-    t1 = time.perf_counter()
-    O.solve(Xd, y, wl.C, wl.q, tol=1e-300, max_iter=sample_iters)
-    t2 = time.perf_counter()
-    # solve() repeats the set-up; subtract it to get the iterations alone
-    per_iter = max((t2 - t1) - (t1 - t0), 1e-9) / sample_iters
-    setup_s = t1 - t0
-    total = setup_s + per_iter * iters_needed
-    return {"value": 1.0 / total, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"oracle set-up ({setup_s:.1f} s) + {sample_iters} iterations "
-                       f"({per_iter:.2f} s each) on the same d=1e5 n=1e3 data, "
-                       f"extrapolated to {iters_needed} iterations")}
+    ref = O.solve(Xd, y, wl.C, wl.q, tol=wl.tol, max_iter=2000)
+    s = time.perf_counter() - t0
+    return {"value": 1.0 / s, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"one whole oracle solve of the same d=1e5 n=1e3 problem to rel. KKT "
+                       f"{wl.tol:g}: {ref['iters']} iterations, converged={bool(ref['converged'])}, "
+                       f"{s:.1f} s")}
+
+
+def batched_leg(dwd, Xd, y, tol, grid):
+    """64 (C, q) problems on one X: dwd_solve_batch against plain solves."""
+    import numpy as np
+    plist = [dict(C=C, q=q, tol=tol, profile=1) for C, q in grid]
+    P = dwd.Problem(Xd, y, storage="f32")
+    P.solve_batch([dict(C=grid[0][0], q=grid[0][1], tol=tol, max_iter=20)])  # warm-up
+    t = time.perf_counter()
+    rb = P.solve_batch(plist)
+    t_batch = time.perf_counter() - t
+    t = time.perf_counter()
+    plain = [P.solve(C, q, tol=tol, want_state=False) for C, q in grid]
+    t_plain = time.perf_counter() - t
+    d, n = P.d, P.n
+    P.close()
+    ib = rb["info"]
+    it_total = sum(i["iters"] for i in ib)
+    flops = 2.0 * d * n * it_total
+    pass_s = ib[0]["stream_ms"] / 1e3
+    achieved = flops / pass_s / 1e12 if pass_s > 0 else None
+    wdiff = max(np.linalg.norm(rb["W"][j] - plain[j]["w"]) / np.linalg.norm(plain[j]["w"])
+                for j in range(len(grid)))
+    return {
+        "problems": len(grid), "grid": "C = 10^(-2+4a/15), a=0..15, x q in {0.5,1,2,4}",
+        "batched_solves_per_s": len(grid) / t_batch, "batched_s": t_batch,
+        "plain_solves_per_s": len(grid) / t_plain, "plain_s": t_plain,
+        "gain": t_plain / t_batch,
+        "converged_batched": sum(i["converged"] for i in ib),
+        "converged_plain": sum(p["info"]["converged"] for p in plain),
+        "kkt_check_max_batched": max(i["kkt_check"] for i in ib),
+        "kkt_check_max_plain": max(p["info"]["kkt_check"] for p in plain),
+        "max_rel_w_diff_batched_vs_plain": wdiff,
+        "iters_max": max(i["iters"] for i in ib), "iters_sum": it_total,
+        "mfma": {"kernel": "k_pass_b<float,double> (Z~ [s_1..s_B], FP64 MFMA)",
+                 "achieved": achieved, "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                 "frac": (achieved / FP64_MFMA_PEAK_TFS) if achieved else None,
+                 "flops": flops, "pass_ms": ib[0]["stream_ms"],
+                 "launches": ib[0]["stream_launches"]},
+    }
+
+
+def serving_leg(dwd, torch, dev, count, tol):
+    """Replay a prefix of the seeded request stream with dwd_serve."""
+    import numpy as np
+    import synth
+    base = synth.request_stream(count, rate=1.0)
+    reqs = []
+    for r in base:
+        if r.layout == "csr":
+            ip, ix, val, y = synth.request_csr_data(r)
+            reqs.append(dict(csr=(ip, ix, val, r.d), y=y))
+        else:
+            X, y = synth.request_dense_data(r)
+            reqs.append(dict(X=torch.from_numpy(X).to(dev), y=y))
+            del X
+        reqs[-1]["params"] = dict(C=r.C, q=r.q, tol=tol, storage=r.storage)
+    torch.cuda.synchronize()
+    # plain per-request solves, one after another
+    t_plain = []
+    conv_plain = 0
+    for rq in reqs:
+        p = rq["params"]
+        t = time.perf_counter()
+        if "csr" in rq:
+            P = dwd.Problem(csr=rq["csr"], y=rq["y"], storage=p["storage"])
+        else:
+            P = dwd.Problem(rq["X"], rq["y"], storage=p["storage"])
+        res = P.solve(p["C"], p["q"], tol=tol, want_state=False)
+        P.close()
+        t_plain.append(time.perf_counter() - t)
+        conv_plain += res["info"]["converged"]
+    cap = len(reqs) / sum(t_plain)
+    # Poisson arrivals at 0.75 x capacity (same requests: the stream draws its
+    # arrival gaps and request shapes from one generator in a fixed order)
+    lam = 0.75 * cap
+    timed = synth.request_stream(count, rate=lam)
+    for rq, r in zip(reqs, timed):
+        rq["t_arrival"] = r.t_arrival
+    out = dwd.serve(reqs)
+    lat = np.array([o["latency"] for o in out]) * 1e3
+    ok = sum(o["status"] == 0 for o in out)
+    span = max(o["t_done"] for o in out)
+    # every request queued at t = 0: throughput of the continuous batching
+    for rq in reqs:
+        rq["t_arrival"] = 0.0
+    t = time.perf_counter()
+    out0 = dwd.serve(reqs)
+    t_sat = time.perf_counter() - t
+    lat0 = np.array([o["latency"] for o in out0]) * 1e3
+    kinds = {"dense_f32": 0, "dense_bf16": 0, "csr": 0}
+    for r in base:
+        kinds["csr" if r.layout == "csr" else "dense_" + r.storage] += 1
+    return {
+        "requests": len(reqs), "stream": "synth.request_stream(seed 5), first requests",
+        "mix": kinds,
+        "plain_solves_per_s": cap, "plain_p50_ms": float(np.percentile(np.array(t_plain) * 1e3, 50)),
+        "converged_plain": conv_plain,
+        "arrival_rate_per_s": lam,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "ok": ok, "span_s": span,
+        "saturated": {"solves_per_s": len(reqs) / t_sat, "gain_vs_plain": (len(reqs) / t_sat) / cap,
+                      "p50_ms": float(np.percentile(lat0, 50)),
+                      "p99_ms": float(np.percentile(lat0, 99)),
+                      "ok": sum(o["status"] == 0 for o in out0),
+                      "kkt_check_max": max(o["info"]["kkt_check"] for o in out0)},
+    }
 
 
 def main():
@@ -60,7 +219,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64, help="0 to skip the serving leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a 1 GiB device copy (counter calibration) and one solve")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this "
@@ -80,6 +242,17 @@ def main():
     d, n = wl.data.d, wl.data.n
     ld = ((d + 1023) // 1024) * 1024
 
+    if args.copy_probe:
+        # counter calibration: a plain copy of known size, then one solve
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        r = dwd.Problem(Xd, y, storage="f32").solve(wl.C, wl.q, tol=wl.tol, want_state=False)
+        print(json.dumps({"copy_bytes": 2 * a.numel() * 4, "iters": r["info"]["iters"]}),
+              flush=True)
+        return
+
     def step(profile):
         t = time.perf_counter()
         P = dwd.Problem(Xd, y, storage="f32")
@@ -94,6 +267,7 @@ def main():
     runs = [step(1) for _ in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    print(f"[bench] plain: {args.steps} solves in {elapsed:.2f} s", file=sys.stderr, flush=True)
 
     infos = [r["info"] for r, _ in runs]
     lat = np.array([ms for _, ms in runs])
@@ -104,6 +278,8 @@ def main():
     bpl = pass_bytes(d, ld, n, 4)
     achieved = bpl / (avg_us * 1e-6) / 1e9
     iters = int(np.median([i["iters"] for i in infos]))
+    copy_gbs = copy_bandwidth(torch, dev)
+    traffic = recorded_traffic(bpl)
     out = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -125,14 +301,25 @@ def main():
                    "setup_ms": float(np.median([i["setup_ms"] for i in infos])),
                    "solve_ms": float(np.median([i["solve_ms"] for i in infos]))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "roofline": {"bound": "hbm", "kernel": "k_pass2<float,8> (Z~ [s, alpha] pass)",
+        "roofline": {"bound": "hbm", "kernel": "k_pass2<float,8,true> (Z~ [s, alpha] pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_ratio": traffic["ratio_to_algorithmic"] if traffic else None,
                      "avg_launch_us": avg_us, "launches": launches,
-                     "bytes_per_launch": bpl},
+                     "bytes_per_launch": bpl,
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
     }
+    if not args.no_batched:
+        out["batched"] = batched_leg(dwd, Xd, y, wl.tol, synth.sweep_grid())
+        print(f"[bench] batched: gain {out['batched']['gain']:.2f}", file=sys.stderr, flush=True)
+    if args.serve_requests > 0:
+        del Xd
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(dwd, torch, dev, args.serve_requests, wl.tol)
+        print("[bench] serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(X, y, wl, iters, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(X, y, wl)
     print(json.dumps(out), flush=True)
 
 

@@ -89,7 +89,8 @@ typedef struct {
   int32_t check_every; /* iterations queued between host reads of the stop flag */
   int32_t refine;    /* BF16 storage: continue on FP32 data until tol is met    */
   double lowp_tol;   /* BF16 storage: tolerance of the BF16 phase; <= 0: 30*tol */
-  int32_t profile;   /* 1: time the Z-streaming kernels with HIP events         */
+  int32_t profile;   /* 1: time the Z-streaming kernels with HIP events
+                        (dwd_solve_batch reads it from p[0])                    */
   int32_t batch_fp32; /* dwd_solve_batch: 1 = FP32 MFMA products (FP64 sums
                         across K tiles, relative error ~1e-7 per pass, checked
                         and refined in FP64 at the end); 0 = FP64 MFMA (default) */
@@ -111,7 +112,9 @@ typedef struct {
   int32_t iters_lowp;   /* iterations run on BF16 storage                      */
   int32_t status;       /* dwd_status of this problem                          */
   double setup_ms, solve_ms;
-  double stream_ms;     /* profile=1: summed duration of the Z~ [s, alpha] passes */
+  double stream_ms;     /* profile=1: summed duration of the Z~ [s, alpha] passes
+                           (dwd_solve_batch: of all Z~ [s_1..s_B] launches of the
+                           batch, the same value in every report)              */
   int32_t stream_launches; /* profile=1: number of such launches               */
   int32_t resumed;      /* times the loop resumed because the final check failed */
   double streamT_ms;    /* profile=1: summed duration of the Z~^T [u, rho] passes */

@@ -14,7 +14,8 @@ namespace dwd {
 
 hipError_t launch_init_b(const BatchPtrs& P, int B, hipStream_t st);
 hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, const BatchPtrs& P,
-                                  const int* idx, int bact, hipStream_t st);
+                                  const int* idx, int bact, hipStream_t st, hipEvent_t ev0,
+                                  hipEvent_t ev1);
 hipError_t launch_check_b(const BatchPtrs& P, int p, const double* partT, int nchunks,
                           hipStream_t st);
 hipError_t launch_resume_b(const BatchPtrs& P, const int* idx, int cnt, hipStream_t st);
@@ -134,6 +135,29 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   };
   hipEvent_t all_ev[4] = {e0, e1, ev[0], ev[1]};
   EvGuard guard{all_ev, 4};
+  // Optional timing of every pass launch (params[0].profile): event pairs
+  // around the Z~ [s_1..s_B] product, summed after the solve.
+  const bool profile = p[0].profile != 0;
+  std::vector<hipEvent_t> pev;
+  struct PoolGuard {
+    std::vector<hipEvent_t>& v;
+    ~PoolGuard() {
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    }
+  } pguard{pev};
+  auto pass_events = [&](hipEvent_t* a, hipEvent_t* b) -> hipError_t {
+    *a = *b = nullptr;
+    if (!profile) return hipSuccess;
+    hipEvent_t x, y;
+    hipError_t e;
+    if ((e = hipEventCreate(&x)) != hipSuccess) return e;
+    pev.push_back(x);
+    if ((e = hipEventCreate(&y)) != hipSuccess) return e;
+    pev.push_back(y);
+    *a = x;
+    *b = y;
+    return hipSuccess;
+  };
   HIP_TRY_B(hipEventRecord(e0, st));
   HIP_TRY_B(hipMemcpyAsync(dcs, hcs, (size_t)B * sizeof(Consts), hipMemcpyHostToDevice, st));
   HIP_TRY_B(hipMemcpyAsync(didx[0], hidx[0], (size_t)B * 4, hipMemcpyHostToDevice, st));
@@ -146,8 +170,12 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   auto run = [&](int bact, int budget, int fp64) -> dwd_status {
     int queued = 0, pending = -1;
     for (int cidx = 0;; ++cidx) {
-      for (int j = 0; j < chunk && queued < budget; ++j, ++queued)
-        HIP_TRY_B(launch_batch_iteration(P->X_rec, P->st_rec, fp64, bp, didx[cur], bact, st));
+      for (int j = 0; j < chunk && queued < budget; ++j, ++queued) {
+        hipEvent_t pa, pb;
+        HIP_TRY_B(pass_events(&pa, &pb));
+        HIP_TRY_B(launch_batch_iteration(P->X_rec, P->st_rec, fp64, bp, didx[cur], bact, st, pa,
+                                         pb));
+      }
       const int slot = cidx & 1;
       HIP_TRY_B(hipMemcpyAsync(hsc[slot], bp.sc, (size_t)B * sizeof(Scal),
                                hipMemcpyDeviceToHost, st));
@@ -225,6 +253,12 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   HIP_TRY_B(hipStreamSynchronize(st));
   float ms = 0.0f;
   HIP_TRY_B(hipEventElapsedTime(&ms, e0, e1));
+  double pass_ms = 0.0;
+  for (size_t j = 0; j + 1 < pev.size(); j += 2) {
+    float t = 0.0f;
+    HIP_TRY_B(hipEventElapsedTime(&t, pev[j], pev[j + 1]));
+    pass_ms += t;
+  }
   if (W) {
     std::vector<double> hw((size_t)P->d);
     for (int j = 0; j < B; ++j) {
@@ -258,6 +292,8 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
       in.solve_ms = ms;
       in.status = hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
       in.resumed = resumed[j];
+      in.stream_ms = pass_ms;  // all pass launches of the batch
+      in.stream_launches = (int32_t)(pev.size() / 2);
     }
   }
   return all_conv ? DWD_OK : DWD_NOT_CONVERGED;

@@ -647,7 +647,8 @@ bool batch_ptrs_ok(const BatchPtrs& P) {
 }
 
 hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, const BatchPtrs& P,
-                                  const int* idx, int bact, hipStream_t st) {
+                                  const int* idx, int bact, hipStream_t st, hipEvent_t ev0,
+                                  hipEvent_t ev1) {
   if (!X || !idx || bact < 1 || !batch_ptrs_ok(P)) return hipErrorInvalidValue;
   if (storage != DWD_FP32 && storage != DWD_FP64) return hipErrorInvalidValue;
   const dim3 grow(batch_row_grid(P.nb, bact));
@@ -655,6 +656,7 @@ hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, con
   hipLaunchKernelGGL(k_step1c_b, grow, dim3(256), 0, st, P, idx, bact);
   hipLaunchKernelGGL(k_plan_b, dim3(bact), dim3(256), 0, st, P, idx);
   const dim3 gp((unsigned)(P.ld / BT_M), (bact + BT_N - 1) / BT_N);
+  if (ev0) (void)hipEventRecord(ev0, st);
   if (storage == DWD_FP32 && !fp64_mfma)
     hipLaunchKernelGGL((k_pass_b<float, float>), gp, dim3(BT_T), 0, st, (const float*)X, P, idx,
                        bact);
@@ -664,6 +666,7 @@ hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, con
   else
     hipLaunchKernelGGL((k_pass_b<double, double>), gp, dim3(BT_T), 0, st, (const double*)X, P,
                        idx, bact);
+  if (ev1) (void)hipEventRecord(ev1, st);
   hipLaunchKernelGGL(k_galpha_b, grow, dim3(256), 0, st, P, idx, bact);
   hipLaunchKernelGGL(k_tail_b, dim3(bact), dim3(NTB), 0, st, P, idx);
   return hipGetLastError();
