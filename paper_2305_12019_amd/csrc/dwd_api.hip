@@ -508,8 +508,11 @@ hipError_t Problem::pass_T(const double* v1, const double* v2, const Scal* sc) {
 
 hipEvent_t Problem::next_event(int kind, int k) {
   if (ev_used >= (int)ev_pool.size()) {
+    // timing-only events: no system-scope fence (cache writeback and
+    // invalidate) at record, which would both inflate the timed interval and
+    // flush what the following kernels reuse
     hipEvent_t ev;
-    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     ev_pool.push_back(ev);
     ev_kind.push_back(kind);
     ev_iter.push_back(k);

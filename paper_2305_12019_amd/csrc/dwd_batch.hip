@@ -150,9 +150,9 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
     if (!profile) return hipSuccess;
     hipEvent_t x, y;
     hipError_t e;
-    if ((e = hipEventCreate(&x)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&x, hipEventDisableSystemFence)) != hipSuccess) return e;
     pev.push_back(x);
-    if ((e = hipEventCreate(&y)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&y, hipEventDisableSystemFence)) != hipSuccess) return e;
     pev.push_back(y);
     *a = x;
     *b = y;

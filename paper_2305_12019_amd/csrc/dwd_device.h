@@ -14,37 +14,60 @@ namespace dwd {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Vec;
+// Loads of the streamed data are nontemporal: X is read once per pass and
+// is far larger than the caches, so it should not evict the n x n matrices
+// and the n-vectors that the other kernels of the iteration reuse.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+// raw(): one nontemporal vector load, kept in its storage type until
+// cvt() widens it to FP64 at the point of use (half the registers of loads
+// in flight for FP32 data); load() = cvt(raw()).
 template <>
 struct Vec<double> {
   static constexpr int N = 2;
-  __device__ static __forceinline__ void load(const double* p, double (&o)[2]) {
-    const double2 v = *reinterpret_cast<const double2*>(p);
+  typedef nt_d2 raw_t;
+  __device__ static __forceinline__ raw_t raw(const double* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  }
+  __device__ static __forceinline__ void cvt(const raw_t& v, double (&o)[2]) {
     o[0] = v.x;
     o[1] = v.y;
   }
+  __device__ static __forceinline__ void load(const double* p, double (&o)[2]) { cvt(raw(p), o); }
 };
 template <>
 struct Vec<float> {
   static constexpr int N = 4;
-  __device__ static __forceinline__ void load(const float* p, double (&o)[4]) {
-    const float4 v = *reinterpret_cast<const float4*>(p);
+  typedef nt_f4 raw_t;
+  __device__ static __forceinline__ raw_t raw(const float* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+  }
+  __device__ static __forceinline__ void cvt(const raw_t& v, double (&o)[4]) {
     o[0] = v.x;
     o[1] = v.y;
     o[2] = v.z;
     o[3] = v.w;
   }
+  __device__ static __forceinline__ void load(const float* p, double (&o)[4]) { cvt(raw(p), o); }
 };
 template <>
 struct Vec<uint16_t> {
   static constexpr int N = 8;
-  __device__ static __forceinline__ void load(const uint16_t* p, double (&o)[8]) {
-    const uint4 v = *reinterpret_cast<const uint4*>(p);
+  typedef nt_u4 raw_t;
+  __device__ static __forceinline__ raw_t raw(const uint16_t* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p));
+  }
+  __device__ static __forceinline__ void cvt(const raw_t& v, double (&o)[8]) {
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       o[2 * i] = (double)__uint_as_float(w[i] << 16);
       o[2 * i + 1] = (double)__uint_as_float(w[i] & 0xFFFF0000u);
     }
+  }
+  __device__ static __forceinline__ void load(const uint16_t* p, double (&o)[8]) {
+    cvt(raw(p), o);
   }
 };
 

@@ -432,57 +432,121 @@ constexpr int PANEL = 2048;
 // writes w and Z~ alpha and leaves Steps 2-3 to k_dspace, which takes ||g||
 // from the pass itself.
 template <typename T, int NW, bool FUSED>
-__global__ void __launch_bounds__(NW * 64) k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2)))
+k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
   if (p.sc->done) return;
+  constexpr int NT = NW * 64;
   constexpr int V = Vec<T>::N;
   constexpr int ROWS = 64 * V;
-  __shared__ double sv[2][PANEL];
-  __shared__ double red[NW][2][ROWS];
+  constexpr int RPT = (ROWS + NT - 1) / NT;  // epilogue rows per thread
+  constexpr int RB = (512 + NT - 1) / NT;    // plan partial blocks per thread (n <= 2048)
+  // Both Step 1c candidates of the scaled operand, [s | s1 | alpha0 | alpha1],
+  // are staged so that staging does not wait for the plan; after the column
+  // loop the same memory holds the per-wave row sums.
+  __shared__ double lds[4 * PANEL];
+  static_assert(2 * NW * ROWS <= 4 * PANEL, "row sums must fit the staging buffer");
+  double(*red)[2][ROWS] = reinterpret_cast<double(*)[2][ROWS]>(lds);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t rbase = (int64_t)blockIdx.x * ROWS;
   const T* xrow = X + rbase + lane * V;
-  const Step2Plan pl = step2_plan<NW * 64>(c, p);
-  const double* sv_s = pl.redo ? p.s1 : p.s;
-  const double* sv_a = pl.redo ? p.al1 : p.al0;
+  // Everything the prologue needs is requested before anything waits: the
+  // first four columns of this wave's share of the first panel, the rows'
+  // u and rho for the epilogue, the plan partials and the staged operand.
+  typename Vec<T>::raw_t pf[4];
+  const int per0 = (min(PANEL, c.n) + NW - 1) / NW;
+  const int pj0 = wid * per0, pj1 = min(min(PANEL, c.n), pj0 + per0);
+  const bool have_pf = pj0 + 4 <= pj1;
+  if (have_pf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pf[u] = Vec<T>::raw(xrow + (int64_t)(pj0 + u) * c.ld);
+  }
+  double u_in[RPT], rho_in[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int rr = threadIdx.x + q * NT;
+    u_in[q] = rr < ROWS ? p.u[rbase + rr] : 0.0;
+    rho_in[q] = rr < ROWS ? p.rho[rbase + rr] : 0.0;
+  }
+  const int nb = ngemv_blocks(c.n);
+  const bool few = nb <= RB * NT;
+  double raw[RB][6];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int b = threadIdx.x + r * NT;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) raw[r][j] = (few && b < nb) ? plan_part(p, j, b) : 0.0;
+  }
+  const int k_it = p.sc->k;
+  const double u2 = p.sc->u2;
+  auto stage = [&](int pc, int pn) {
+    for (int i = threadIdx.x; i < pn; i += NT) {
+      const double yz = p.y[pc + i] * c.inv_zs;
+      lds[i] = yz * p.s[pc + i];
+      lds[PANEL + i] = yz * p.s1[pc + i];
+      lds[2 * PANEL + i] = yz * p.al0[pc + i];
+      lds[3 * PANEL + i] = yz * p.al1[pc + i];
+    }
+  };
+  stage(0, min(PANEL, c.n));
+  double a[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) a[j] = 0.0;
+  if (few) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) a[j] += raw[r][j];
+  } else {
+    for (int b = threadIdx.x; b < nb; b += NT)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) a[j] += plan_part(p, j, b);
+  }
+  block_sum_k<NT, 6>(a);  // also orders the staging writes before their reads
+  const Step2Plan pl = step2_plan_finish(c, a, k_it, u2);
+  const int os = pl.redo ? PANEL : 0;
   double as[V], aa[V];
 #pragma unroll
   for (int e = 0; e < V; ++e) as[e] = aa[e] = 0.0;
+  auto group = [&](const typename Vec<T>::raw_t (&xr)[4], int j) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double x[V];
+      Vec<T>::cvt(xr[u], x);
+      const double s0 = lds[os + j + u], s1 = lds[2 * PANEL + os + j + u];
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        as[e] = fma(x[e], s0, as[e]);
+        aa[e] = fma(x[e], s1, aa[e]);
+      }
+    }
+  };
   for (int pc = 0; pc < c.n; pc += PANEL) {
     const int pn = min(PANEL, c.n - pc);
-    for (int i = threadIdx.x; i < pn; i += NW * 64) {
-      const double yz = p.y[pc + i] * c.inv_zs;
-      sv[0][i] = yz * sv_s[pc + i];
-      sv[1][i] = yz * sv_a[pc + i];
+    if (pc > 0) {
+      stage(pc, pn);
+      __syncthreads();
     }
-    __syncthreads();
     const int per = (pn + NW - 1) / NW;
     const int j0 = wid * per, j1 = min(pn, j0 + per);
     int j = j0;
+    if (pc == 0 && have_pf) {
+      group(pf, j);
+      j += 4;
+    }
     for (; j + 4 <= j1; j += 4) {
-      double x0[V], x1[V], x2[V], x3[V];
-      Vec<T>::load(xrow + (int64_t)(pc + j) * c.ld, x0);
-      Vec<T>::load(xrow + (int64_t)(pc + j + 1) * c.ld, x1);
-      Vec<T>::load(xrow + (int64_t)(pc + j + 2) * c.ld, x2);
-      Vec<T>::load(xrow + (int64_t)(pc + j + 3) * c.ld, x3);
+      typename Vec<T>::raw_t x[4];
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        as[e] = fma(x0[e], sv[0][j], as[e]);
-        aa[e] = fma(x0[e], sv[1][j], aa[e]);
-        as[e] = fma(x1[e], sv[0][j + 1], as[e]);
-        aa[e] = fma(x1[e], sv[1][j + 1], aa[e]);
-        as[e] = fma(x2[e], sv[0][j + 2], as[e]);
-        aa[e] = fma(x2[e], sv[1][j + 2], aa[e]);
-        as[e] = fma(x3[e], sv[0][j + 3], as[e]);
-        aa[e] = fma(x3[e], sv[1][j + 3], aa[e]);
-      }
+      for (int u = 0; u < 4; ++u) x[u] = Vec<T>::raw(xrow + (int64_t)(pc + j + u) * c.ld);
+      group(x, j);
     }
     for (; j < j1; ++j) {
       double x0[V];
       Vec<T>::load(xrow + (int64_t)(pc + j) * c.ld, x0);
+      const double s0 = lds[os + j], s1 = lds[2 * PANEL + os + j];
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        as[e] = fma(x0[e], sv[0][j], as[e]);
-        aa[e] = fma(x0[e], sv[1][j], aa[e]);
+        as[e] = fma(x0[e], s0, as[e]);
+        aa[e] = fma(x0[e], s1, aa[e]);
       }
     }
     __syncthreads();
@@ -498,7 +562,10 @@ __global__ void __launch_bounds__(NW * 64) k_pass2(const T* __restrict__ X, Cons
   const double br = c.sqmu / sigma, gr = 1.0 / (sigma * c.sqmu);
   const double rs = c.tau * sigma * c.sqmu;
   double acc[NP2] = {0, 0, 0, 0, 0, 0};
-  for (int rr = threadIdx.x; rr < ROWS; rr += NW * 64) {
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int rr = threadIdx.x + q * NT;
+    if (rr >= ROWS) break;
     double zs = 0.0, za = 0.0;
 #pragma unroll
     for (int ww = 0; ww < NW; ++ww) {
@@ -506,8 +573,8 @@ __global__ void __launch_bounds__(NW * 64) k_pass2(const T* __restrict__ X, Cons
       za += red[ww][1][rr];
     }
     const int64_t k = rbase + rr;
-    const double rho = p.rho[k];
-    const double b = c.mu * p.u[k] + br * rho;
+    const double rho = rho_in[q];
+    const double b = c.mu * u_in[q] + br * rho;
     const double w = (b - zs) / c.mu;
     p.w[k] = w;
     if constexpr (FUSED) {
