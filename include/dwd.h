@@ -94,6 +94,15 @@ typedef struct {
   int32_t batch_fp32; /* dwd_solve_batch: 1 = FP32 MFMA products (FP64 sums
                         across K tiles, relative error ~1e-7 per pass, checked
                         and refined in FP64 at the end); 0 = FP64 MFMA (default) */
+  int32_t batch_tile; /* dwd_solve_batch: slots per block of the Z~ [s_1..s_B]
+                        product, in units of 16: 1, 2 or 4; 0 (default) = chosen
+                        per active-slot count by timing the candidates on the
+                        first iterations (cached per device and shape).  Every
+                        choice gives bit-identical results.                    */
+  int32_t graph;     /* dwd_solve_batch: 1 (default) = replay each chunk of
+                        check_every iterations as a captured hipGraph once the
+                        tile is fixed (not with profile = 1); 0 = launch each
+                        kernel.  Results are identical either way.             */
 } dwd_params;
 
 /* Per-solve report.  Residuals are those of Section 4.3 on the scaled
@@ -119,7 +128,7 @@ typedef struct {
   int32_t resumed;      /* times the loop resumed because the final check failed */
   double streamT_ms;    /* profile=1: summed duration of the Z~^T [u, rho] passes */
   int32_t streamT_launches;
-  int32_t reserved;
+  int32_t graph_launches; /* dwd_solve_batch: chunks replayed as a captured graph */
 } dwd_info;
 
 typedef struct dwd_problem_s* dwd_problem;

@@ -72,6 +72,8 @@ dwd_status validate_params(const dwd_params* p, bool for_solve) {
     return fail(DWD_E_INVALID, "tau must be in (0, (1+sqrt 5)/2)");
   if (!std::isfinite(p->sigma0) || !std::isfinite(p->eps_c))
     return fail(DWD_E_INVALID, "sigma0 and eps_c must be finite");
+  if (p->batch_tile != 0 && p->batch_tile != 1 && p->batch_tile != 2 && p->batch_tile != 4)
+    return fail(DWD_E_INVALID, "batch_tile must be 0, 1, 2 or 4");
   return DWD_OK;
 }
 
@@ -713,6 +715,9 @@ void dwd_default_params(dwd_params* p) {
   p->refine = 1;
   p->lowp_tol = 0.0;
   p->profile = 0;
+  p->batch_fp32 = 0;
+  p->batch_tile = 0;
+  p->graph = 1;
 }
 
 dwd_status dwd_setup(const dwd_matrix* X, const double* y, const dwd_params* p, void* stream,

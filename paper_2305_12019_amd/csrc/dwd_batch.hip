@@ -6,6 +6,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "dwd_solver.h"
@@ -14,8 +18,8 @@ namespace dwd {
 
 hipError_t launch_init_b(const BatchPtrs& P, int B, hipStream_t st);
 hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, const BatchPtrs& P,
-                                  const int* idx, int bact, hipStream_t st, hipEvent_t ev0,
-                                  hipEvent_t ev1);
+                                  const int* idx, int bact, int tile, hipStream_t st,
+                                  hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_check_b(const BatchPtrs& P, int p, const double* partT, int nchunks,
                           hipStream_t st);
 hipError_t launch_resume_b(const BatchPtrs& P, const int* idx, int cnt, hipStream_t st);
@@ -24,6 +28,103 @@ hipError_t launch_anchor_b(const BatchPtrs& P, int p, const double* partT, int n
 int batch_pass_row_blocks(int64_t ld);
 
 namespace {
+
+// Tile tuner for the batched pass.  The tile width (16, 32 or 64 slots per
+// block) that runs fastest depends on the number of active slots, on the
+// shape and on the device; every width gives bit-identical results, so the
+// tuner simply times the candidates on real iterations of the solve (a
+// rotation over the candidates until each has two completed timings) and
+// caches the winner per (device, storage, product precision, ld, n, slot
+// bucket) for the rest of the process.
+constexpr int kTiles[3] = {1, 2, 4};
+constexpr int kTrialsPerTile = 2;
+
+struct TuneKey {
+  int device, storage, fp64, n, bucket;
+  int64_t ld;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(device, storage, fp64, n, bucket, ld) <
+           std::tie(o.device, o.storage, o.fp64, o.n, o.bucket, o.ld);
+  }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;  // key -> tile
+
+int slot_bucket(int bact) { return std::min(4, (bact + 15) / 16); }
+
+struct Tuner {
+  TuneKey base;
+  int forced = 0;
+  struct Trial {
+    int bucket, ti, chunk;
+    hipEvent_t a, b;
+  };
+  std::vector<Trial> trials;
+  std::map<int, int> rot;                       // bucket -> trial launches issued
+  std::map<int, std::array<double, 3>> sum;     // bucket -> summed ms per candidate
+  std::map<int, std::array<int, 3>> cnt;
+  std::vector<hipEvent_t> pool;
+  ~Tuner() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+  int cached(int bucket) {
+    if (forced) return forced;
+    TuneKey k = base;
+    k.bucket = bucket;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tuned.find(k);
+    return it == g_tuned.end() ? 0 : it->second;
+  }
+  // Tile for the next launch at `bact` active slots.  While the bucket is
+  // untuned the launch is a timed trial: it uses the events in *ea/*eb if
+  // the caller brings a pair (profiling), else a pair from the pool.
+  hipError_t pick(int bact, int chunk, int* tile, hipEvent_t* ea, hipEvent_t* eb) {
+    const int bucket = slot_bucket(bact);
+    const int t = cached(bucket);
+    if (t) {
+      *tile = t;
+      return hipSuccess;
+    }
+    const int ti = rot[bucket]++ % 3;
+    *tile = kTiles[ti];
+    if (!*ea) {
+      hipError_t e;
+      if ((e = hipEventCreateWithFlags(ea, hipEventDisableSystemFence)) != hipSuccess) return e;
+      pool.push_back(*ea);
+      if ((e = hipEventCreateWithFlags(eb, hipEventDisableSystemFence)) != hipSuccess) return e;
+      pool.push_back(*eb);
+    }
+    trials.push_back({bucket, ti, chunk, *ea, *eb});
+    return hipSuccess;
+  }
+  // Fold in the trials of chunks <= done_chunk (their work has completed).
+  void collect(int done_chunk) {
+    std::vector<Trial> left;
+    for (const Trial& t : trials) {
+      if (t.chunk > done_chunk) {
+        left.push_back(t);
+        continue;
+      }
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess) continue;
+      auto& s = sum[t.bucket];  // value-initialised (zeros) on first use
+      auto& c = cnt[t.bucket];
+      s[t.ti] += ms;
+      c[t.ti] += 1;
+      if (c[0] >= kTrialsPerTile && c[1] >= kTrialsPerTile && c[2] >= kTrialsPerTile) {
+        int best = 0;
+        for (int i = 1; i < 3; ++i)
+          if (s[i] / c[i] < s[best] / c[best]) best = i;
+        TuneKey k = base;
+        k.bucket = t.bucket;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned.emplace(k, kTiles[best]);
+      }
+    }
+    trials.swap(left);
+  }
+};
 
 struct BatchBuffers {
   std::vector<void*> dev;
@@ -70,7 +171,7 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   bp.G = P->G;
   bp.n = n;
   bp.ld = ld;
-  bp.nb = ngemv_blocks(n);
+  bp.nb = (n + 15) / 16;  // 16-row tiles of the n x n products
   bp.npb = batch_pass_row_blocks(ld);
   const size_t nB = (size_t)n * B;
   double* nv = nullptr;
@@ -164,18 +265,82 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   HIP_TRY_B(launch_init_b(bp, B, st));
 
   const int chunk = std::max(1, p[0].check_every > 0 ? p[0].check_every : 8);
+  Tuner tuner;
+  tuner.base = TuneKey{P->device, P->st_rec, fp64_mfma, n, 0, ld};
+  tuner.forced = p[0].batch_tile;
+  // Chunks of iterations replayed as a captured graph once the tile of the
+  // current slot count is fixed; re-captured when the active list, the tile
+  // or the product precision changes.  Capture needs a stream other than the
+  // legacy default one, so it is done on a stream of its own; the graph is
+  // launched on the solve's stream.
+  const bool use_graph = p[0].graph != 0 && !profile;
+  struct GraphCache {
+    hipStream_t cap = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int bact = -1, cur = -1, tile = 0, fp64 = -1;
+    void drop() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (g) (void)hipGraphDestroy(g);
+      exec = nullptr;
+      g = nullptr;
+    }
+    ~GraphCache() {
+      drop();
+      if (cap) (void)hipStreamDestroy(cap);
+    }
+  } gc;
+  int graph_launches = 0, graph_captures = 0;
+  int cur = 0;
+  auto queue_chunk = [&](int bact, int len, int fp64, int cidx) -> dwd_status {
+    const int fixed = tuner.cached(slot_bucket(bact));
+    if (use_graph && fixed && len == chunk) {
+      if (!(gc.exec && gc.bact == bact && gc.cur == cur && gc.tile == fixed && gc.fp64 == fp64)) {
+        gc.drop();
+        if (!gc.cap) HIP_TRY_B(hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking));
+        HIP_TRY_B(hipStreamBeginCapture(gc.cap, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int j = 0; j < len && ce == hipSuccess; ++j)
+          ce = launch_batch_iteration(P->X_rec, P->st_rec, fp64, bp, didx[cur], bact, fixed,
+                                      gc.cap, nullptr, nullptr);
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(gc.cap, &g);
+        if (ce != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          return hip_fail(ce, "batched iteration (capture)");
+        }
+        HIP_TRY_B(ee);
+        gc.g = g;
+        HIP_TRY_B(hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0));
+        gc.bact = bact;
+        gc.cur = cur;
+        gc.tile = fixed;
+        gc.fp64 = fp64;
+        ++graph_captures;
+      }
+      HIP_TRY_B(hipGraphLaunch(gc.exec, st));
+      ++graph_launches;
+      return DWD_OK;
+    }
+    for (int j = 0; j < len; ++j) {
+      hipEvent_t pa, pb;
+      HIP_TRY_B(pass_events(&pa, &pb));
+      int tile = 0;
+      HIP_TRY_B(tuner.pick(bact, cidx, &tile, &pa, &pb));
+      HIP_TRY_B(launch_batch_iteration(P->X_rec, P->st_rec, fp64, bp, didx[cur], bact, tile, st,
+                                       pa, pb));
+    }
+    return DWD_OK;
+  };
   // Run the stepping loop over the active list in didx[cur] (bact entries)
   // until every listed problem has stopped or `budget` iterations are queued.
-  int cur = 0;
   auto run = [&](int bact, int budget, int fp64) -> dwd_status {
     int queued = 0, pending = -1;
     for (int cidx = 0;; ++cidx) {
-      for (int j = 0; j < chunk && queued < budget; ++j, ++queued) {
-        hipEvent_t pa, pb;
-        HIP_TRY_B(pass_events(&pa, &pb));
-        HIP_TRY_B(launch_batch_iteration(P->X_rec, P->st_rec, fp64, bp, didx[cur], bact, st, pa,
-                                         pb));
-      }
+      const int len = std::min(chunk, budget - queued);
+      dwd_status qs = queue_chunk(bact, len, fp64, cidx);
+      if (qs != DWD_OK) return qs;
+      queued += len;
       const int slot = cidx & 1;
       HIP_TRY_B(hipMemcpyAsync(hsc[slot], bp.sc, (size_t)B * sizeof(Scal),
                                hipMemcpyDeviceToHost, st));
@@ -183,6 +348,7 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
       if (queued >= budget) break;
       if (pending >= 0) {
         HIP_TRY_B(hipEventSynchronize(ev[pending & 1]));
+        tuner.collect(pending);
         const Scal* hs = hsc[pending & 1];
         int nact = 0;
         int* nidx = hidx[1 - cur];
@@ -199,6 +365,7 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
       pending = cidx;
     }
     HIP_TRY_B(hipStreamSynchronize(st));
+    tuner.collect(1 << 30);
     return DWD_OK;
   };
   // Final FP64 check of every listed problem over the data of record.
@@ -294,6 +461,7 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
       in.resumed = resumed[j];
       in.stream_ms = pass_ms;  // all pass launches of the batch
       in.stream_launches = (int32_t)(pev.size() / 2);
+      in.graph_launches = graph_launches;
     }
   }
   return all_conv ? DWD_OK : DWD_NOT_CONVERGED;

@@ -3,9 +3,11 @@
 // mu (Section 3.3.2), so G~, M^-1 and M^-1 y are shared; each problem keeps
 // its own (C, q, sigma, ...) and iterates exactly as a single solve would.
 // The pass over Z becomes one matrix product Z~ [s_1 .. s_B] on MFMA with
-// the Step 2-3 epilogue; the n x n products keep one wave per row, with an
-// XCD-aware block order so that the blocks of all problems that read the
-// same rows of M^-1 / G~ run on one XCD and share its L2.
+// the Step 2-3 epilogue, and the n x n products M^-1 [x_1 .. x_B],
+// [G~; M^-1] [dr_1 .. dr_B] and G~ [alpha_1 .. alpha_B] become FP64 MFMA
+// products in 16 x 16 tiles with the Step 1a-1c element work fused into
+// their epilogues; blocks that read the same rows of M^-1 / G~ are placed on
+// one XCD so that they share its L2.
 #include <float.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -14,16 +16,6 @@
 #include "dwd_internal.h"
 
 namespace dwd {
-
-// Block id -> (row block, active slot).  Blocks are dealt to the 8 XCDs
-// round-robin; a row block stays on one XCD while the slots cycle.
-__device__ __forceinline__ void rows_slot(int bid, int bact, int& rb, int& slot) {
-  const int xcd = bid & 7, m = bid >> 3;
-  rb = xcd + 8 * (m / bact);
-  slot = m % bact;
-}
-
-int batch_row_grid(int nb, int bact) { return 8 * ((nb + 7) / 8) * bact; }
 
 // ---------------------------------------------------------------------------
 // Initial point of every problem (as k_init) and t = x = 0 for the first
@@ -77,154 +69,270 @@ hipError_t launch_init_b(const BatchPtrs& P, int B, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Step 1a + 1b per (row, problem); see k_step1ab.
+// n x n by n x B products on FP64 MFMA.  A block computes one 16 x 16 tile
+// (16 rows of the n x n matrices, 16 active slots); its 8 waves split the
+// inner dimension and their partial tiles are summed in a fixed order.
+// Lane l = i + 16 q supplies A[row i][k] and B[k][slot i] for the k = q mod 4
+// of each group of four, from four consecutive k that it loads itself (step t
+// of a group multiplies the k = 4q + t terms).  A dot product of every slot's
+// column with one fixed n-vector (m_y) rides along on the same loads.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_step1ab_b(BatchPtrs P, const int* __restrict__ idx,
-                                                   int bact) {
-  int rb, slot;
-  rows_slot(blockIdx.x, bact, rb, slot);
-  if (rb >= P.nb) return;
-  const int pr = idx[slot];
-  Scal* sc = P.sc + pr;
-  if (sc->done) return;
-  const Consts c = P.cs[pr];
-  __shared__ double wy[4];
-  __shared__ int ws[4];
-  const size_t on = (size_t)pr * P.n;
-  const double* x = P.XX + on;
+constexpr int NM_W = 8, NM_T = NM_W * 64;
+
+typedef double nm_acc_t __attribute__((ext_vector_type(4)));
+
+// Block id -> (row tile, slot tile): the blocks of one row tile share an XCD.
+__device__ __forceinline__ bool nm_tile(int nbx, int nby, int& bx, int& by) {
+  const int b = blockIdx.x, xcd = b & 7, m = b >> 3;
+  bx = xcd + 8 * (m / nby);
+  by = m % nby;
+  return bx < nbx;
+}
+
+int nm_grid(int n, int bact) {
+  const int nbx = (n + 15) / 16, nby = (bact + 15) / 16;
+  return 8 * ((nbx + 7) / 8) * nby;
+}
+
+template <int NA, bool DOT>
+struct NmRegs {
+  double a[NA][4], b[4], m[DOT ? 4 : 1];
+};
+
+template <int NA, bool DOT>
+__device__ __forceinline__ void nm_load(const double* const (&A)[NA], const double* col,
+                                        const double* dv, int n, int row, int k0, int kend,
+                                        NmRegs<NA, DOT>& R) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = k0 + t;
+    const bool ok = k < kend;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) R.a[a][t] = (ok && row < n) ? A[a][(size_t)row * n + k] : 0.0;
+    R.b[t] = (ok && col) ? col[k] : 0.0;
+    if constexpr (DOT) R.m[t] = ok ? dv[k] : 0.0;
+  }
+}
+
+// Products of this block's tile, left in red[a][i * 16 + j] (row i, slot j)
+// of every output a, and the slot dot products in dot[j]; ends with a block
+// barrier.  col: the B column of the lane's slot (null: zeros).
+template <int NA, bool DOT>
+__device__ __forceinline__ void nm_products(const double* const (&A)[NA], const double* col,
+                                            const double* dv, int n, int r0,
+                                            double (*red)[NM_W][256], double (*dsum)[16],
+                                            double* out_red, double* dot) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int row = rb * 4 + wid;
-  const bool mine = row < c.n && lane == 0;
-  double myr = 0.0, tr = 0.0, xir = 0.0, alr = 0.0, r0 = 1.0, yr = 0.0;
-  if (mine) {
-    myr = P.my[row];
-    tr = P.T[on + row];
-    xir = P.XI[on + row];
-    alr = P.AL[on + row];
-    r0 = P.R[on + row];
-    yr = P.y[row];
+  const int i = lane & 15, q = lane >> 4;
+  const int kper = (((n + NM_W - 1) / NM_W) + 15) & ~15;
+  const int kw0 = wid * kper, kw1 = min(n, kw0 + kper);
+  nm_acc_t acc[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) acc[a] = nm_acc_t{0.0, 0.0, 0.0, 0.0};
+  double dacc = 0.0;
+  const int row = r0 + i;
+  NmRegs<NA, DOT> cur, nxt;
+  if (kw0 < kw1) nm_load<NA, DOT>(A, col, dv, n, row, kw0 + 4 * q, kw1, cur);
+  for (int kb = kw0; kb < kw1; kb += 16) {
+    if (kb + 16 < kw1) nm_load<NA, DOT>(A, col, dv, n, row, kb + 16 + 4 * q, kw1, nxt);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+        acc[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.a[a][t], cur.b[t], acc[a], 0, 0, 0);
+      if constexpr (DOT) dacc = fma(cur.m[t], cur.b[t], dacc);
+    }
+    cur = nxt;
   }
-  const double sigma = sc->sigma;
-  const int kk = sc->k;
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < c.n; j += 256) acc = fma(P.my[j], x[j], acc);
-  double f = 0.0;
-  if (row < c.n) f = wave_row_dot(P.Minv + (size_t)row * c.n, x, c.n, lane);
-  const double beta_bar = -bsum<256>(acc) / c.ymy;
-  double ydr = 0.0;
-  int steps = 0;
-  if (mine) {
-    const double tolN = eps_k(c, kk) / sqrt((double)c.n);
-    const double s = f + beta_bar * myr;
-    const double v = s - tr;
-    const double cc = v + xir - alr / sigma;
-    const double rn = prox_newton(cc, sigma, r0, tolN, c, steps);
-    const double dr = rn - r0;
-    P.F[on + row] = f;
-    P.S[on + row] = s;
-    P.V[on + row] = v;
-    P.RN[on + row] = rn;
-    P.DR[on + row] = dr;
-    ydr = yr * dr;
-  }
-  if (lane == 0) {
-    wy[wid] = ydr;
-    ws[wid] = steps;
+  // D[i'][j'] of a 16 x 16 f64 MFMA sits in register i'/4 of lane j' + 16 (i' % 4)
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[a][wid][(4 * v + q) * 16 + i] = acc[a][v];
+  if constexpr (DOT) {
+    dacc += __shfl_xor(dacc, 16, 64);
+    dacc += __shfl_xor(dacc, 32, 64);
+    if (q == 0) dsum[wid][i] = dacc;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const size_t o = (size_t)pr * P.nb + rb;
-    P.part_n1[o] = (wy[0] + wy[1]) + (wy[2] + wy[3]);
-    P.part_it[o] = (double)max(max(ws[0], ws[1]), max(ws[2], ws[3]));
-    if (rb == 0) sc->beta_bar = beta_bar;
+  if (threadIdx.x < 256) {
+    const int e = threadIdx.x;
+    const int ti = e & 15, tj = e >> 4;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < NM_W; ++w) v += red[a][w][ti * 16 + tj];
+      out_red[a] = v;
+    }
+    if constexpr (DOT) {
+      double d = 0.0;
+#pragma unroll
+      for (int w = 0; w < NM_W; ++w) d += dsum[w][tj];
+      *dot = d;
+    }
+  }
+}
+
+// Sum (or max) over the 16 consecutive lanes that hold one slot's 16 rows.
+__device__ __forceinline__ double sum16(double v) {
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double max16(double v) {
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// The lane's B column (slot c0 + lane % 16), or null if the slot is empty or
+// its problem has stopped.
+__device__ __forceinline__ const double* nm_col(const BatchPtrs& P, const int* idx, int bact,
+                                                int c0, const double* base, int which) {
+  const int slot = c0 + (threadIdx.x & 15);
+  if (slot >= bact) return nullptr;
+  const int pr = idx[slot];
+  const Scal* sc = P.sc + pr;
+  if (sc->done) return nullptr;
+  if (which == 1) base = sc->redo ? P.AL1 : P.AL0;  // alpha of the chosen outcome
+  return base + (size_t)pr * P.n;
+}
+
+// ---------------------------------------------------------------------------
+// Steps 1a + 1b for every (row, problem) of the tile: f = M^-1 x, then
+// beta_bar = -m_y^T x / (y^T m_y), s, v and the prox (see k_step1ab).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NM_T) k_s1ab_mm(BatchPtrs P, const int* __restrict__ idx,
+                                                  int bact) {
+  int bx, by;
+  if (!nm_tile((P.n + 15) / 16, (bact + 15) / 16, bx, by)) return;
+  __shared__ double red[1][NM_W][256];
+  __shared__ double dsum[NM_W][16];
+  const int r0 = bx * 16, c0 = by * 16;
+  const double* A[1] = {P.Minv};
+  double f, mx;
+  nm_products<1, true>(A, nm_col(P, idx, bact, c0, P.XX, 0), P.my, P.n, r0, red, dsum, &f, &mx);
+  if (threadIdx.x >= 256) return;
+  const int e = threadIdx.x, row = r0 + (e & 15), slot = c0 + (e >> 4);
+  double ydr = 0.0, steps_d = 0.0;
+  int pr = -1;
+  bool live = false;
+  if (slot < bact) {
+    pr = idx[slot];
+    live = !P.sc[pr].done;
+  }
+  double beta_bar = 0.0;
+  if (live) {
+    Scal* sc = P.sc + pr;
+    const Consts c = P.cs[pr];
+    beta_bar = -mx / c.ymy;
+    if (row < c.n) {
+      const size_t on = (size_t)pr * P.n;
+      const double sigma = sc->sigma;
+      const double tolN = eps_k(c, sc->k) / sqrt((double)c.n);
+      const double s = f + beta_bar * P.my[row];
+      const double v = s - P.T[on + row];
+      const double cc = v + P.XI[on + row] - P.AL[on + row] / sigma;
+      const double r0v = P.R[on + row];
+      int steps = 0;
+      const double rn = prox_newton(cc, sigma, r0v, tolN, c, steps);
+      const double dr = rn - r0v;
+      P.F[on + row] = f;
+      P.S[on + row] = s;
+      P.V[on + row] = v;
+      P.RN[on + row] = rn;
+      P.DR[on + row] = dr;
+      ydr = P.y[row] * dr;
+      steps_d = (double)steps;
+    }
+  }
+  ydr = sum16(ydr);
+  steps_d = max16(steps_d);
+  if (live && (e & 15) == 0) {
+    const size_t o = (size_t)pr * P.nb + bx;
+    P.part_n1[o] = ydr;
+    P.part_it[o] = steps_d;
+    if (bx == 0) P.sc[pr].beta_bar = beta_bar;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Step 1c per (row, problem); see k_step1c_rows.
+// Step 1c for every (row, problem) of the tile: G~ dr and M^-1 dr, both
+// outcomes and their NPC partials (see k_step1c_rows).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_step1c_b(BatchPtrs P, const int* __restrict__ idx,
-                                                  int bact) {
-  int rb, slot;
-  rows_slot(blockIdx.x, bact, rb, slot);
-  if (rb >= P.nb) return;
-  const int pr = idx[slot];
-  Scal* sc = P.sc + pr;
-  if (sc->done) return;
-  const Consts c = P.cs[pr];
-  __shared__ double wsum[4][NPC];
-  const size_t on = (size_t)pr * P.n;
-  const double* drv = P.DR + on;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int row = rb * 4 + wid;
-  const bool mine = row < c.n && lane == 0;
-  double dr = 0.0, rn = 1.0, a0 = 0.0, yi = 0.0, xr = 0.0, pu = 0.0, s0 = 0.0, v0 = 0.0;
-  double f0 = 0.0, my0 = 0.0, t0 = 0.0;
-  if (mine) {
-    dr = drv[row];
-    rn = P.RN[on + row];
-    a0 = P.AL[on + row];
-    yi = P.y[row];
-    xr = P.XX[on + row];
-    pu = P.PU[on + row];
-    s0 = P.S[on + row];
-    v0 = P.V[on + row];
-    f0 = P.F[on + row];
-    my0 = P.my[row];
-    t0 = P.T[on + row];
+__global__ void __launch_bounds__(NM_T) k_s1c_mm(BatchPtrs P, const int* __restrict__ idx,
+                                                 int bact) {
+  int bx, by;
+  if (!nm_tile((P.n + 15) / 16, (bact + 15) / 16, bx, by)) return;
+  __shared__ double red[2][NM_W][256];
+  __shared__ double dsum[NM_W][16];
+  const int r0 = bx * 16, c0 = by * 16;
+  const double* A[2] = {P.G, P.Minv};
+  double hv[2], mdr;
+  nm_products<2, true>(A, nm_col(P, idx, bact, c0, P.DR, 0), P.my, P.n, r0, red, dsum, hv, &mdr);
+  if (threadIdx.x >= 256) return;
+  const int e = threadIdx.x, row = r0 + (e & 15), slot = c0 + (e >> 4);
+  int pr = -1;
+  bool live = false;
+  if (slot < bact) {
+    pr = idx[slot];
+    live = !P.sc[pr].done;
   }
-  const double sigma = sc->sigma;
-  const double beta_bar = sc->beta_bar;
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < c.n; j += 256) acc = fma(P.my[j], drv[j], acc);
-  double hg = 0.0, hm = 0.0;
-  if (row < c.n)
-    wave_row_dot2(P.G + (size_t)row * c.n, P.Minv + (size_t)row * c.n, drv, c.n, lane, hg, hm);
-  const double mdr = bsum<256>(acc);
-  const double beta1 = beta_bar + mdr / c.ymy;
   double out[NPC];
 #pragma unroll
   for (int j = 0; j < NPC; ++j) out[j] = 0.0;
-  if (mine) {
-    const double rq1 = pow_qp1(rn, c);
-    const double rq = pow_q(rn, c);
-    out[0] = dr * hg;
-    {
-      const double xi = fmax(0.0, rn - v0 + (a0 - c.C) / sigma);
-      const double pres = v0 + xi - rn;
-      const double a1 = a0 - c.tau * sigma * pres;
-      P.XI0[on + row] = xi;
-      P.AL0[on + row] = a1;
-      nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1);
-      out[1 + 9] = s0 * (c.mu * (xr + beta_bar * yi - s0));
-      out[1 + 10] = pu * s0;
-    }
-    {
-      const double s = f0 - hm + beta1 * my0;
-      const double v = s - (t0 - dr);
-      const double xi = fmax(0.0, rn - v + (a0 - c.C) / sigma);
-      const double pres = v + xi - rn;
-      const double a1 = a0 - c.tau * sigma * pres;
-      P.S1[on + row] = s;
-      P.V1[on + row] = v;
-      P.XI1[on + row] = xi;
-      P.AL1[on + row] = a1;
-      nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1 + NPO);
-      out[1 + NPO + 9] = s * (c.mu * (xr - dr + beta1 * yi - s));
-      out[1 + NPO + 10] = pu * s;
+  double beta1 = 0.0;
+  if (live) {
+    Scal* sc = P.sc + pr;
+    const Consts c = P.cs[pr];
+    const double beta_bar = sc->beta_bar;
+    beta1 = beta_bar + mdr / c.ymy;
+    if (row < c.n) {
+      const size_t on = (size_t)pr * P.n;
+      const double sigma = sc->sigma;
+      const double hg = hv[0], hm = hv[1];
+      const double dr = P.DR[on + row], rn = P.RN[on + row], a0 = P.AL[on + row];
+      const double yi = P.y[row], xr = P.XX[on + row], pu = P.PU[on + row];
+      const double s0 = P.S[on + row], v0 = P.V[on + row], f0 = P.F[on + row];
+      const double my0 = P.my[row], t0 = P.T[on + row];
+      const double rq1 = pow_qp1(rn, c);
+      const double rq = pow_q(rn, c);
+      out[0] = dr * hg;
+      {
+        const double xi = fmax(0.0, rn - v0 + (a0 - c.C) / sigma);
+        const double pres = v0 + xi - rn;
+        const double a1 = a0 - c.tau * sigma * pres;
+        P.XI0[on + row] = xi;
+        P.AL0[on + row] = a1;
+        nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1);
+        out[1 + 9] = s0 * (c.mu * (xr + beta_bar * yi - s0));
+        out[1 + 10] = pu * s0;
+      }
+      {
+        const double s = f0 - hm + beta1 * my0;
+        const double v = s - (t0 - dr);
+        const double xi = fmax(0.0, rn - v + (a0 - c.C) / sigma);
+        const double pres = v + xi - rn;
+        const double a1 = a0 - c.tau * sigma * pres;
+        P.S1[on + row] = s;
+        P.V1[on + row] = v;
+        P.XI1[on + row] = xi;
+        P.AL1[on + row] = a1;
+        nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1 + NPO);
+        out[1 + NPO + 9] = s * (c.mu * (xr - dr + beta1 * yi - s));
+        out[1 + NPO + 10] = pu * s;
+      }
     }
   }
-  if (lane == 0) {
 #pragma unroll
-    for (int j = 0; j < NPC; ++j) wsum[wid][j] = out[j];
+  for (int j = 0; j < NPC; ++j) out[j] = sum16(out[j]);
+  if (live && (e & 15) == 0) {
+    double* dst = P.part_c + ((size_t)pr * P.nb + bx) * NPC;
+#pragma unroll
+    for (int j = 0; j < NPC; ++j) dst[j] = out[j];
+    if (bx == 0) P.sc[pr].beta1 = beta1;
   }
-  __syncthreads();
-  if (threadIdx.x < NPC) {
-    const int j = threadIdx.x;
-    P.part_c[((size_t)pr * P.nb + rb) * NPC + j] =
-        (wsum[0][j] + wsum[1][j]) + (wsum[2][j] + wsum[3][j]);
-  }
-  if (rb == 0 && threadIdx.x == 0) sc->beta1 = beta1;
 }
 
 // ---------------------------------------------------------------------------
@@ -267,11 +375,13 @@ __global__ void __launch_bounds__(256) k_plan_b(BatchPtrs P, const int* __restri
 // 2-3:  g = w - rho/(sigma sqrt(mu)), u = gamma g,
 // rho -= tau sigma sqrt(mu)(w - u), and per-problem block partials (NP2
 // layout of the single pass; the two Z~ alpha entries are 0 here: the batched
-// tail gets them in n-space).  Block tile: 256 rows x 64 slots, 8 waves, wave
-// w owns rows 32w..32w+31; the next K tile is loaded into registers while the
-// current one is multiplied.
+// tail gets them in n-space).  Block tile: 256 rows x 16 NB slots, 8 waves,
+// wave w owns rows 32w..32w+31; the next K tile is loaded into registers
+// while the current one is multiplied.  Every output element is the same
+// sequence of MFMA steps over k whatever NB is, so the tile width (chosen by
+// the host's tuner) does not change any result.
 // ---------------------------------------------------------------------------
-constexpr int BT_M = 256, BT_N = 64, BT_K = 16, BT_T = 512;
+constexpr int BT_M = 256, BT_K = 16, BT_T = 512;
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v_b __attribute__((ext_vector_type(4)));
@@ -297,17 +407,18 @@ struct MfmaB<double> {
 };
 
 // Global loads of one K tile into registers: A is 256 rows x 16 columns of X
-// (2 four-element row segments per thread), B is 16 x 64 of SB (2 per thread).
-template <typename TD>
+// (2 four-element row segments per thread), B is 16 x 16 NB of SB.
+template <typename TD, int NB>
 struct TileRegs {
+  static constexpr int NBL = (16 * 16 * NB + BT_T - 1) / BT_T;  // B elements per thread
   TD a[2][4];
-  double b[2];
+  double b[NBL];
 };
 
-template <typename TD>
+template <typename TD, int NB>
 __device__ __forceinline__ void tile_load(const TD* __restrict__ X, const double* __restrict__ SB,
                                           int64_t ld, int n, int64_t m0, int k0, int bact_tile,
-                                          TileRegs<TD>& R) {
+                                          TileRegs<TD, NB>& R) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -317,14 +428,14 @@ __device__ __forceinline__ void tile_load(const TD* __restrict__ X, const double
     if (k < n) {
       const TD* src = X + (int64_t)k * ld + m0 + r4;
       if constexpr (sizeof(TD) == 4) {
-        const float4 v = *reinterpret_cast<const float4*>(src);
+        const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(src));
         R.a[h][0] = v.x;
         R.a[h][1] = v.y;
         R.a[h][2] = v.z;
         R.a[h][3] = v.w;
       } else {
-        const double2 v0 = *reinterpret_cast<const double2*>(src);
-        const double2 v1 = *reinterpret_cast<const double2*>(src + 2);
+        const nt_d2 v0 = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(src));
+        const nt_d2 v1 = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(src + 2));
         R.a[h][0] = v0.x;
         R.a[h][1] = v0.y;
         R.a[h][2] = v1.x;
@@ -334,16 +445,20 @@ __device__ __forceinline__ void tile_load(const TD* __restrict__ X, const double
 #pragma unroll
       for (int q = 0; q < 4; ++q) R.a[h][q] = (TD)0;
     }
+  }
+#pragma unroll
+  for (int h = 0; h < TileRegs<TD, NB>::NBL; ++h) {
     // B: slot j = e / 16, kk = e % 16 (16 consecutive k of one slot)
+    const int e = tid + h * BT_T;
     const int j = e >> 4, kb = e & 15;
     const int kq = k0 + kb;
-    R.b[h] = (j < bact_tile && kq < n) ? SB[(size_t)j * n + kq] : 0.0;
+    R.b[h] = (e < 16 * 16 * NB && j < bact_tile && kq < n) ? SB[(size_t)j * n + kq] : 0.0;
   }
 }
 
-template <typename TD, typename T>
-__device__ __forceinline__ void tile_store(const TileRegs<TD>& R, T (*As)[BT_M + 4],
-                                           T (*Bs)[BT_N + 4]) {
+template <typename TD, typename T, int NB>
+__device__ __forceinline__ void tile_store(const TileRegs<TD, NB>& R, T (*As)[BT_M + 4],
+                                           T (*Bs)[16 * NB + 4]) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -351,28 +466,36 @@ __device__ __forceinline__ void tile_store(const TileRegs<TD>& R, T (*As)[BT_M +
     const int kk = e >> 6, r4 = (e & 63) * 4;
 #pragma unroll
     for (int q = 0; q < 4; ++q) As[kk][r4 + q] = (T)R.a[h][q];
-    const int j = e >> 4, kb = e & 15;
-    Bs[kb][j] = (T)R.b[h];
+  }
+#pragma unroll
+  for (int h = 0; h < TileRegs<TD, NB>::NBL; ++h) {
+    const int e = tid + h * BT_T;
+    if (e < 16 * 16 * NB) Bs[e & 15][e >> 4] = (T)R.b[h];
   }
 }
 
-template <typename TD, typename T>
+// FP64 products (T = double) accumulate in the MFMA registers over the whole
+// inner dimension; FP32 products (T = float) are summed per K tile and the
+// tile sums added in FP64.
+template <typename TD, typename T, int NB>
 __global__ void __launch_bounds__(BT_T) k_pass_b(const TD* __restrict__ X, BatchPtrs P,
                                                  const int* __restrict__ idx, int bact) {
   typedef typename MfmaB<T>::acc_t acc_t;
+  constexpr int BN = 16 * NB;
+  constexpr bool F64 = sizeof(T) == 8;
   __shared__ T As[BT_K][BT_M + 4];
-  __shared__ T Bs[BT_K][BT_N + 4];
-  __shared__ double red[8][BT_N][NP2];
-  __shared__ int s_p[BT_N];
-  __shared__ int s_live[BT_N];
-  __shared__ double s_sig[BT_N], s_gam[BT_N], s_tau[BT_N];
+  __shared__ T Bs[BT_K][BN + 4];
+  __shared__ double red[8][BN][NP2];
+  __shared__ int s_p[BN];
+  __shared__ int s_live[BN];
+  __shared__ double s_sig[BN], s_gam[BN], s_tau[BN];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int64_t m0 = (int64_t)blockIdx.x * BT_M;
-  const int slot0 = blockIdx.y * BT_N;
-  const int bact_tile = min(BT_N, bact - slot0);
+  const int slot0 = blockIdx.y * BN;
+  const int bact_tile = min(BN, bact - slot0);
   const int n = P.n;
   const double* SB = P.SB + (size_t)slot0 * n;
-  if (tid < BT_N) {
+  if (tid < BN) {
     const int slot = slot0 + tid;
     int p = -1, live = 0;
     if (tid < bact_tile) {
@@ -388,51 +511,63 @@ __global__ void __launch_bounds__(BT_T) k_pass_b(const TD* __restrict__ X, Batch
       s_tau[tid] = P.cs[p].tau;
     }
   }
-  double acc64[2][4][4];
+  acc_t acc[2][NB];
+  double acc64[F64 ? 1 : 2][F64 ? 1 : NB][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc64[a][b][v] = 0.0;
-  TileRegs<TD> R;
-  tile_load<TD>(X, SB, P.ld, n, m0, 0, bact_tile, R);
-  for (int k0 = 0; k0 < n; k0 += BT_K) {
-    tile_store<TD, T>(R, As, Bs);
-    __syncthreads();
-    if (k0 + BT_K < n) tile_load<TD>(X, SB, P.ld, n, m0, k0 + BT_K, bact_tile, R);
-    acc_t acc[2][4];
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = (T)0;
+  if constexpr (!F64) {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[a][b][v] = (T)0;
-#pragma unroll
-    for (int ks = 0; ks < BT_K; ks += 4) {
-      const int li = lane & 15, lk = lane >> 4;
-      T av[2], bv[4];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[ks + lk][wid * 32 + a * 16 + li];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[ks + lk][b * 16 + li];
+        for (int v = 0; v < 4; ++v) acc64[a][b][v] = 0.0;
+  }
+  TileRegs<TD, NB> R;
+  tile_load<TD, NB>(X, SB, P.ld, n, m0, 0, bact_tile, R);
+  for (int k0 = 0; k0 < n; k0 += BT_K) {
+    tile_store<TD, T, NB>(R, As, Bs);
+    __syncthreads();
+    if (k0 + BT_K < n) tile_load<TD, NB>(X, SB, P.ld, n, m0, k0 + BT_K, bact_tile, R);
+    if constexpr (!F64) {
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = MfmaB<T>::op(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[a][b][v] = (T)0;
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int ks = 0; ks < BT_K; ks += 4) {
+      const int li = lane & 15, lk = lane >> 4;
+      T av[2], bv[NB];
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int a = 0; a < 2; ++a) av[a] = As[ks + lk][wid * 32 + a * 16 + li];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc64[a][b][v] += (double)acc[a][b][v];
+      for (int b = 0; b < NB; ++b) bv[b] = Bs[ks + lk][b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = MfmaB<T>::op(av[a], bv[b], acc[a][b]);
+    }
+    if constexpr (!F64) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc64[a][b][v] += (double)acc[a][b][v];
+    }
     __syncthreads();
   }
   const double mu = P.cs[s_p[0] >= 0 ? s_p[0] : 0].mu;
   const double sqmu = sqrt(mu);
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < NB; ++b) {
     const int j = b * 16 + (lane & 15);
     const int p = s_p[j];
     const bool live = s_live[j] != 0;
@@ -447,7 +582,11 @@ __global__ void __launch_bounds__(BT_T) k_pass_b(const TD* __restrict__ X, Batch
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t k = m0 + wid * 32 + a * 16 + MfmaB<T>::row(lane, v);
-          const double zs = acc64[a][b][v];
+          double zs;
+          if constexpr (F64)
+            zs = acc[a][b][v];
+          else
+            zs = acc64[a][b][v];
           const double rho = P.RHO[od + k];
           const double bb = mu * P.U[od + k] + br * rho;
           const double w = (bb - zs) / mu;
@@ -473,7 +612,7 @@ __global__ void __launch_bounds__(BT_T) k_pass_b(const TD* __restrict__ X, Batch
     }
   }
   __syncthreads();
-  for (int e = tid; e < BT_N * NP2; e += BT_T) {
+  for (int e = tid; e < BN * NP2; e += BT_T) {
     const int j = e / NP2, q = e % NP2;
     if (!s_live[j]) continue;
     double v = 0.0;
@@ -484,35 +623,37 @@ __global__ void __launch_bounds__(BT_T) k_pass_b(const TD* __restrict__ X, Batch
 }
 
 // ---------------------------------------------------------------------------
-// G~ alpha^{k+1} per (row, problem), with block partials of alpha^T G~ alpha,
-// for ||Z~ alpha||^2 (dual objective) and ||Z~ alpha + D rho||^2 (eta_D3).
+// G~ alpha^{k+1} for every (row, problem) of the tile, with the partials of
+// alpha^T G~ alpha for ||Z~ alpha||^2 (dual objective) and
+// ||Z~ alpha + D rho||^2 (eta_D3).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_galpha_b(BatchPtrs P, const int* __restrict__ idx,
-                                                  int bact) {
-  int rb, slot;
-  rows_slot(blockIdx.x, bact, rb, slot);
-  if (rb >= P.nb) return;
-  const int pr = idx[slot];
-  Scal* sc = P.sc + pr;
-  if (sc->done) return;
-  __shared__ double wsum[4];
-  const size_t on = (size_t)pr * P.n;
-  const double* al = (sc->redo ? P.AL1 : P.AL0) + on;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int row = rb * 4 + wid;
-  double h = 0.0;
-  if (row < P.n) h = wave_row_dot(P.G + (size_t)row * P.n, al, P.n, lane);
-  if (lane == 0) {
-    double contrib = 0.0;
-    if (row < P.n) {
-      P.HA[on + row] = h;
-      contrib = al[row] * h;
-    }
-    wsum[wid] = contrib;
+__global__ void __launch_bounds__(NM_T) k_ga_mm(BatchPtrs P, const int* __restrict__ idx,
+                                                int bact) {
+  int bx, by;
+  if (!nm_tile((P.n + 15) / 16, (bact + 15) / 16, bx, by)) return;
+  __shared__ double red[1][NM_W][256];
+  const int r0 = bx * 16, c0 = by * 16;
+  const double* A[1] = {P.G};
+  double h;
+  nm_products<1, false>(A, nm_col(P, idx, bact, c0, nullptr, 1), nullptr, P.n, r0, red, nullptr,
+                        &h, nullptr);
+  if (threadIdx.x >= 256) return;
+  const int e = threadIdx.x, row = r0 + (e & 15), slot = c0 + (e >> 4);
+  int pr = -1;
+  bool live = false;
+  if (slot < bact) {
+    pr = idx[slot];
+    live = !P.sc[pr].done;
   }
-  __syncthreads();
-  if (threadIdx.x == 0)
-    P.part_ga[(size_t)pr * P.nb + rb] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+  double contrib = 0.0;
+  if (live && row < P.n) {
+    const size_t on = (size_t)pr * P.n;
+    const double* al = (P.sc[pr].redo ? P.AL1 : P.AL0) + on;
+    P.HA[on + row] = h;
+    contrib = al[row] * h;
+  }
+  contrib = sum16(contrib);
+  if (live && (e & 15) == 0) P.part_ga[(size_t)pr * P.nb + bx] = contrib;
 }
 
 // ---------------------------------------------------------------------------
@@ -646,28 +787,48 @@ bool batch_ptrs_ok(const BatchPtrs& P) {
   return P.ld % kLdAlign == 0;
 }
 
+// The pass with a tile of 16 * tile slots per block (tile = 1, 2 or 4).
+template <int NB>
+static void pass_b_nb(const void* X, int storage, int fp64_mfma, const BatchPtrs& P,
+                      const int* idx, int bact, hipStream_t st) {
+  const dim3 gp((unsigned)(P.ld / BT_M), (bact + 16 * NB - 1) / (16 * NB));
+  if (storage == DWD_FP32 && !fp64_mfma)
+    hipLaunchKernelGGL((k_pass_b<float, float, NB>), gp, dim3(BT_T), 0, st, (const float*)X, P,
+                       idx, bact);
+  else if (storage == DWD_FP32)
+    hipLaunchKernelGGL((k_pass_b<float, double, NB>), gp, dim3(BT_T), 0, st, (const float*)X, P,
+                       idx, bact);
+  else
+    hipLaunchKernelGGL((k_pass_b<double, double, NB>), gp, dim3(BT_T), 0, st, (const double*)X,
+                       P, idx, bact);
+}
+
+hipError_t launch_pass_b(const void* X, int storage, int fp64_mfma, const BatchPtrs& P,
+                         const int* idx, int bact, int tile, hipStream_t st) {
+  switch (tile) {
+    case 1: pass_b_nb<1>(X, storage, fp64_mfma, P, idx, bact, st); break;
+    case 2: pass_b_nb<2>(X, storage, fp64_mfma, P, idx, bact, st); break;
+    case 4: pass_b_nb<4>(X, storage, fp64_mfma, P, idx, bact, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, const BatchPtrs& P,
-                                  const int* idx, int bact, hipStream_t st, hipEvent_t ev0,
-                                  hipEvent_t ev1) {
+                                  const int* idx, int bact, int tile, hipStream_t st,
+                                  hipEvent_t ev0, hipEvent_t ev1) {
   if (!X || !idx || bact < 1 || !batch_ptrs_ok(P)) return hipErrorInvalidValue;
   if (storage != DWD_FP32 && storage != DWD_FP64) return hipErrorInvalidValue;
-  const dim3 grow(batch_row_grid(P.nb, bact));
-  hipLaunchKernelGGL(k_step1ab_b, grow, dim3(256), 0, st, P, idx, bact);
-  hipLaunchKernelGGL(k_step1c_b, grow, dim3(256), 0, st, P, idx, bact);
+  if (P.nb != (P.n + 15) / 16) return hipErrorInvalidValue;
+  const dim3 gnm(nm_grid(P.n, bact));
+  hipLaunchKernelGGL(k_s1ab_mm, gnm, dim3(NM_T), 0, st, P, idx, bact);
+  hipLaunchKernelGGL(k_s1c_mm, gnm, dim3(NM_T), 0, st, P, idx, bact);
   hipLaunchKernelGGL(k_plan_b, dim3(bact), dim3(256), 0, st, P, idx);
-  const dim3 gp((unsigned)(P.ld / BT_M), (bact + BT_N - 1) / BT_N);
   if (ev0) (void)hipEventRecord(ev0, st);
-  if (storage == DWD_FP32 && !fp64_mfma)
-    hipLaunchKernelGGL((k_pass_b<float, float>), gp, dim3(BT_T), 0, st, (const float*)X, P, idx,
-                       bact);
-  else if (storage == DWD_FP32)
-    hipLaunchKernelGGL((k_pass_b<float, double>), gp, dim3(BT_T), 0, st, (const float*)X, P, idx,
-                       bact);
-  else
-    hipLaunchKernelGGL((k_pass_b<double, double>), gp, dim3(BT_T), 0, st, (const double*)X, P,
-                       idx, bact);
+  hipError_t e = launch_pass_b(X, storage, fp64_mfma, P, idx, bact, tile, st);
+  if (e != hipSuccess) return e;
   if (ev1) (void)hipEventRecord(ev1, st);
-  hipLaunchKernelGGL(k_galpha_b, grow, dim3(256), 0, st, P, idx, bact);
+  hipLaunchKernelGGL(k_ga_mm, gnm, dim3(NM_T), 0, st, P, idx, bact);
   hipLaunchKernelGGL(k_tail_b, dim3(bact), dim3(NTB), 0, st, P, idx);
   return hipGetLastError();
 }

@@ -44,7 +44,7 @@ class Params(C.Structure):
                 ("mu", C.c_double), ("sigma0", C.c_double), ("eps_c", C.c_double),
                 ("rho_residual", C.c_int32), ("resync", C.c_int32), ("check_every", C.c_int32),
                 ("refine", C.c_int32), ("lowp_tol", C.c_double), ("profile", C.c_int32),
-                ("batch_fp32", C.c_int32)]
+                ("batch_fp32", C.c_int32), ("batch_tile", C.c_int32), ("graph", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -57,7 +57,7 @@ class Info(C.Structure):
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("stream_ms", C.c_double),
                 ("stream_launches", C.c_int32), ("resumed", C.c_int32),
                 ("streamT_ms", C.c_double), ("streamT_launches", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("graph_launches", C.c_int32)]
 
     def to_dict(self) -> Dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}

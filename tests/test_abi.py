@@ -42,12 +42,37 @@ def test_default_params(D):
     assert p.eps_c < 0 and p.sigma0 == 0.0 and p.rho_residual == 1
 
 
-def test_struct_sizes_match_header_layout(D):
-    # field offsets follow the C declaration order with natural alignment
-    assert C.sizeof(D.Matrix) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4
-    assert C.sizeof(D.Params) == 3 * 8 + 4 + 4 + 4 * 8 + 4 * 4 + 8 + 4 + 4
-    assert D.params().batch_fp32 == 0
-    assert C.sizeof(D.Info) == 11 * 8 + 6 * 4 + 3 * 8 + 2 * 4 + 8 + 2 * 4
+def test_struct_layouts_match_the_header(D, tmp_path):
+    """Compile a probe against include/dwd.h and compare every field offset
+    and struct size with the ctypes binding."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    pairs = [(D.Matrix, "dwd_matrix"), (D.Params, "dwd_params"), (D.Info, "dwd_info"),
+             (D.Request, "dwd_request"), (D.ServeOpts, "dwd_serve_opts"),
+             (D.Response, "dwd_response")]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "dwd.h"', "int main(void) {"]
+    for cls, cname in pairs:
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for ln in out.splitlines():
+        cname, field, val = ln.split()
+        got[(cname, field)] = int(val)
+    for cls, cname in pairs:
+        assert C.sizeof(cls) == got[(cname, "sizeof")], cname
+        for fname, _ in cls._fields_:
+            assert getattr(cls, fname).offset == got[(cname, fname)], (cname, fname)
+    assert D.params().batch_fp32 == 0 and D.params().batch_tile == 0 and D.params().graph == 1
 
 
 def test_status_strings(D):

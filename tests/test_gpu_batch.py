@@ -97,3 +97,33 @@ def test_batch_sweep_full_size(dwd):
         assert i["kkt_check"] <= 2e-5, i
     assert np.all(np.isfinite(res["W"]))
     P.close()
+
+
+def test_batch_tile_widths_and_graph_replay_are_bit_identical(dwd):
+    """Every tile width of the batched pass runs the same MFMA sequence per
+    output element, and a graph-replayed chunk runs the same kernels as eager
+    launches: W, beta and the iteration counts must agree bit for bit.  The
+    graph case is solved twice (every chunk is replayed many times, with the
+    host's own copies and waits between replays)."""
+    X, y = synth.random_two_class(6000, 150, seed=21, mean=0.5, dtype="f32")
+    grid = [(C, q) for C in (0.1, 1.0, 10.0) for q in (1.0, 2.0)] + [(0.5, 0.5), (2.0, 4.0)]
+    P = dwd.Problem(X, y, storage="f32")
+    runs = {}
+    for tile in (1, 2, 4):
+        for graph in (0, 1):
+            r = P.solve_batch([dict(C=C, q=q, tol=1e-6, batch_tile=tile, graph=graph)
+                               for C, q in grid])
+            runs[(tile, graph)] = r
+    again = P.solve_batch([dict(C=C, q=q, tol=1e-6, batch_tile=2, graph=1) for C, q in grid])
+    ref = runs[(4, 0)]
+    assert all(i["converged"] == 1 for i in ref["info"])
+    assert ref["info"][0]["graph_launches"] == 0
+    assert runs[(2, 1)]["info"][0]["graph_launches"] > 0
+    for key, r in list(runs.items()) + [("again", again)]:
+        assert np.array_equal(r["W"], ref["W"]), key
+        for a, b in zip(r["info"], ref["info"]):
+            assert a["iters"] == b["iters"] and a["beta"] == b["beta"], key
+    # the tuned default agrees as well
+    auto = P.solve_batch([dict(C=C, q=q, tol=1e-6) for C, q in grid])
+    assert np.array_equal(auto["W"], ref["W"])
+    P.close()
