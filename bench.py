@@ -138,9 +138,11 @@ def batched_leg(dwd, Xd, y, tol, grid):
         "kkt_check_max_plain": max(p["info"]["kkt_check"] for p in plain),
         "max_rel_w_diff_batched_vs_plain": wdiff,
         "iters_max": max(i["iters"] for i in ib), "iters_sum": it_total,
-        "mfma": {"kernel": "k_pass_b<float,double> (Z~ [s_1..s_B], FP64 MFMA)",
-                 "achieved": achieved, "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
-                 "frac": (achieved / FP64_MFMA_PEAK_TFS) if achieved else None,
+        "resumed": sum(i["resumed"] for i in ib),
+        "mfma": {"kernel": "k_pass_b<float,float,NB> (Z~ [s_1..s_B], FP32 MFMA, FP64 sums over "
+                           "K tiles; resumed problems continue on the FP64 MFMA variant)",
+                 "achieved": achieved, "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                 "frac": (achieved / FP32_MFMA_PEAK_TFS) if achieved else None,
                  "flops": flops, "pass_ms": ib[0]["stream_ms"],
                  "launches": ib[0]["stream_launches"]},
     }

@@ -91,9 +91,12 @@ typedef struct {
   double lowp_tol;   /* BF16 storage: tolerance of the BF16 phase; <= 0: 30*tol */
   int32_t profile;   /* 1: time the Z-streaming kernels with HIP events
                         (dwd_solve_batch reads it from p[0])                    */
-  int32_t batch_fp32; /* dwd_solve_batch: 1 = FP32 MFMA products (FP64 sums
-                        across K tiles, relative error ~1e-7 per pass, checked
-                        and refined in FP64 at the end); 0 = FP64 MFMA (default) */
+  int32_t batch_fp32; /* dwd_solve_batch: 1 (default) = FP32 MFMA products when
+                        every tol >= 1e-5 (FP64 sums across K tiles, relative
+                        error ~1e-7 per pass; each problem is then checked in
+                        FP64 and, if the check misses tol, resumed from
+                        re-anchored n-space state with FP64 products);
+                        0 = FP64 MFMA products throughout                     */
   int32_t batch_tile; /* dwd_solve_batch: slots per block of the Z~ [s_1..s_B]
                         product, in units of 16: 1, 2 or 4; 0 (default) = chosen
                         per active-slot count by timing the candidates on the

@@ -715,7 +715,7 @@ void dwd_default_params(dwd_params* p) {
   p->refine = 1;
   p->lowp_tol = 0.0;
   p->profile = 0;
-  p->batch_fp32 = 0;
+  p->batch_fp32 = 1;
   p->batch_tile = 0;
   p->graph = 1;
 }

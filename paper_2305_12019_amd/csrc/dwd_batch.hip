@@ -209,14 +209,15 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   HIP_TRY_B(bb.halloc((void**)&hsc[1], (size_t)B * sizeof(Scal)));
   Consts* hcs = nullptr;
   HIP_TRY_B(bb.halloc((void**)&hcs, (size_t)B * sizeof(Consts)));
-  // FP64 MFMA products by default.  FP32 MFMA (opt-in; FP64 sums across K
-  // tiles) carries a relative error of about 1e-7 per pass, which the n-space
-  // recurrences of Z~^T u and Z~^T rho accumulate; the final FP64 check and the
-  // re-anchored FP64 resume below repair that.
+  // FP32 MFMA products (FP64 sums across K tiles) when every problem asks
+  // for tol >= 1e-5 and none opts out; they carry a relative error of about
+  // 1e-7 per pass, which the n-space recurrences of Z~^T u and Z~^T rho
+  // accumulate; the final FP64 check and the re-anchored FP64 resume below
+  // repair that.  Otherwise FP64 MFMA products.
   int max_iter = 1;
-  int fp64_mfma = 1;
+  int fp64_mfma = 0;
   for (int j = 0; j < B; ++j) {
-    if (p[j].batch_fp32 && p[j].tol >= 1e-6) fp64_mfma = 0;
+    if (!p[j].batch_fp32 || p[j].tol < 1e-5) fp64_mfma = 1;
     hcs[j] = make_consts(P, &p[j]);
     hcs[j].sigma0 = default_sigma0(&p[j], n);
     max_iter = std::max(max_iter, p[j].max_iter);

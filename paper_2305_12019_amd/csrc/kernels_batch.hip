@@ -478,7 +478,8 @@ __device__ __forceinline__ void tile_store(const TileRegs<TD, NB>& R, T (*As)[BT
 // inner dimension; FP32 products (T = float) are summed per K tile and the
 // tile sums added in FP64.
 template <typename TD, typename T, int NB>
-__global__ void __launch_bounds__(BT_T) k_pass_b(const TD* __restrict__ X, BatchPtrs P,
+__global__ void __launch_bounds__(BT_T) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 2 : 4)))
+k_pass_b(const TD* __restrict__ X, BatchPtrs P,
                                                  const int* __restrict__ idx, int bact) {
   typedef typename MfmaB<T>::acc_t acc_t;
   constexpr int BN = 16 * NB;
@@ -527,12 +528,14 @@ __global__ void __launch_bounds__(BT_T) k_pass_b(const TD* __restrict__ X, Batch
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc64[a][b][v] = 0.0;
   }
-  TileRegs<TD, NB> R;
-  tile_load<TD, NB>(X, SB, P.ld, n, m0, 0, bact_tile, R);
-  for (int k0 = 0; k0 < n; k0 += BT_K) {
+  // Two K tiles in flight in registers while the staged one is multiplied.
+  TileRegs<TD, NB> R0, R1;
+  tile_load<TD, NB>(X, SB, P.ld, n, m0, 0, bact_tile, R0);
+  if (BT_K < n) tile_load<TD, NB>(X, SB, P.ld, n, m0, BT_K, bact_tile, R1);
+  auto step = [&](TileRegs<TD, NB>& R, int k0) {
     tile_store<TD, T, NB>(R, As, Bs);
     __syncthreads();
-    if (k0 + BT_K < n) tile_load<TD, NB>(X, SB, P.ld, n, m0, k0 + BT_K, bact_tile, R);
+    if (k0 + 2 * BT_K < n) tile_load<TD, NB>(X, SB, P.ld, n, m0, k0 + 2 * BT_K, bact_tile, R);
     if constexpr (!F64) {
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -563,6 +566,10 @@ __global__ void __launch_bounds__(BT_T) k_pass_b(const TD* __restrict__ X, Batch
           for (int v = 0; v < 4; ++v) acc64[a][b][v] += (double)acc[a][b][v];
     }
     __syncthreads();
+  };
+  for (int k0 = 0; k0 < n; k0 += 2 * BT_K) {
+    step(R0, k0);
+    if (k0 + BT_K < n) step(R1, k0 + BT_K);
   }
   const double mu = P.cs[s_p[0] >= 0 ? s_p[0] : 0].mu;
   const double sqmu = sqrt(mu);

@@ -72,7 +72,7 @@ def test_struct_layouts_match_the_header(D, tmp_path):
         assert C.sizeof(cls) == got[(cname, "sizeof")], cname
         for fname, _ in cls._fields_:
             assert getattr(cls, fname).offset == got[(cname, fname)], (cname, fname)
-    assert D.params().batch_fp32 == 0 and D.params().batch_tile == 0 and D.params().graph == 1
+    assert D.params().batch_fp32 == 1 and D.params().batch_tile == 0 and D.params().graph == 1
 
 
 def test_status_strings(D):
