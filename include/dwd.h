@@ -87,7 +87,9 @@ typedef struct {
                         default 0: only at the start, otherwise carried by exact
                         n-space recurrences and verified by the final check   */
   int32_t check_every; /* iterations queued between host reads of the stop flag */
-  int32_t refine;    /* BF16 storage: continue on FP32 data until tol is met    */
+  int32_t refine;    /* BF16 storage: continue on FP32 data until tol is met;
+                        0: stop after the BF16 phase (the final FP64 check then
+                        only reports the residual against the data of record) */
   double lowp_tol;   /* BF16 storage: tolerance of the BF16 phase; <= 0: 30*tol */
   int32_t profile;   /* 1: time the Z-streaming kernels with HIP events
                         (dwd_solve_batch reads it from p[0])                    */
@@ -106,6 +108,10 @@ typedef struct {
                         check_every iterations as a captured hipGraph once the
                         tile is fixed (not with profile = 1); 0 = launch each
                         kernel.  Results are identical either way.             */
+  int32_t sigma_every; /* apply the sigma rule of Section 4.4 after every
+                        sigma_every-th iteration (the paper gives no cadence);
+                        default 2 (1 = every iteration)                        */
+  int32_t reserved_p;
 } dwd_params;
 
 /* Per-solve report.  Residuals are those of Section 4.3 on the scaled

@@ -398,7 +398,7 @@ def default_sigma0(C, q, n):
 def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
           sigma0: Optional[float] = None, eps_c: Optional[float] = None,
           record: bool = False, start: Optional[Dict] = None,
-          scale: bool = True, rho_residual: bool = True) -> Dict:
+          scale: bool = True, rho_residual: bool = True, sigma_every: int = 2) -> Dict:
     """Run Algorithm 1 on eq-gen-scale and return the unscaled solution.
 
     ``X`` has shape (n, d) (row i = sample x_i), ``y`` is +-1.  Returns a dict
@@ -408,7 +408,10 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
     residuals ``eta`` and ``converged``.  ``start`` may hold a previous
     result's scaled state to resume from.  ``scale=False`` skips the data
     scaling of Section 4.2 (Z_scale = 1), for the check that scaling does
-    not change the solution.
+    not change the solution.  ``sigma_every``: the sigma rule of Section 4.4
+    is applied after iterations whose count is a multiple of it (the paper
+    gives no cadence; the default reading is every second iteration, 1 =
+    every iteration).
     """
     y = np.asarray(y, dtype=np.float64)
     if scale:
@@ -477,7 +480,8 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
             converged = True
             break
         # Section 4.4
-        sigma = sigma_update(sigma, e["P"], e["D"])
+        if (k + 1) % sigma_every == 0:
+            sigma = sigma_update(sigma, e["P"], e["D"])
     return dict(w=w / zscale, u=u / zscale, beta=float(beta), r=r, xi=xi, alpha=alpha,
                 w_scaled=w, u_scaled=u, rho=rho, sigma=sigma, zscale=zscale,
                 iters=it, n_double=n_double, newton_max=newton_max, eta=e,

@@ -50,7 +50,8 @@ int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz
   if (layout == DWD_CSR) b = 2 * nnz * (4 + (storage == DWD_FP64 ? 8 : 4)) + (n + d + 2) * 8;
   const int64_t nn = (int64_t)n * n * 8;
   b += 2 * nn;                                          // G~, M^-1
-  b += (int64_t)n * 8 * 24 + ld * 8 * 4;                // vectors
+  if (storage == DWD_BF16 && layout != DWD_CSR) b += 2 * nn + (int64_t)n * 8;  // BF16 factor
+  b += (int64_t)n * 8 * 24 + ld * 8 * 3;                // vectors
   b += (ld / kLdAlign) * 2 * (int64_t)n * 8;            // pass partials
   const int splits = gram_splits(ld, n);
   b += std::max<int64_t>((int64_t)splits * nn, nn);     // set-up scratch (Gram / inverse)
@@ -74,6 +75,7 @@ dwd_status validate_params(const dwd_params* p, bool for_solve) {
     return fail(DWD_E_INVALID, "sigma0 and eps_c must be finite");
   if (p->batch_tile != 0 && p->batch_tile != 1 && p->batch_tile != 2 && p->batch_tile != 4)
     return fail(DWD_E_INVALID, "batch_tile must be 0, 1, 2 or 4");
+  if (p->sigma_every < 1) return fail(DWD_E_INVALID, "sigma_every must be >= 1");
   return DWD_OK;
 }
 
@@ -326,39 +328,52 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   if (!(frob2 > 0.0)) return cleanup(fail(DWD_E_INVALID, "X is all zero"));
   P->zscale = sqrt(sqrt(frob2));  // Z_scale = sqrt(||X||_F)
 
-  // a1: Gram G~ and M = I + G~/mu
+  // a1-a2: Gram G~ = Z~^T Z~ of the streamed image, M = I + G~/mu, M^-1 in
+  // place, M^-1 y and y^T M^-1 y.  BF16 storage factors the BF16 image too:
+  // the BF16 phase then solves the BF16 problem exactly (its n-space
+  // recurrences and ||g|| prediction match the data it streams).
   const size_t nn = (size_t)n * n;
-  if ((e = P->alloc((void**)&P->G, nn * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(G)"));
-  if ((e = P->alloc((void**)&P->Minv, nn * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(Minv)"));
-  const int splits = csr ? 1 : gram_splits(ld, n);
-  double* Gpart = nullptr;
-  if ((e = alloc_tmp((void**)&Gpart, std::max(nn * splits, nn) * 8)) != hipSuccess)
-    return cleanup(hip_fail(e, "hipMalloc(Gram partials)"));
-  if (csr)
-    e = launch_csr_gram(P->ipT, P->ixT, P->valT, P->csr_dtype, n, Gpart, st);
-  else
-    e = launch_gram(P->X_rec, P->st_rec, ld, n, Gpart, splits, st);
-  if (e == hipSuccess)
-    e = launch_gram_finish(Gpart, splits, n, P->y, 1.0 / (P->zscale * P->zscale), P->mu, P->G,
-                           P->Minv, st);
-  // a2: M^-1 in place (Gpart reused as work space), then M^-1 y and y^T M^-1 y
-  int* d_status = (int*)(dscal + 8);
-  int zero = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(d_status, &zero, 4, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = spd_inverse_inplace(P->Minv, n, Gpart, d_status, st);
-  if (e == hipSuccess) e = P->alloc((void**)&P->my, (size_t)n * 8);
-  if (e == hipSuccess) e = launch_gemv_rows(P->Minv, n, P->y, P->my, st);
-  if (e == hipSuccess) e = launch_dot(P->y, P->my, n, dscal + 1, st);
-  double hv[2] = {0, 0};
-  int hstat = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(hv, dscal, 16, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(&hstat, d_status, 4, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(Gpart);
-  if (e != hipSuccess) return cleanup(hip_fail(e, "Gram/inverse"));
-  if (hstat != 0 || !(hv[1] > 0.0) || !std::isfinite(hv[1]))
-    return cleanup(fail(DWD_E_NUMERIC, "factorisation of I + Z~^T Z~/mu failed"));
-  P->ymy = hv[1];
+  auto factor = [&](const void* Xsrc, int st_src, double** G, double** Minv, double** my,
+                    double* ymy) -> dwd_status {
+    hipError_t e2;
+    if ((e2 = P->alloc((void**)G, nn * 8)) != hipSuccess) return hip_fail(e2, "hipMalloc(G)");
+    if ((e2 = P->alloc((void**)Minv, nn * 8)) != hipSuccess)
+      return hip_fail(e2, "hipMalloc(Minv)");
+    const int splits = csr ? 1 : gram_splits(ld, n);
+    double* Gpart = nullptr;
+    if ((e2 = alloc_tmp((void**)&Gpart, std::max(nn * splits, nn) * 8)) != hipSuccess)
+      return hip_fail(e2, "hipMalloc(Gram partials)");
+    if (csr)
+      e2 = launch_csr_gram(P->ipT, P->ixT, P->valT, P->csr_dtype, n, Gpart, st);
+    else
+      e2 = launch_gram(Xsrc, st_src, ld, n, Gpart, splits, st);
+    if (e2 == hipSuccess)
+      e2 = launch_gram_finish(Gpart, splits, n, P->y, 1.0 / (P->zscale * P->zscale), P->mu, *G,
+                              *Minv, st);
+    int* d_status = (int*)(dscal + 8);
+    int zero = 0;
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(d_status, &zero, 4, hipMemcpyHostToDevice, st);
+    if (e2 == hipSuccess) e2 = spd_inverse_inplace(*Minv, n, Gpart, d_status, st);
+    if (e2 == hipSuccess) e2 = P->alloc((void**)my, (size_t)n * 8);
+    if (e2 == hipSuccess) e2 = launch_gemv_rows(*Minv, n, P->y, *my, st);
+    if (e2 == hipSuccess) e2 = launch_dot(P->y, *my, n, dscal + 1, st);
+    double hv[2] = {0, 0};
+    int hstat = 0;
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(hv, dscal, 16, hipMemcpyDeviceToHost, st);
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(&hstat, d_status, 4, hipMemcpyDeviceToHost, st);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+    (void)hipFree(Gpart);
+    if (e2 != hipSuccess) return hip_fail(e2, "Gram/inverse");
+    if (hstat != 0 || !(hv[1] > 0.0) || !std::isfinite(hv[1]))
+      return fail(DWD_E_NUMERIC, "factorisation of I + Z~^T Z~/mu failed");
+    *ymy = hv[1];
+    return DWD_OK;
+  };
+  if ((s = factor(P->X_rec, P->st_rec, &P->G, &P->Minv, &P->my, &P->ymy)) != DWD_OK)
+    return cleanup(s);
+  if (P->storage == DWD_BF16 &&
+      (s = factor(P->X_lowp, DWD_BF16, &P->G_lp, &P->Minv_lp, &P->my_lp, &P->ymy_lp)) != DWD_OK)
+    return cleanup(s);
 
   // Iteration buffers.
   if ((e = P->alloc_iter_buffers()) != hipSuccess) return cleanup(hip_fail(e, "iteration buffers"));
@@ -391,16 +406,14 @@ hipError_t Problem::alloc_iter_buffers() {
   take(ip.f); take(ip.s); take(ip.v); take(ip.dr); take(ip.hG); take(ip.rn); take(ip.s1);
   take(ip.v1); take(ip.xi0); take(ip.xi1); take(ip.al0); take(ip.al1);
   double* db = nullptr;
-  if ((e = alloc((void**)&db, (size_t)ld * 8 * 4)) != hipSuccess) return e;
+  if ((e = alloc((void**)&db, (size_t)ld * 8 * 3)) != hipSuccess) return e;
   ip.u = db;
   ip.rho = db + ld;
   ip.w = db + 2 * ld;
-  ip.za = db + 3 * ld;
   nchunks = (int)(ld / kLdAlign);
   if ((e = alloc((void**)&ip.partT, (size_t)nchunks * 2 * n_ * 8)) != hipSuccess) return e;
   const int npb = std::max(pass2_blocks(DWD_FP64, ld), 1);  // FP64 has the most blocks
   if ((e = alloc((void**)&ip.part_g, (size_t)npb * NP2 * 8)) != hipSuccess) return e;
-  if ((e = alloc((void**)&ip.part_d, (size_t)dspace_blocks(ld) * NP2 * 8)) != hipSuccess) return e;
   if ((e = alloc((void**)&ip.part_n1, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
   if ((e = alloc((void**)&ip.part_it, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
   if ((e = alloc((void**)&ip.part_c, (size_t)ngemv_blocks(n_) * NPC * 8)) != hipSuccess) return e;
@@ -409,6 +422,12 @@ hipError_t Problem::alloc_iter_buffers() {
   ip.my = my;
   ip.Minv = Minv;
   ip.G = G;
+  ip_lp = ip;
+  if (G_lp) {
+    ip_lp.G = G_lp;
+    ip_lp.Minv = Minv_lp;
+    ip_lp.my = my_lp;
+  }
   return hipSuccess;
 }
 
@@ -447,6 +466,15 @@ Consts make_consts(const Problem* P, const dwd_params* p) {
   c.qexp = p->q / (p->q + 1.0);
   c.rho_residual = p->rho_residual ? 1 : 0;
   c.qkind = qkind_of(p->q);
+  c.sigma_every = p->sigma_every;
+  c.pad_c = 0;
+  return c;
+}
+
+Consts lowp_consts(const Problem* P, const dwd_params* p) {
+  Consts c = make_consts(P, p);
+  c.ymy = P->ymy_lp;
+  c.tol = p->lowp_tol > 0.0 ? p->lowp_tol : std::min(0.5, 30.0 * p->tol);
   return c;
 }
 
@@ -459,6 +487,8 @@ hipError_t Problem::queue_iteration(const Consts& c, const void* Xit, int st_it,
                                     bool profile, int k) {
   hipError_t e;
   const hipStream_t s = stream;
+  // The BF16 phase iterates on the BF16 image with that image's own factor.
+  const IterPtrs& I = st_it == DWD_BF16 ? ip_lp : ip;
   if (fresh) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile) {
@@ -467,16 +497,16 @@ hipError_t Problem::queue_iteration(const Consts& c, const void* Xit, int st_it,
       (void)hipEventRecord(e0, s);
     }
     if (layout == DWD_CSR)
-      e = launch_csr_gemvT(ipT, ixT, valT, csr_dtype, n, ip.u, ip.rho, ip.partT, ip.sc, s);
+      e = launch_csr_gemvT(ipT, ixT, valT, csr_dtype, n, I.u, I.rho, I.partT, I.sc, s);
     else
-      e = launch_gemvT(Xit, st_it, ld, n, ip.u, ip.rho, ip.partT, ip.sc, s);
+      e = launch_gemvT(Xit, st_it, ld, n, I.u, I.rho, I.partT, I.sc, s);
     if (e != hipSuccess) return e;
     if (profile) (void)hipEventRecord(e1, s);
   }
   // Without a fresh pass, t and x were formed by the previous tail kernel.
-  if (fresh && (e = launch_rhs(c, ip, nchunks, 1, s)) != hipSuccess) return e;
-  if ((e = launch_step1ab(c, ip, s)) != hipSuccess) return e;
-  if ((e = launch_step1c_rows(c, ip, s)) != hipSuccess) return e;
+  if (fresh && (e = launch_rhs(c, I, nchunks, 1, s)) != hipSuccess) return e;
+  if ((e = launch_step1ab(c, I, s)) != hipSuccess) return e;
+  if ((e = launch_step1c_rows(c, I, s)) != hipSuccess) return e;
   {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile) {
@@ -485,21 +515,14 @@ hipError_t Problem::queue_iteration(const Consts& c, const void* Xit, int st_it,
       (void)hipEventRecord(e0, s);
     }
     if (layout == DWD_CSR)
-      e = launch_csr_pass(ipX, ixX, valX, csr_dtype, d, c, ip, s);
+      e = launch_csr_pass(ipX, ixX, valX, csr_dtype, d, c, I, s);
     else
-      e = launch_pass2(Xit, st_it, c, ip, s);
+      e = launch_pass2(Xit, st_it, c, I, s);
     if (e != hipSuccess) return e;
     if (profile) (void)hipEventRecord(e1, s);
   }
-  if (layout == DWD_CSR) {
-    if ((e = launch_tail(c, ip, csr_pass_blocks(ld), 1, s)) != hipSuccess) return e;
-  } else if (st_it == DWD_BF16) {
-    if ((e = launch_dspace(c, ip, pass2_blocks(st_it, ld), s)) != hipSuccess) return e;
-    if ((e = launch_tail(c, ip, dspace_blocks(ld), 0, s)) != hipSuccess) return e;
-  } else {
-    if ((e = launch_tail(c, ip, pass2_blocks(st_it, ld), 1, s)) != hipSuccess) return e;
-  }
-  return hipSuccess;
+  const int nblk = layout == DWD_CSR ? csr_pass_blocks(ld) : pass2_blocks(st_it, ld);
+  return launch_tail(c, I, nblk, s);
 }
 
 hipError_t Problem::pass_T(const double* v1, const double* v2, const Scal* sc) {
@@ -589,8 +612,7 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
   int iters_lowp = 0;
   if (P->storage == DWD_BF16) {
     // Phase 1 on the BF16 image, to the looser tolerance.
-    Consts c1 = c;
-    c1.tol = p->lowp_tol > 0.0 ? p->lowp_tol : std::min(0.5, 30.0 * p->tol);
+    const Consts c1 = lowp_consts(P, p);
     HIP_TRY(P->run_loop(c1, P->X_lowp, DWD_BF16, p->resync, check_every, profile, 0));
     Scal hs;
     HIP_TRY(hipMemcpy(&hs, P->ip.sc, sizeof(Scal), hipMemcpyDeviceToHost));
@@ -617,7 +639,10 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
     HIP_TRY(hipMemcpyAsync(&hs, P->ip.sc, sizeof(Scal), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const double chk = std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]);
-    if (!hs.converged || chk < p->tol || resumed >= 2 || hs.k >= p->max_iter) break;
+    // (BF16 storage without refinement: the check only reports the residual
+    // of the BF16 solution against the data of record.)
+    const bool no_refine = P->storage == DWD_BF16 && !p->refine;
+    if (!hs.converged || chk < p->tol || resumed >= 2 || hs.k >= p->max_iter || no_refine) break;
     ++resumed;
     hipLaunchKernelGGL(k_reset_done, dim3(1), dim3(1), 0, st, P->ip.sc);
     HIP_TRY(hipGetLastError());
@@ -718,6 +743,7 @@ void dwd_default_params(dwd_params* p) {
   p->batch_fp32 = 1;
   p->batch_tile = 0;
   p->graph = 1;
+  p->sigma_every = 2;
 }
 
 dwd_status dwd_setup(const dwd_matrix* X, const double* y, const dwd_params* p, void* stream,

@@ -249,13 +249,13 @@ __device__ __forceinline__ void finish_etas(const Consts& c, const double* r, do
 
 
 // Stopping rule of Section 4.3 and sigma rule of Section 4.4 on the residuals
-// e[]; returns the new sigma and sets *stop.
+// e[] after iteration count k1; returns the new sigma and sets *stop.
 __device__ __forceinline__ double stop_and_sigma(const Consts& c, const double* e, double sigma,
-                                                 bool* stop) {
+                                                 int k1, bool* stop) {
   const double pd = fmax(e[E_P], e[E_D]);
   const double cg_min = fmin(e[E_C], e[E_GAP]), cg_max = fmax(e[E_C], e[E_GAP]);
   *stop = pd < c.tol && cg_min < sqrt(c.tol) && cg_max < 0.05;
-  if (*stop) return sigma;
+  if (*stop || k1 % c.sigma_every != 0) return sigma;
   const double ep = e[E_P], ed = e[E_D];
   if (ep >= 1e-300 && ed >= 1e-300) {
     const double chi = ep / ed;

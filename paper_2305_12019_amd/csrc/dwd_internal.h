@@ -86,6 +86,8 @@ struct Consts {
   double qexp;         // q/(q+1)
   int32_t rho_residual;
   int32_t qkind;       // 1,2,4: integer q; 5: q = 0.5; 0: general
+  int32_t sigma_every; // the sigma rule runs after iterations k with k % sigma_every == 0
+  int32_t pad_c;
   double sigma0;       // initial sigma (used by the batched initialiser)
 };
 
@@ -97,9 +99,8 @@ struct IterPtrs {
   const double* G;
   double *r, *xi, *alpha, *Pu, *Prho, *t, *x, *f, *s, *v, *dr, *hG, *rn;
   double *s1, *v1, *xi0, *xi1, *al0, *al1;  // the two outcomes of Step 1c
-  double *u, *rho, *w, *za;  // d-space, length ld (za: BF16 phase only)
+  double *u, *rho, *w;  // d-space, length ld
   double *part_g;       // pass partials (NP2 per block)
-  double *part_d;       // d-space step partials (NP2 per block; BF16 phase)
   double *part_n1;      // Step 1b block partials of y^T dr
   double *part_it;      // Step 1b block maxima of Newton steps
   double *part_c;       // Step 1c block partials (NPC per block)

@@ -144,7 +144,9 @@ hipError_t advance(Slot& s, int chunk) {
       return queue_chunk(s, chunk);
     case CHECK: {
       const double chk = std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]);
-      if (hs.converged && chk >= s.prm.tol && s.resumed < 2 && hs.k < s.prm.max_iter) {
+      const bool no_refine = s.P->storage == DWD_BF16 && !s.prm.refine;
+      if (hs.converged && chk >= s.prm.tol && s.resumed < 2 && hs.k < s.prm.max_iter &&
+          !no_refine) {
         ++s.resumed;
         hipError_t e = start_phase(s, RESUME);
         if (e != hipSuccess) return e;
@@ -278,8 +280,7 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
       }
       used += (double)fp;
       s.c = make_consts(s.P, &s.prm);
-      s.c_lowp = s.c;
-      s.c_lowp.tol = s.prm.lowp_tol > 0.0 ? s.prm.lowp_tol : std::min(0.5, 30.0 * s.prm.tol);
+      s.c_lowp = s.P->storage == DWD_BF16 ? lowp_consts(s.P, &s.prm) : s.c;
       memset(s.hs, 0, sizeof(Scal));
       if (launch_init(s.c, s.P->ip, default_sigma0(&s.prm, s.P->n), s.stream) != hipSuccess ||
           queue_chunk(s, chunk) != hipSuccess) {

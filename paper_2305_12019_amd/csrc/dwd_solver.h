@@ -23,9 +23,7 @@ hipError_t launch_step1c_rows(const Consts& c, const IterPtrs& p, hipStream_t st
 hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterPtrs& p,
                         hipStream_t st);
 int pass2_blocks(int storage, int64_t ld);
-hipError_t launch_dspace(const Consts& c, const IterPtrs& p, int nblk_p2, hipStream_t st);
-int dspace_blocks(int64_t ld);
-hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, int fused, hipStream_t st);
+hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, hipStream_t st);
 hipError_t launch_check(const Consts& c, const IterPtrs& p, int nchunks, hipStream_t st);
 bool iter_ptrs_ok(const IterPtrs& p);
 hipError_t launch_csr_frob(const void* val, int dtype, int64_t nnz, double* part, int nblk,
@@ -59,7 +57,15 @@ struct Problem {
   double* Minv = nullptr;
   double* my = nullptr;
   double* d_scal = nullptr;
+  // BF16 storage: the FP64 factor of the BF16 image (G~, M^-1, M^-1 y,
+  // y^T M^-1 y of the problem the BF16 phase solves), and the iteration
+  // pointers that use it.
+  double* G_lp = nullptr;
+  double* Minv_lp = nullptr;
+  double* my_lp = nullptr;
+  double ymy_lp = 1.0;
   IterPtrs ip{};
+  IterPtrs ip_lp{};
   int nchunks = 0;
   void* h_flags = nullptr;     // pinned host words for stop flags
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -95,6 +101,8 @@ dwd_status fail(dwd_status s, const std::string& msg);
 dwd_status hip_fail(hipError_t e, const char* where);
 dwd_status validate_params(const dwd_params* p, bool for_solve);
 Consts make_consts(const Problem* P, const dwd_params* p);
+// Constants of the BF16 phase: its own y^T M^-1 y and the looser tolerance.
+Consts lowp_consts(const Problem* P, const dwd_params* p);
 double default_sigma0(const dwd_params* p, int n);
 int64_t padded_ld(int64_t d);
 int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz);

@@ -761,7 +761,7 @@ __global__ void __launch_bounds__(NTB) k_tail_b(BatchPtrs P, const int* __restri
     const int k1 = k0 + 1;
     sc->k = k1;
     bool stop = false;
-    const double sig = stop_and_sigma(c, e, sigma, &stop);
+    const double sig = stop_and_sigma(c, e, sigma, k1, &stop);
     if (stop) {
       sc->converged = 1;
       sc->done = 1;

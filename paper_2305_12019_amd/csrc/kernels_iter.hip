@@ -90,8 +90,8 @@ static hipError_t gemvT_t(const void* X, int64_t ld, int n, const double* v1, co
 bool iter_ptrs_ok(const IterPtrs& p) {
   const void* req[] = {p.y, p.my, p.Minv, p.G, p.r, p.xi, p.alpha, p.Pu, p.Prho, p.t, p.x,
                        p.f, p.s, p.v, p.dr, p.hG, p.rn, p.s1, p.v1, p.xi0, p.xi1, p.al0,
-                       p.al1, p.u, p.rho, p.w, p.za, p.part_g, p.part_d, p.part_n1, p.part_it,
-                       p.part_c, p.partT, p.sc};
+                       p.al1, p.u, p.rho, p.w, p.part_g, p.part_n1, p.part_it, p.part_c,
+                       p.partT, p.sc};
   for (const void* q : req)
     if (!q) return false;
   return true;
@@ -121,7 +121,6 @@ __global__ void k_init(Consts c, IterPtrs p, double sigma0) {
     p.u[i] = 0.0;
     p.rho[i] = 0.0;
     p.w[i] = 0.0;
-    p.za[i] = 0.0;
   }
   if (i == 0) {
     Scal* s = p.sc;
@@ -427,11 +426,10 @@ hipError_t launch_step1c_rows(const Consts& c, const IterPtrs& p, hipStream_t st
 // ---------------------------------------------------------------------------
 constexpr int PANEL = 2048;
 
-// FUSED = true when the streamed data is the data of record, so that the
-// n-space prediction of ||g|| is exact; the BF16 phase (FUSED = false)
-// writes w and Z~ alpha and leaves Steps 2-3 to k_dspace, which takes ||g||
-// from the pass itself.
-template <typename T, int NW, bool FUSED>
+// The n-space prediction of ||g|| that sizes the ball projection is exact
+// for the data the pass streams: the data of record with its factor, or the
+// BF16 image with the factor of the BF16 image (BF16 phase).
+template <typename T, int NW>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2)))
 k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
   if (p.sc->done) return;
@@ -577,51 +575,10 @@ k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
     const double b = c.mu * u_in[q] + br * rho;
     const double w = (b - zs) / c.mu;
     p.w[k] = w;
-    if constexpr (FUSED) {
-      const double u = gamma * (w - gr * rho);
-      const double rn = rho - rs * (w - u);
-      p.u[k] = u;
-      p.rho[k] = rn;
-      const double dres = za + c.sqmu * rn;
-      acc[0] += (w - u) * (w - u);
-      acc[1] += w * w;
-      acc[2] += dres * dres;
-      acc[3] += za * za;
-      acc[4] += rn * rn;
-      acc[5] += u * u;
-    } else {
-      const double g = w - gr * rho;
-      p.za[k] = za;
-      acc[0] += g * g;
-    }
-  }
-  block_sum_k<NW * 64, NP2>(acc);
-  if (threadIdx.x < NP2) p.part_g[(size_t)blockIdx.x * NP2 + threadIdx.x] = acc[threadIdx.x];
-}
-
-// Steps 2 and 3 in d-space for the BF16 phase: gamma from the pass's own
-// ||g||^2, then u, rho and the same NP2 partials as the fused pass.
-__global__ void __launch_bounds__(256) k_dspace(Consts c, IterPtrs p, int nblk_p2) {
-  Scal* sc = p.sc;
-  if (sc->done) return;
-  double g2 = 0.0;
-  for (int b = threadIdx.x; b < nblk_p2; b += 256) g2 += p.part_g[(size_t)b * NP2];
-  g2 = block_sum<256>(g2);
-  const double ng = sqrt(g2);
-  const double gamma = (ng <= c.R) ? 1.0 : c.R / ng;
-  const double sigma = sc->sigma;
-  const double gr = 1.0 / (sigma * c.sqmu);
-  const double rs = c.tau * sigma * c.sqmu;
-  double acc[NP2] = {0, 0, 0, 0, 0, 0};
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < c.ld;
-       k += (int64_t)gridDim.x * 256) {
-    const double w = p.w[k];
-    const double rho = p.rho[k];
     const double u = gamma * (w - gr * rho);
     const double rn = rho - rs * (w - u);
     p.u[k] = u;
     p.rho[k] = rn;
-    const double za = p.za[k];
     const double dres = za + c.sqmu * rn;
     acc[0] += (w - u) * (w - u);
     acc[1] += w * w;
@@ -630,21 +587,11 @@ __global__ void __launch_bounds__(256) k_dspace(Consts c, IterPtrs p, int nblk_p
     acc[4] += rn * rn;
     acc[5] += u * u;
   }
-  block_sum_k<256, NP2>(acc);
-  if (threadIdx.x < NP2) p.part_d[(size_t)blockIdx.x * NP2 + threadIdx.x] = acc[threadIdx.x];
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc->gamma = gamma;
+  block_sum_k<NW * 64, NP2>(acc);
+  if (threadIdx.x < NP2) p.part_g[(size_t)blockIdx.x * NP2 + threadIdx.x] = acc[threadIdx.x];
 }
 
-int dspace_blocks(int64_t ld) {
-  int64_t b = (ld + 255) / 256;
-  return (int)(b > 1024 ? 1024 : b);
-}
-
-hipError_t launch_dspace(const Consts& c, const IterPtrs& p, int nblk_p2, hipStream_t st) {
-  hipLaunchKernelGGL(k_dspace, dim3(dspace_blocks(c.ld)), dim3(256), 0, st, c, p, nblk_p2);
-  return hipGetLastError();
-}
-
+// Blocks of the pass: 64 V rows each (V = 2, 4, 8 for FP64, FP32, BF16).
 int pass2_blocks(int storage, int64_t ld) {
   const int rows = storage == DWD_FP64 ? 128 : (storage == DWD_FP32 ? 256 : 512);
   return (int)(ld / rows);
@@ -655,14 +602,12 @@ hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterP
   if (!X || !iter_ptrs_ok(p) || c.ld % kLdAlign != 0) return hipErrorInvalidValue;
   const int nb = pass2_blocks(storage, c.ld);
   if (storage == DWD_FP64)
-    hipLaunchKernelGGL((k_pass2<double, 8, true>), dim3(nb), dim3(512), 0, st, (const double*)X,
-                       c, p);
+    hipLaunchKernelGGL((k_pass2<double, 8>), dim3(nb), dim3(512), 0, st, (const double*)X, c, p);
   else if (storage == DWD_FP32)
-    hipLaunchKernelGGL((k_pass2<float, 8, true>), dim3(nb), dim3(512), 0, st, (const float*)X, c,
-                       p);
+    hipLaunchKernelGGL((k_pass2<float, 8>), dim3(nb), dim3(512), 0, st, (const float*)X, c, p);
   else
-    hipLaunchKernelGGL((k_pass2<uint16_t, 4, false>), dim3(nb), dim3(256), 0, st,
-                       (const uint16_t*)X, c, p);
+    hipLaunchKernelGGL((k_pass2<uint16_t, 4>), dim3(nb), dim3(256), 0, st, (const uint16_t*)X,
+                       c, p);
   return hipGetLastError();
 }
 
@@ -675,9 +620,9 @@ hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterP
 // ---------------------------------------------------------------------------
 constexpr int NT1 = 512;
 
-// fused = 1: d-space partials and gamma come from the fused pass (part_g,
-// step2_plan); fused = 0: from k_dspace (part_d, sc->gamma).
-__global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d, int fused) {
+// The d-space partials come from the pass (part_g, nblk_d blocks) and gamma
+// from the same plan the pass used.
+__global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d) {
   Scal* sc = p.sc;
   if (sc->done) return;
   __shared__ double s_sigma;
@@ -686,7 +631,6 @@ __global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d, 
   const int k0 = sc->k;
   const double u2 = sc->u2;
   const double sigma = sc->sigma;
-  const double gamma_d = sc->gamma;
   const double beta_bar = sc->beta_bar;
   const double beta_1 = sc->beta1;
   const int nd = sc->n_double;
@@ -702,7 +646,7 @@ __global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d, 
 #pragma unroll
   for (int j = 0; j < K; ++j) acc[j] = 0.0;
   double nmax = 0.0;
-  const double* pd_src = fused ? p.part_g : p.part_d;
+  const double* pd_src = p.part_g;
   for (int b = threadIdx.x; b < nb; b += NT1) {
 #pragma unroll
     for (int j = 0; j < 9; ++j) acc[j] += p.part_c[(size_t)b * NPC + 1 + o * NPO + j];
@@ -723,7 +667,7 @@ __global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d, 
     nmax = m;
   }
 
-  const double gamma = fused ? pl.gamma : gamma_d;
+  const double gamma = pl.gamma;
   const double beta = o ? beta_1 : beta_bar;
   if (threadIdx.x == 0) {
     const double m = nmax;
@@ -749,7 +693,7 @@ __global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d, 
     const int k1 = k0 + 1;
     sc->k = k1;
     bool stop = false;
-    const double sig = stop_and_sigma(c, e, sigma, &stop);
+    const double sig = stop_and_sigma(c, e, sigma, k1, &stop);
     if (stop) {
       sc->converged = 1;
       sc->done = 1;
@@ -791,9 +735,8 @@ __global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d, 
   }
 }
 
-hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, int fused,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_tail, dim3(1), dim3(NT1), 0, st, c, p, nblk_d, fused);
+hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, hipStream_t st) {
+  hipLaunchKernelGGL(k_tail, dim3(1), dim3(NT1), 0, st, c, p, nblk_d);
   return hipGetLastError();
 }
 

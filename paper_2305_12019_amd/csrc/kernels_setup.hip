@@ -109,6 +109,16 @@ __device__ __forceinline__ void gram_stage(const void* Xs, int64_t ld, int n, in
                                                            kb + kq);
         S[kq][c] = v.x;
         S[kq + 1][c] = v.y;
+      } else if constexpr (sizeof(T) == 2) {
+        // BF16: the upper 16 bits of an FP32 value
+        const uint4 v = *reinterpret_cast<const uint4*>((const uint16_t*)Xs + (int64_t)gc * ld +
+                                                        kb + kq);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          S[kq + 2 * q][c] = (double)__uint_as_float(w[q] << 16);
+          S[kq + 2 * q + 1][c] = (double)__uint_as_float(w[q] & 0xFFFF0000u);
+        }
       } else {
         const float4 v = *reinterpret_cast<const float4*>((const float*)Xs + (int64_t)gc * ld +
                                                          kb + kq);
@@ -209,6 +219,9 @@ hipError_t launch_gram(const void* Xs, int storage, int64_t ld, int n, double* G
   dim3 grid(nt * (nt + 1) / 2, splits);
   if (storage == DWD_FP64)
     hipLaunchKernelGGL(k_gram_mfma<double>, grid, dim3(256), 0, st, Xs, ld, n, nt, splits, Gpart);
+  else if (storage == DWD_BF16)
+    hipLaunchKernelGGL(k_gram_mfma<uint16_t>, grid, dim3(256), 0, st, Xs, ld, n, nt, splits,
+                       Gpart);
   else
     hipLaunchKernelGGL(k_gram_mfma<float>, grid, dim3(256), 0, st, Xs, ld, n, nt, splits, Gpart);
   return hipGetLastError();

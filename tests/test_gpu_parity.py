@@ -154,6 +154,31 @@ def test_bf16_storage_with_fp32_refinement(dwd):
     assert kkt <= 2e-8, e
 
 
+def _bf16_round(X):
+    """Round FP32 values to BF16 (nearest, ties to even), returned as FP32."""
+    b = np.ascontiguousarray(X, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def test_bf16_phase_solves_the_bf16_problem(dwd):
+    """With refinement off and a tight phase tolerance, the BF16 phase alone
+    must reach the solution of the problem posed on the BF16-rounded data
+    (its factor is the FP64 factor of that image)."""
+    X, y = synth.random_two_class(5000, 120, seed=32, mean=0.6, log_scale=1.0, dtype="f32")
+    Xb = _bf16_round(X)
+    assert np.max(np.abs(Xb - X) / np.maximum(np.abs(X), 1e-30)) <= 2.0 ** -8
+    for q, C in ((1.0, 1.0), (2.0, 0.3)):
+        got = dwd.solve(X, y, C, q, tol=1e-8, storage="bf16", refine=0, lowp_tol=1e-8,
+                        max_iter=20000)
+        assert got["info"]["iters_lowp"] == got["info"]["iters"]
+        ref = O.solve(Xb, y, C, q, tol=1e-9, max_iter=20000)
+        f = _obj(Xb, y, got["w"], got["beta"], C, q)
+        fr = _obj(Xb, y, ref["w"], ref["beta"], C, q)
+        assert abs(f - fr) <= 1e-6 * abs(fr), (q, C, f, fr)
+        assert np.linalg.norm(got["w"] - ref["w"]) <= 1e-4 * np.linalg.norm(ref["w"]), (q, C)
+
+
 # ---------------------------------------------------------------------------
 # Edge cases.
 # ---------------------------------------------------------------------------
@@ -244,3 +269,59 @@ def test_hdlss_full_size_properties(dwd):
     # r - xi = Z~^T w~ + beta y = y (x^T w + beta) for the unscaled w
     # (w~ = Z_scale w, Z~ = Z / Z_scale), up to the primal residual
     assert np.max(np.abs(m_gpu - m_ref)) <= 10 * wl.tol * (1 + wl.C)
+
+
+def _margins_by_rows(X, y, w, beta, rows=64):
+    """y_i (x_i^T w + beta) for every sample, in FP64, a block of rows at a time."""
+    m = np.empty(X.shape[0])
+    for r0 in range(0, X.shape[0], rows):
+        r1 = min(X.shape[0], r0 + rows)
+        m[r0:r1] = y[r0:r1] * (X[r0:r1].astype(np.float64) @ w + beta)
+    return m
+
+
+def _z_alpha_by_rows(X, y, a, rows=64):
+    """Z alpha = sum_i a_i y_i x_i in FP64, a block of rows at a time."""
+    acc = np.zeros(X.shape[1])
+    for r0 in range(0, X.shape[0], rows):
+        r1 = min(X.shape[0], r0 + rows)
+        acc += X[r0:r1].astype(np.float64).T @ (y[r0:r1] * a[r0:r1])
+    return acc
+
+
+def test_large_bf16_full_size(dwd):
+    """The large mixed-precision workload at full size (d=1e6, n=2000, q=2,
+    C=1, BF16 storage of Z, FP64 factors, FP32 refinement): the FP64 check on
+    the device, every sample's margin recomputed in FP64 on the host, a
+    duality-gap certificate, and agreement with FP32 storage."""
+    torch = pytest.importorskip("torch")
+    wl = synth.LARGE_BF16
+    X, y = synth.two_class(wl.data)
+    Xd = torch.from_numpy(X).to("cuda")
+    got = dwd.solve(Xd, y, wl.C, wl.q, tol=wl.tol, storage="bf16", max_iter=20000)
+    info = got["info"]
+    print("large BF16 solve:", {k: info[k] for k in ("iters", "iters_lowp", "setup_ms",
+                                                      "solve_ms", "kkt_check", "eta_gap")})
+    assert info["converged"] == 1 and info["iters_lowp"] > 0
+    assert info["kkt_check"] <= 1.2 * wl.tol
+    # r - xi = y (x^T w + beta) for every sample, up to the primal residual
+    m = _margins_by_rows(X, y, got["w"], got["beta"])
+    assert np.max(np.abs((got["r"] - got["xi"]) - m)) <= 10 * wl.tol * (1 + wl.C)
+    assert np.all(got["xi"] >= 0.0) and np.all(got["r"] > 0.0)
+    assert np.linalg.norm(got["w"]) <= 1.0 + 1e-4
+    # duality-gap certificate at a feasible alpha
+    wn = got["w"] / max(1.0, np.linalg.norm(got["w"]))
+    P = float(np.sum(O.reduced_loss(_margins_by_rows(X, y, wn, got["beta"]), wl.C, wl.q)))
+    a = _dual_feasible(got["alpha"], y, wl.C)
+    D = float(O.kappa(wl.q) * np.sum(a ** (wl.q / (wl.q + 1.0)))
+              - np.linalg.norm(_z_alpha_by_rows(X, y, a)))
+    assert D <= P
+    assert (P - D) <= 0.06 * (1.0 + abs(P) + abs(D)), (P, D)
+    # the same problem with FP32 storage reaches the same objective
+    ref = dwd.solve(Xd, y, wl.C, wl.q, tol=wl.tol, storage="f32", max_iter=20000,
+                    want_state=False)
+    assert ref["info"]["converged"] == 1
+    wr = ref["w"] / max(1.0, np.linalg.norm(ref["w"]))
+    Pr = float(np.sum(O.reduced_loss(_margins_by_rows(X, y, wr, ref["beta"]), wl.C, wl.q)))
+    print("primal objective bf16 %.9g f32 %.9g" % (P, Pr))
+    assert abs(P - Pr) <= 1e-4 * abs(Pr)
