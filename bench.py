@@ -17,6 +17,10 @@ Beside it, on the same data and to the same tolerance, the line carries
   roofline  the Z~ [s, alpha] pass of the plain solve, timed live with HIP
             events on the solver's stream, against the HBM peak and against a
             measured device copy;
+  large     the d=1e6 n=2000 q=2 workload (feature scales log-uniform in
+            [0.1, 10]) solved with Z in BF16 (FP64 factors of the BF16 image,
+            FP32 refinement, FP64 check) against Z in FP32, both to rel. KKT
+            1e-5 (--no-large skips it);
   cpu_baseline  one whole solve of the FP64 oracle on the host cores.
 Prints one JSON line.
 """
@@ -215,6 +219,33 @@ def serving_leg(dwd, torch, dev, count, tol):
     }
 
 
+def large_leg(dwd, torch, dev):
+    """Mixed precision on one large problem: BF16 storage against FP32."""
+    import synth
+    wl = synth.LARGE_BF16
+    X, y = synth.two_class(wl.data)
+    Xd = torch.from_numpy(X).to(dev)
+    del X
+    torch.cuda.synchronize()
+    out = {"workload": wl.name, "d": wl.data.d, "n": wl.data.n, "q": wl.q, "C": wl.C,
+           "tol": wl.tol, "max_iter": 20000}
+    for storage in ("bf16", "f32"):
+        t = time.perf_counter()
+        P = dwd.Problem(Xd, y, storage=storage)
+        r = P.solve(wl.C, wl.q, tol=wl.tol, want_state=False, max_iter=20000)
+        P.close()
+        torch.cuda.synchronize()
+        i = r["info"]
+        out[storage] = {"solve_s": time.perf_counter() - t, "setup_ms": i["setup_ms"],
+                        "iters": i["iters"], "iters_bf16": i["iters_lowp"],
+                        "converged": i["converged"], "kkt_check": i["kkt_check"],
+                        "eta_gap": i["eta_gap"], "primal_obj": i["primal_obj"]}
+    out["gain_bf16_vs_f32"] = out["f32"]["solve_s"] / out["bf16"]["solve_s"]
+    del Xd
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +254,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64, help="0 to skip the serving leg")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration) and one solve")
     args = ap.parse_args()
@@ -303,7 +335,7 @@ def main():
                    "setup_ms": float(np.median([i["setup_ms"] for i in infos])),
                    "solve_ms": float(np.median([i["solve_ms"] for i in infos]))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "roofline": {"bound": "hbm", "kernel": "k_pass2<float,8,true> (Z~ [s, alpha] pass)",
+        "roofline": {"bound": "hbm", "kernel": "k_pass2<float,8> (Z~ [s, alpha] pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
@@ -320,6 +352,12 @@ def main():
         torch.cuda.empty_cache()
         out["serving"] = serving_leg(dwd, torch, dev, args.serve_requests, wl.tol)
         print("[bench] serving done", file=sys.stderr, flush=True)
+    if not args.no_large:
+        if args.serve_requests <= 0:
+            del Xd
+            torch.cuda.empty_cache()
+        out["large"] = large_leg(dwd, torch, dev)
+        print("[bench] large done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, y, wl)
     print(json.dumps(out), flush=True)
