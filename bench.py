@@ -21,6 +21,11 @@ Beside it, on the same data and to the same tolerance, the line carries
             [0.1, 10]) solved with Z in BF16 (FP64 factors of the BF16 image,
             FP32 refinement, FP64 check) against Z in FP32, both to rel. KKT
             1e-5 (--no-large skips it);
+  representer  the same HDLSS solves in the representer mode (the d-vectors
+            carried as n-vector coefficients, so an iteration reads only the
+            n x n matrices and Z is streamed once at the end and by the FP64
+            check): a separate mode, since it bypasses the pass; the large
+            leg runs it too;
   cpu_baseline  one whole solve of the FP64 oracle on the host cores.
 Prints one JSON line.
 """
@@ -229,18 +234,20 @@ def large_leg(dwd, torch, dev):
     torch.cuda.synchronize()
     out = {"workload": wl.name, "d": wl.data.d, "n": wl.data.n, "q": wl.q, "C": wl.C,
            "tol": wl.tol, "max_iter": 20000}
-    for storage in ("bf16", "f32"):
+    for storage, rep in (("bf16", 0), ("f32", 0), ("f32", 1)):
         t = time.perf_counter()
         P = dwd.Problem(Xd, y, storage=storage)
-        r = P.solve(wl.C, wl.q, tol=wl.tol, want_state=False, max_iter=20000)
+        r = P.solve(wl.C, wl.q, tol=wl.tol, want_state=False, max_iter=20000, representer=rep)
         P.close()
         torch.cuda.synchronize()
         i = r["info"]
-        out[storage] = {"solve_s": time.perf_counter() - t, "setup_ms": i["setup_ms"],
+        out["representer" if rep else storage] = {
+                        "solve_s": time.perf_counter() - t, "setup_ms": i["setup_ms"],
                         "iters": i["iters"], "iters_bf16": i["iters_lowp"],
                         "converged": i["converged"], "kkt_check": i["kkt_check"],
                         "eta_gap": i["eta_gap"], "primal_obj": i["primal_obj"]}
     out["gain_bf16_vs_f32"] = out["f32"]["solve_s"] / out["bf16"]["solve_s"]
+    out["gain_representer_vs_f32"] = out["f32"]["solve_s"] / out["representer"]["solve_s"]
     del Xd
     torch.cuda.empty_cache()
     return out
@@ -287,10 +294,11 @@ def main():
               flush=True)
         return
 
-    def step(profile):
+    def step(profile, representer=0):
         t = time.perf_counter()
         P = dwd.Problem(Xd, y, storage="f32")
-        r = P.solve(wl.C, wl.q, tol=wl.tol, want_state=False, profile=profile)
+        r = P.solve(wl.C, wl.q, tol=wl.tol, want_state=False, profile=profile,
+                    representer=representer)
         P.close()
         return r, (time.perf_counter() - t) * 1e3
 
@@ -344,6 +352,23 @@ def main():
                      "bytes_per_launch": bpl,
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
     }
+    # representer mode on the same workload (a separate mode: no pass per iteration)
+    for _ in range(max(1, args.warmup)):
+        step(0, 1)
+    torch.cuda.synchronize()
+    t0r = time.perf_counter()
+    rruns = [step(0, 1) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    er = time.perf_counter() - t0r
+    rinfo = [r["info"] for r, _ in rruns]
+    out["representer"] = {
+        "solves_per_s": args.steps / er, "ms_per_solve": er / args.steps * 1e3,
+        "iters": int(np.median([i["iters"] for i in rinfo])),
+        "converged": all(i["converged"] == 1 for i in rinfo),
+        "kkt_check_max": max(i["kkt_check"] for i in rinfo),
+        "gain_vs_pass": (args.steps / er) / out["value"],
+        "latency_ms": {"p50": float(np.percentile([ms for _, ms in rruns], 50)),
+                       "p99": float(np.percentile([ms for _, ms in rruns], 99))}}
     if not args.no_batched:
         out["batched"] = batched_leg(dwd, Xd, y, wl.tol, synth.sweep_grid())
         print(f"[bench] batched: gain {out['batched']['gain']:.2f}", file=sys.stderr, flush=True)

@@ -111,7 +111,16 @@ typedef struct {
   int32_t sigma_every; /* apply the sigma rule of Section 4.4 after every
                         sigma_every-th iteration (the paper gives no cadence);
                         default 2 (1 = every iteration)                        */
-  int32_t reserved_p;
+  int32_t representer; /* dwd_solve / dwd_serve: 1 = representer iteration:
+                        w, u, rho stay in range(Z~) (zero start, T = 0), so
+                        they are carried as n-vectors (w~ = Z~ a_w, ...) and
+                        every d-space norm of Steps 2-3 and Section 4.3 is an
+                        n-space quadratic form with G~; an iteration reads
+                        only the n x n matrices, and Z is streamed once at the
+                        end (w = Z~ a_w) and by the final FP64 check.  Same
+                        iterates as 0 in exact arithmetic.  0 (default) = one
+                        pass over Z per iteration.  BF16 storage is not used
+                        by the iteration in this mode.                         */
 } dwd_params;
 
 /* Per-solve report.  Residuals are those of Section 4.3 on the scaled

@@ -51,7 +51,7 @@ int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz
   const int64_t nn = (int64_t)n * n * 8;
   b += 2 * nn;                                          // G~, M^-1
   if (storage == DWD_BF16 && layout != DWD_CSR) b += 2 * nn + (int64_t)n * 8;  // BF16 factor
-  b += (int64_t)n * 8 * 24 + ld * 8 * 3;                // vectors
+  b += (int64_t)n * 8 * 27 + ld * 8 * 3;                // vectors
   b += (ld / kLdAlign) * 2 * (int64_t)n * 8;            // pass partials
   const int splits = gram_splits(ld, n);
   b += std::max<int64_t>((int64_t)splits * nn, nn);     // set-up scratch (Gram / inverse)
@@ -394,9 +394,9 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
 hipError_t Problem::alloc_iter_buffers() {
   const int n_ = n;
   hipError_t e;
-  // 24 n-vectors
+  // 27 n-vectors
   double* nb = nullptr;
-  if ((e = alloc((void**)&nb, (size_t)n_ * 8 * 24)) != hipSuccess) return e;
+  if ((e = alloc((void**)&nb, (size_t)n_ * 8 * 27)) != hipSuccess) return e;
   double* q = nb;
   auto take = [&](double*& dst) {
     dst = q;
@@ -405,6 +405,7 @@ hipError_t Problem::alloc_iter_buffers() {
   take(ip.r); take(ip.xi); take(ip.alpha); take(ip.Pu); take(ip.Prho); take(ip.t); take(ip.x);
   take(ip.f); take(ip.s); take(ip.v); take(ip.dr); take(ip.hG); take(ip.rn); take(ip.s1);
   take(ip.v1); take(ip.xi0); take(ip.xi1); take(ip.al0); take(ip.al1);
+  take(ip.au); take(ip.arho); take(ip.aw);
   double* db = nullptr;
   if ((e = alloc((void**)&db, (size_t)ld * 8 * 3)) != hipSuccess) return e;
   ip.u = db;
@@ -412,7 +413,8 @@ hipError_t Problem::alloc_iter_buffers() {
   ip.w = db + 2 * ld;
   nchunks = (int)(ld / kLdAlign);
   if ((e = alloc((void**)&ip.partT, (size_t)nchunks * 2 * n_ * 8)) != hipSuccess) return e;
-  const int npb = std::max(pass2_blocks(DWD_FP64, ld), 1);  // FP64 has the most blocks
+  // partials of the pass (FP64 has the most blocks) or of the representer step
+  const int npb = std::max({pass2_blocks(DWD_FP64, ld), csr_pass_blocks(ld), ngemv_blocks(n_), 1});
   if ((e = alloc((void**)&ip.part_g, (size_t)npb * NP2 * 8)) != hipSuccess) return e;
   if ((e = alloc((void**)&ip.part_n1, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
   if ((e = alloc((void**)&ip.part_it, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
@@ -467,7 +469,7 @@ Consts make_consts(const Problem* P, const dwd_params* p) {
   c.rho_residual = p->rho_residual ? 1 : 0;
   c.qkind = qkind_of(p->q);
   c.sigma_every = p->sigma_every;
-  c.pad_c = 0;
+  c.representer = p->representer ? 1 : 0;
   return c;
 }
 
@@ -489,6 +491,20 @@ hipError_t Problem::queue_iteration(const Consts& c, const void* Xit, int st_it,
   const hipStream_t s = stream;
   // The BF16 phase iterates on the BF16 image with that image's own factor.
   const IterPtrs& I = st_it == DWD_BF16 ? ip_lp : ip;
+  if (c.representer) {
+    // Representer iteration: no pass over Z.  A fresh start anchors
+    // Z~^T u = G~ au and Z~^T rho = G~ arho exactly.
+    if (fresh) {
+      if ((e = launch_ngemv(n, I.G, I.au, I.Pu, I.G, I.arho, I.Prho, nullptr, nullptr, I.sc, s)) !=
+          hipSuccess)
+        return e;
+    }
+    if ((e = launch_rhs(c, I, nchunks, 0, s)) != hipSuccess) return e;
+    if ((e = launch_step1ab(c, I, s)) != hipSuccess) return e;
+    if ((e = launch_step1c_rows(c, I, s)) != hipSuccess) return e;
+    if ((e = launch_rep_step(c, I, s)) != hipSuccess) return e;
+    return launch_tail(c, I, ngemv_blocks(n), s);
+  }
   if (fresh) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile) {
@@ -523,6 +539,35 @@ hipError_t Problem::queue_iteration(const Consts& c, const void* Xit, int st_it,
   }
   const int nblk = layout == DWD_CSR ? csr_pass_blocks(ld) : pass2_blocks(st_it, ld);
   return launch_tail(c, I, nblk, s);
+}
+
+hipError_t Problem::expand() {
+  Consts c{};
+  c.d = d;
+  c.ld = ld;
+  c.n = n;
+  c.inv_zs = 1.0 / zscale;
+  if (layout == DWD_CSR) return launch_csr_expand(ipX, ixX, valX, csr_dtype, d, c, ip, stream);
+  return launch_expand(X_rec, st_rec, c, ip, stream);
+}
+
+hipError_t Problem::dres(const Consts& c, const double* alpha, const double* rho, double* part,
+                        int* nblk) {
+  if (layout == DWD_CSR) {
+    *nblk = csr_pass_blocks(ld);
+    return launch_csr_dres(ipX, ixX, valX, csr_dtype, d, c, alpha, y, rho, part, stream);
+  }
+  *nblk = dres_blocks(st_rec, ld);
+  return launch_dres(X_rec, st_rec, c, alpha, y, rho, part, stream);
+}
+
+hipError_t Problem::queue_check(const Consts& c) {
+  hipError_t e;
+  if (c.representer && (e = expand()) != hipSuccess) return e;
+  if ((e = pass_T(ip.w, ip.rho, nullptr)) != hipSuccess) return e;
+  int nblk = 0;
+  if ((e = dres(c, ip.alpha, ip.rho, ip.part_g, &nblk)) != hipSuccess) return e;
+  return launch_check(c, ip, nchunks, ip.part_g, nblk, stream);
 }
 
 hipError_t Problem::pass_T(const double* v1, const double* v2, const Scal* sc) {
@@ -610,7 +655,7 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
   const bool profile = p->profile != 0;
   const int check_every = p->check_every > 0 ? p->check_every : 8;
   int iters_lowp = 0;
-  if (P->storage == DWD_BF16) {
+  if (P->storage == DWD_BF16 && !c.representer) {
     // Phase 1 on the BF16 image, to the looser tolerance.
     const Consts c1 = lowp_consts(P, p);
     HIP_TRY(P->run_loop(c1, P->X_lowp, DWD_BF16, p->resync, check_every, profile, 0));
@@ -632,16 +677,13 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
   Scal hs;
   int resumed = 0;
   for (;;) {
-    HIP_TRY(P->pass_T(P->ip.w, P->ip.rho, nullptr));
-    HIP_TRY(launch_ngemv(P->n, P->G, P->ip.alpha, P->ip.hG, nullptr, nullptr, nullptr, nullptr,
-                         nullptr, nullptr, st));
-    HIP_TRY(launch_check(c, P->ip, P->nchunks, st));
+    HIP_TRY(P->queue_check(c));
     HIP_TRY(hipMemcpyAsync(&hs, P->ip.sc, sizeof(Scal), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const double chk = std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]);
     // (BF16 storage without refinement: the check only reports the residual
     // of the BF16 solution against the data of record.)
-    const bool no_refine = P->storage == DWD_BF16 && !p->refine;
+    const bool no_refine = P->storage == DWD_BF16 && !p->refine && !c.representer;
     if (!hs.converged || chk < p->tol || resumed >= 2 || hs.k >= p->max_iter || no_refine) break;
     ++resumed;
     hipLaunchKernelGGL(k_reset_done, dim3(1), dim3(1), 0, st, P->ip.sc);

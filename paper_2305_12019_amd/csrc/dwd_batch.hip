@@ -21,7 +21,7 @@ hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, con
                                   const int* idx, int bact, int tile, hipStream_t st,
                                   hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_check_b(const BatchPtrs& P, int p, const double* partT, int nchunks,
-                          hipStream_t st);
+                          const double* part_dres, int nblk, hipStream_t st);
 hipError_t launch_resume_b(const BatchPtrs& P, const int* idx, int cnt, hipStream_t st);
 hipError_t launch_anchor_b(const BatchPtrs& P, int p, const double* partT, int nchunks,
                            hipStream_t st);
@@ -375,7 +375,10 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
       const int j = list[i];
       HIP_TRY_B(launch_gemvT(P->X_rec, P->st_rec, ld, n, bp.W + (size_t)j * ld,
                              bp.RHO + (size_t)j * ld, P->ip.partT, nullptr, st));
-      HIP_TRY_B(launch_check_b(bp, j, P->ip.partT, P->nchunks, st));
+      int nblk = 0;
+      HIP_TRY_B(P->dres(hcs[j], bp.AL + (size_t)j * n, bp.RHO + (size_t)j * ld, P->ip.part_g,
+                        &nblk));
+      HIP_TRY_B(launch_check_b(bp, j, P->ip.partT, P->nchunks, P->ip.part_g, nblk, st));
     }
     HIP_TRY_B(hipMemcpyAsync(hsc[0], bp.sc, (size_t)B * sizeof(Scal), hipMemcpyDeviceToHost, st));
     HIP_TRY_B(hipStreamSynchronize(st));

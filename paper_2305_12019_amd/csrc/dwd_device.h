@@ -228,17 +228,18 @@ __device__ __forceinline__ Step2Plan step2_plan_finish(const Consts& c, const do
 // Residuals of Section 4.3 from the reduced sums r[], computed in registers.
 __device__ __forceinline__ void finish_etas(const Consts& c, const double* r, double* e) {
   const double den = c.opC;
+  // (squared norms that are quadratic forms in n-space can round below 0)
   e[E_P1] = sqrt(r[R_PRES2]) / den;
-  e[E_P2] = c.sqmu * sqrt(r[R_WU2]) / den;
-  e[E_P3] = fmax(sqrt(r[R_W2]) - c.R, 0.0) / den;
+  e[E_P2] = c.sqmu * sqrt(fmax(r[R_WU2], 0.0)) / den;
+  e[E_P3] = fmax(sqrt(fmax(r[R_W2], 0.0)) - c.R, 0.0) / den;
   e[E_D1] = sqrt(r[R_AMIN2]) / den;
   e[E_D2] = sqrt(r[R_AMAX2]) / den;
-  e[E_D3] = sqrt(r[R_DRES2]) / den;
+  e[E_D3] = sqrt(fmax(r[R_DRES2], 0.0)) / den;
   e[E_C1] = fabs(r[R_YA]) / den;
   e[E_C2] = fabs(r[R_XCA]) / den;
   e[E_C3] = r[R_COMP2] / den;
   const double prim = r[R_SUMRQ] + c.C * r[R_SUMXI];
-  const double dual = c.kappa * r[R_SUMAQ] - c.R * sqrt(r[R_ZA2]);
+  const double dual = c.kappa * r[R_SUMAQ] - c.R * sqrt(fmax(r[R_ZA2], 0.0));
   e[E_PRIM] = prim;
   e[E_DUAL] = dual;
   e[E_GAP] = fabs(prim - dual) / (1.0 + fabs(prim) + fabs(dual));

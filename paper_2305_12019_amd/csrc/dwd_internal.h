@@ -87,7 +87,7 @@ struct Consts {
   int32_t rho_residual;
   int32_t qkind;       // 1,2,4: integer q; 5: q = 0.5; 0: general
   int32_t sigma_every; // the sigma rule runs after iterations k with k % sigma_every == 0
-  int32_t pad_c;
+  int32_t representer; // 1: d-vectors carried as n-vector coefficients (w~ = Z~ a_w, ...)
   double sigma0;       // initial sigma (used by the batched initialiser)
 };
 
@@ -99,6 +99,7 @@ struct IterPtrs {
   const double* G;
   double *r, *xi, *alpha, *Pu, *Prho, *t, *x, *f, *s, *v, *dr, *hG, *rn;
   double *s1, *v1, *xi0, *xi1, *al0, *al1;  // the two outcomes of Step 1c
+  double *au, *arho, *aw;  // representer coefficients: u~ = Z~ au, rho = Z~ arho, w~ = Z~ aw
   double *u, *rho, *w;  // d-space, length ld
   double *part_g;       // pass partials (NP2 per block)
   double *part_n1;      // Step 1b block partials of y^T dr

@@ -75,7 +75,7 @@ void destroy_slot(Slot& s) {
 // Queue up to `chunk` iterations of the current phase and the flag copy.
 hipError_t queue_chunk(Slot& s, int chunk) {
   Problem* P = s.P;
-  const bool lowp = (s.phase == MAIN && P->storage == DWD_BF16);
+  const bool lowp = (s.phase == MAIN && P->storage == DWD_BF16 && !s.c.representer);
   const Consts& c = lowp ? s.c_lowp : s.c;
   const void* X = lowp ? P->X_lowp : P->X_rec;
   const int st_it = lowp ? DWD_BF16 : P->st_rec;
@@ -97,11 +97,7 @@ hipError_t queue_chunk(Slot& s, int chunk) {
 hipError_t queue_check(Slot& s) {
   Problem* P = s.P;
   hipError_t e;
-  if ((e = P->pass_T(P->ip.w, P->ip.rho, nullptr)) != hipSuccess) return e;
-  if ((e = launch_ngemv(P->n, P->G, P->ip.alpha, P->ip.hG, nullptr, nullptr, nullptr, nullptr,
-                        nullptr, nullptr, s.stream)) != hipSuccess)
-    return e;
-  if ((e = launch_check(s.c, P->ip, P->nchunks, s.stream)) != hipSuccess) return e;
+  if ((e = P->queue_check(s.c)) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(s.hs, P->ip.sc, sizeof(Scal), hipMemcpyDeviceToHost, s.stream)) !=
       hipSuccess)
     return e;
@@ -125,8 +121,9 @@ hipError_t advance(Slot& s, int chunk) {
   switch (s.phase) {
     case MAIN:
       if (s.queued > 0 && (hs.done || s.k_base + s.queued >= s.prm.max_iter)) {
-        if (s.P->storage == DWD_BF16) s.iters_lowp = hs.k;
-        if (s.P->storage == DWD_BF16 && s.prm.refine && hs.k < s.prm.max_iter) {
+        const bool bf16 = s.P->storage == DWD_BF16 && !s.c.representer;
+        if (bf16) s.iters_lowp = hs.k;
+        if (bf16 && s.prm.refine && hs.k < s.prm.max_iter) {
           hipError_t e = start_phase(s, REFINE);
           if (e != hipSuccess) return e;
           return queue_chunk(s, chunk);
@@ -144,7 +141,7 @@ hipError_t advance(Slot& s, int chunk) {
       return queue_chunk(s, chunk);
     case CHECK: {
       const double chk = std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]);
-      const bool no_refine = s.P->storage == DWD_BF16 && !s.prm.refine;
+      const bool no_refine = s.P->storage == DWD_BF16 && !s.prm.refine && !s.c.representer;
       if (hs.converged && chk >= s.prm.tol && s.resumed < 2 && hs.k < s.prm.max_iter &&
           !no_refine) {
         ++s.resumed;

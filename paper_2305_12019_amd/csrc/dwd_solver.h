@@ -24,7 +24,14 @@ hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterP
                         hipStream_t st);
 int pass2_blocks(int storage, int64_t ld);
 hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, hipStream_t st);
-hipError_t launch_check(const Consts& c, const IterPtrs& p, int nchunks, hipStream_t st);
+hipError_t launch_check(const Consts& c, const IterPtrs& p, int nchunks, const double* part_dres,
+                        int nblk, hipStream_t st);
+hipError_t launch_dres(const void* X, int storage, const Consts& c, const double* alpha,
+                       const double* y, const double* rho, double* part, hipStream_t st);
+int dres_blocks(int storage, int64_t ld);
+hipError_t launch_csr_dres(const int64_t* ip, const int32_t* ix, const void* val, int dtype,
+                           int64_t d, const Consts& c, const double* alpha, const double* y,
+                           const double* rho, double* part, hipStream_t st);
 bool iter_ptrs_ok(const IterPtrs& p);
 hipError_t launch_csr_frob(const void* val, int dtype, int64_t nnz, double* part, int nblk,
                            hipStream_t st);
@@ -37,6 +44,11 @@ hipError_t launch_csr_pass(const int64_t* ip, const int32_t* ix, const void* val
                            int64_t d, const Consts& c, const IterPtrs& p, hipStream_t st);
 int csr_pass_blocks(int64_t ld);
 hipError_t launch_norm2(const double* v, int64_t m, double* out, hipStream_t st);
+hipError_t launch_rep_step(const Consts& c, const IterPtrs& p, hipStream_t st);
+hipError_t launch_expand(const void* X, int storage, const Consts& c, const IterPtrs& p,
+                         hipStream_t st);
+hipError_t launch_csr_expand(const int64_t* ip, const int32_t* ix, const void* val, int dtype,
+                             int64_t d, const Consts& c, const IterPtrs& p, hipStream_t st);
 
 struct Problem {
   int device = 0;
@@ -94,6 +106,15 @@ struct Problem {
                       bool profile, int k_start);
   // Z~^T [v1, v2] over the data of record into ip.partT (dense or CSR).
   hipError_t pass_T(const double* v1, const double* v2, const Scal* sc);
+  // Representer mode: w, u, rho in d-space from their coefficients.
+  hipError_t expand();
+  // Explicit ||Z~ alpha + D rho||^2 partials of (alpha, rho) over the data of
+  // record into part; returns the number of partials in *nblk.
+  hipError_t dres(const Consts& c, const double* alpha, const double* rho, double* part,
+                  int* nblk);
+  // The final FP64 check of the single solve (expansion in representer
+  // mode, Z~^T w pass, explicit dual residual, k_check), queued on stream.
+  hipError_t queue_check(const Consts& c);
   hipEvent_t next_event(int kind, int k);
 };
 

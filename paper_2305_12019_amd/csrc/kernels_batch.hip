@@ -847,34 +847,30 @@ int batch_pass_row_blocks(int64_t ld) { return (int)(ld / BT_M); }
 namespace dwd {
 
 // Final FP64 check of problem p (as k_check): partT holds the pass over the
-// data of record with v1 = w~_p, v2 = rho_p; HA holds G~ alpha_p.
+// data of record with v1 = w~_p; part_dres the explicit ||Z~ alpha_p +
+// D rho_p||^2 partials (nblk of them).
 __global__ void __launch_bounds__(512) k_check_b(BatchPtrs P, int p, const double* partT,
-                                                 int nchunks) {
+                                                 int nchunks, const double* part_dres,
+                                                 int nblk) {
   Scal* sc = P.sc + p;
   const Consts c = P.cs[p];
   const size_t on = (size_t)p * P.n;
-  double acc[3] = {0, 0, 0};
+  double acc[2] = {0, 0};
   const double beta = sc->beta;
   for (int i = threadIdx.x; i < c.n; i += 512) {
-    double sw = 0.0, sr = 0.0;
-    for (int ch = 0; ch < nchunks; ++ch) {
-      sw += partT[((int64_t)ch * 2) * c.n + i];
-      sr += partT[((int64_t)ch * 2 + 1) * c.n + i];
-    }
+    double sw = 0.0;
+    for (int ch = 0; ch < nchunks; ++ch) sw += partT[((int64_t)ch * 2) * c.n + i];
     const double yi = P.y[i];
     const double pres = yi * sw * c.inv_zs + beta * yi + P.XI[on + i] - P.R[on + i];
-    const double a = P.AL[on + i];
     acc[0] += pres * pres;
-    acc[1] += a * P.HA[on + i];
-    acc[2] += a * yi * sr * c.inv_zs;
   }
-  block_sum_k<512, 3>(acc);
+  for (int b = threadIdx.x; b < nblk; b += 512) acc[1] += part_dres[b];
+  block_sum_k<512, 2>(acc);
   if (threadIdx.x == 0) {
     const double den = c.opC;
     const double* e = sc->eta;
     const double p1 = sqrt(acc[0]) / den;
-    const double dres2 = acc[1] + 2.0 * c.sqmu * acc[2] + c.mu * sc->red[R_RHO2];
-    const double d3 = sqrt(fmax(dres2, 0.0)) / den;
+    const double d3 = sqrt(acc[1]) / den;
     sc->eta[E_PCHK] = fmax(p1, fmax(e[E_P2], e[E_P3]));
     sc->eta[E_DCHK] = fmax(e[E_D1], fmax(e[E_D2], c.rho_residual ? d3 : 0.0));
   }
@@ -924,8 +920,8 @@ hipError_t launch_resume_b(const BatchPtrs& P, const int* idx, int cnt, hipStrea
 }
 
 hipError_t launch_check_b(const BatchPtrs& P, int p, const double* partT, int nchunks,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_check_b, dim3(1), dim3(512), 0, st, P, p, partT, nchunks);
+                          const double* part_dres, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_b, dim3(1), dim3(512), 0, st, P, p, partT, nchunks, part_dres, nblk);
   return hipGetLastError();
 }
 

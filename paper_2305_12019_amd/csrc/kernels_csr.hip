@@ -169,6 +169,83 @@ __global__ void __launch_bounds__(CSR_T) k_csr_pass(const int64_t* __restrict__ 
   if (threadIdx.x < NP2) p.part_g[(size_t)blockIdx.x * NP2 + threadIdx.x] = acc[threadIdx.x];
 }
 
+// Expansion of the representer coefficients over CSR(X): w~ = Z~ aw,
+// u~ = Z~ au, rho = Z~ arho, one thread per feature row k < ld.
+template <typename T>
+__global__ void __launch_bounds__(CSR_T) k_csr_expand(const int64_t* __restrict__ ip,
+                                                      const int32_t* __restrict__ ix,
+                                                      const T* __restrict__ val, int64_t d,
+                                                      Consts c, IterPtrs p) {
+  const int64_t k = (int64_t)blockIdx.x * CSR_T + threadIdx.x;
+  if (k >= c.ld) return;
+  double w = 0.0, u = 0.0, r = 0.0;
+  if (k < d) {
+    for (int64_t e = ip[k]; e < ip[k + 1]; ++e) {
+      const int i = ix[e];
+      const double x = (double)val[e] * p.y[i] * c.inv_zs;
+      w = fma(x, p.aw[i], w);
+      u = fma(x, p.au[i], u);
+      r = fma(x, p.arho[i], r);
+    }
+  }
+  p.w[k] = w;
+  p.u[k] = u;
+  p.rho[k] = r;
+}
+
+hipError_t launch_csr_expand(const int64_t* ip, const int32_t* ix, const void* val, int dtype,
+                             int64_t d, const Consts& c, const IterPtrs& p, hipStream_t st) {
+  if (!ip || !ix || !val) return hipErrorInvalidValue;
+  const int nb = (int)((c.ld + CSR_T - 1) / CSR_T);
+  if (dtype == DWD_FP64)
+    hipLaunchKernelGGL(k_csr_expand<double>, dim3(nb), dim3(CSR_T), 0, st, ip, ix,
+                       (const double*)val, d, c, p);
+  else
+    hipLaunchKernelGGL(k_csr_expand<float>, dim3(nb), dim3(CSR_T), 0, st, ip, ix,
+                       (const float*)val, d, c, p);
+  return hipGetLastError();
+}
+
+// Explicit ||Z~ alpha + D rho||^2 for the final check over CSR(X): one thread
+// per feature row, per-block partials.
+template <typename T>
+__global__ void __launch_bounds__(CSR_T) k_csr_dres(const int64_t* __restrict__ ip,
+                                                    const int32_t* __restrict__ ix,
+                                                    const T* __restrict__ val, int64_t d,
+                                                    Consts c, const double* __restrict__ alpha,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ rho,
+                                                    double* __restrict__ part) {
+  const int64_t k = (int64_t)blockIdx.x * CSR_T + threadIdx.x;
+  double s2 = 0.0;
+  if (k < c.ld) {
+    double za = 0.0;
+    if (k < d)
+      for (int64_t e = ip[k]; e < ip[k + 1]; ++e) {
+        const int i = ix[e];
+        za = fma((double)val[e] * y[i] * c.inv_zs, alpha[i], za);
+      }
+    const double dr = za + c.sqmu * rho[k];
+    s2 = dr * dr;
+  }
+  s2 = block_sum<CSR_T>(s2);
+  if (threadIdx.x == 0) part[blockIdx.x] = s2;
+}
+
+hipError_t launch_csr_dres(const int64_t* ip, const int32_t* ix, const void* val, int dtype,
+                           int64_t d, const Consts& c, const double* alpha, const double* y,
+                           const double* rho, double* part, hipStream_t st) {
+  if (!ip || !ix || !val || !alpha || !y || !rho || !part) return hipErrorInvalidValue;
+  const int nb = (int)((c.ld + CSR_T - 1) / CSR_T);
+  if (dtype == DWD_FP64)
+    hipLaunchKernelGGL(k_csr_dres<double>, dim3(nb), dim3(CSR_T), 0, st, ip, ix,
+                       (const double*)val, d, c, alpha, y, rho, part);
+  else
+    hipLaunchKernelGGL(k_csr_dres<float>, dim3(nb), dim3(CSR_T), 0, st, ip, ix,
+                       (const float*)val, d, c, alpha, y, rho, part);
+  return hipGetLastError();
+}
+
 int csr_pass_blocks(int64_t ld) { return (int)((ld + CSR_T - 1) / CSR_T); }
 
 hipError_t launch_csr_pass(const int64_t* ip, const int32_t* ix, const void* val, int dtype,

@@ -90,8 +90,8 @@ static hipError_t gemvT_t(const void* X, int64_t ld, int n, const double* v1, co
 bool iter_ptrs_ok(const IterPtrs& p) {
   const void* req[] = {p.y, p.my, p.Minv, p.G, p.r, p.xi, p.alpha, p.Pu, p.Prho, p.t, p.x,
                        p.f, p.s, p.v, p.dr, p.hG, p.rn, p.s1, p.v1, p.xi0, p.xi1, p.al0,
-                       p.al1, p.u, p.rho, p.w, p.part_g, p.part_n1, p.part_it, p.part_c,
-                       p.partT, p.sc};
+                       p.al1, p.au, p.arho, p.aw, p.u, p.rho, p.w, p.part_g, p.part_n1,
+                       p.part_it, p.part_c, p.partT, p.sc};
   for (const void* q : req)
     if (!q) return false;
   return true;
@@ -116,6 +116,9 @@ __global__ void k_init(Consts c, IterPtrs p, double sigma0) {
     p.alpha[i] = 0.0;
     p.Pu[i] = 0.0;
     p.Prho[i] = 0.0;
+    p.au[i] = 0.0;
+    p.arho[i] = 0.0;
+    p.aw[i] = 0.0;
   }
   if (i < c.ld) {
     p.u[i] = 0.0;
@@ -612,6 +615,183 @@ hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterP
 }
 
 // ---------------------------------------------------------------------------
+// Representer iteration (params.representer): with a zero start and T = 0,
+// every d-vector stays in range(Z~) (Steps 2-3 combine u, rho and
+// w = (b - Z~ s)/mu linearly), so the pass is replaced by n-space algebra on
+// the coefficients u~ = Z~ au, rho = Z~ arho, w~ = Z~ aw:
+//   aw = au + arho/(sigma sqrt(mu)) - s/mu,   Z~^T w~ = v - beta y,
+//   au' = gamma (aw - arho/(sigma sqrt(mu))),  arho' = arho - tau sigma sqrt(mu) (aw - au'),
+// with Z~^T u' and Z~^T rho' from the recurrences the tail also applies, and
+// every d-space norm as a dot product of a coefficient vector with its image
+// under G~: ||Z~ a||^2 = a^T (G~ a).  The one n x n product per iteration is
+// G~ alpha' (for ||Z~ alpha'|| and ||Z~ alpha' + D rho'||).  One wave per
+// row; the block partials have the layout of the pass's (NP2).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rep_step(Consts c, IterPtrs p) {
+  Scal* sc = p.sc;
+  if (sc->done) return;
+  const Step2Plan pl = step2_plan<256>(c, p);
+  const int o = pl.redo;
+  const double* al = o ? p.al1 : p.al0;
+  const double* so = o ? p.s1 : p.s;
+  const double sigma = sc->sigma;
+  const double gamma = pl.gamma;
+  const double gr = 1.0 / (sigma * c.sqmu);
+  const double rs = c.tau * sigma * c.sqmu;
+  // Staged in LDS for the block's rows: alpha' and cv = alpha' + sqrt(mu) arho',
+  // the coefficients of Z~ alpha' + D rho'.  ||Z~ alpha' + D rho'||^2 is then
+  // the quadratic form cv^T G~ cv of one vector (no cancellation between
+  // separately rounded terms near the solution, where the residual is tiny).
+  __shared__ double s_al[PANEL], s_cv[PANEL];
+  __shared__ double ws[4][NP2];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int row = blockIdx.x * 4 + wid;
+  double h = 0.0, g = 0.0;
+  for (int pc = 0; pc < c.n; pc += PANEL) {
+    const int pn = min(PANEL, c.n - pc);
+    __syncthreads();
+    for (int j = threadIdx.x; j < pn; j += 256) {
+      const int jj = pc + j;
+      const double au = p.au[jj], ar = p.arho[jj], sj = so[jj];
+      const double aw = au + gr * ar - sj / c.mu;
+      const double au1 = gamma * (aw - gr * ar);
+      const double ar1 = ar - rs * (aw - au1);
+      s_al[j] = al[jj];
+      s_cv[j] = al[jj] + c.sqmu * ar1;
+    }
+    __syncthreads();
+    if (row < c.n) {
+      const double* Ar = p.G + (size_t)row * c.n + pc;
+      for (int j = lane; j < pn; j += 64) {
+        const double m = Ar[j];
+        h = fma(m, s_al[j], h);
+        g = fma(m, s_cv[j], g);
+      }
+    }
+  }
+  h = wave_sum(h);
+  g = wave_sum(g);
+  double acc[NP2] = {0, 0, 0, 0, 0, 0};
+  if (row < c.n && lane == 0) {
+    const double beta = o ? sc->beta1 : sc->beta_bar;
+    const double s = so[row];
+    const double v = o ? p.v1[row] : p.v[row];
+    const double au = p.au[row], ar = p.arho[row];
+    const double pr = p.Prho[row];
+    const double aw = au + gr * ar - s / c.mu;
+    const double gaw = v - beta * p.y[row];
+    const double au1 = gamma * (aw - gr * ar);
+    const double pu1 = gamma * (gaw - gr * pr);
+    const double ar1 = ar - rs * (aw - au1);
+    const double pr1 = pr - rs * (gaw - pu1);
+    p.aw[row] = aw;
+    p.au[row] = au1;
+    p.arho[row] = ar1;
+    const double a = al[row];
+    acc[0] = (aw - au1) * (gaw - pu1);           // ||w - u||^2
+    acc[1] = aw * gaw;                           // ||w||^2
+    acc[2] = (a + c.sqmu * ar1) * g;             // ||Z~ alpha + D rho||^2
+    acc[3] = a * h;                              // ||Z~ alpha||^2
+    acc[4] = ar1 * pr1;                          // ||rho||^2
+    acc[5] = au1 * pu1;                          // ||u||^2
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NP2; ++j) ws[wid][j] = acc[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < NP2) {
+    const int j = threadIdx.x;
+    p.part_g[(size_t)blockIdx.x * NP2 + j] = (ws[0][j] + ws[1][j]) + (ws[2][j] + ws[3][j]);
+  }
+}
+
+hipError_t launch_rep_step(const Consts& c, const IterPtrs& p, hipStream_t st) {
+  if (!iter_ptrs_ok(p)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_rep_step, dim3(ngemv_blocks(c.n)), dim3(256), 0, st, c, p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Expansion of the representer coefficients: out_j = Z~ a_j (j < 3) row by
+// row, the label signs and 1/Z_scale folded into the staged coefficients.
+// 64 V rows per block of 4 waves; the waves split the columns.
+// ---------------------------------------------------------------------------
+constexpr int EX_PANEL = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_expand(const T* __restrict__ X, Consts c,
+                                                const double* __restrict__ a0,
+                                                const double* __restrict__ a1,
+                                                const double* __restrict__ a2,
+                                                const double* __restrict__ y,
+                                                double* __restrict__ o0, double* __restrict__ o1,
+                                                double* __restrict__ o2) {
+  constexpr int V = Vec<T>::N;
+  constexpr int ROWS = 64 * V;
+  __shared__ double sv[3][EX_PANEL];
+  __shared__ double red[4][3][ROWS];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t rbase = (int64_t)blockIdx.x * ROWS;
+  const T* xrow = X + rbase + lane * V;
+  double acc[3][V];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc[j][e] = 0.0;
+  for (int pc = 0; pc < c.n; pc += EX_PANEL) {
+    const int pn = min(EX_PANEL, c.n - pc);
+    for (int i = threadIdx.x; i < pn; i += 256) {
+      const double yz = y[pc + i] * c.inv_zs;
+      sv[0][i] = yz * a0[pc + i];
+      sv[1][i] = yz * a1[pc + i];
+      sv[2][i] = yz * a2[pc + i];
+    }
+    __syncthreads();
+    const int per = (pn + 3) / 4;
+    const int j0 = wid * per, j1 = min(pn, j0 + per);
+    for (int j = j0; j < j1; ++j) {
+      double x[V];
+      Vec<T>::load(xrow + (int64_t)(pc + j) * c.ld, x);
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[q][e] = fma(x[e], sv[q][j], acc[q][e]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int e = 0; e < V; ++e) red[wid][q][lane * V + e] = acc[q][e];
+  __syncthreads();
+  for (int rr = threadIdx.x; rr < ROWS; rr += 256) {
+    const int64_t k = rbase + rr;
+    double* outs[3] = {o0, o1, o2};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double v = (red[0][q][rr] + red[1][q][rr]) + (red[2][q][rr] + red[3][q][rr]);
+      outs[q][k] = v;
+    }
+  }
+}
+
+// w~ = Z~ aw, u~ = Z~ au, rho = Z~ arho over dense storage.
+hipError_t launch_expand(const void* X, int storage, const Consts& c, const IterPtrs& p,
+                         hipStream_t st) {
+  if (!X || !iter_ptrs_ok(p) || c.ld % kLdAlign != 0) return hipErrorInvalidValue;
+  if (storage == DWD_FP64)
+    hipLaunchKernelGGL(k_expand<double>, dim3((unsigned)(c.ld / 128)), dim3(256), 0, st,
+                       (const double*)X, c, p.aw, p.au, p.arho, p.y, p.w, p.u, p.rho);
+  else if (storage == DWD_FP32)
+    hipLaunchKernelGGL(k_expand<float>, dim3((unsigned)(c.ld / 256)), dim3(256), 0, st,
+                       (const float*)X, c, p.aw, p.au, p.arho, p.y, p.w, p.u, p.rho);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Residuals of Section 4.3, stopping rule, sigma rule of Section 4.4; commit
 // of the Step 1c outcome; recurrences Z~^T u^{k+1} = gamma (Z~^T w - Z~^T rho^k
 // / (sigma sqrt(mu))) and Z~^T rho^{k+1} = Z~^T rho^k - tau sigma sqrt(mu)
@@ -746,40 +926,100 @@ hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, hipStream
 //   eta_P1 check = ||Z~^T w + beta y + xi - r|| / (1+C) with an explicit pass,
 //   eta_D3 check = sqrt(a^T G~ a + 2 sqrt(mu) a^T Z~^T rho + mu ||rho||^2) / (1+C).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(NT1) k_check(Consts c, IterPtrs p, int nchunks) {
+__global__ void __launch_bounds__(NT1) k_check(Consts c, IterPtrs p, int nchunks,
+                                              const double* __restrict__ part_dres, int nblk) {
   Scal* sc = p.sc;
-  double acc[3] = {0, 0, 0};
+  double acc[2] = {0, 0};
   for (int i = threadIdx.x; i < c.n; i += NT1) {
-    double sw = 0.0, sr = 0.0;
-    for (int ch = 0; ch < nchunks; ++ch) {
-      sw += p.partT[((int64_t)ch * 2) * c.n + i];
-      sr += p.partT[((int64_t)ch * 2 + 1) * c.n + i];
-    }
+    double sw = 0.0;
+    for (int ch = 0; ch < nchunks; ++ch) sw += p.partT[((int64_t)ch * 2) * c.n + i];
     const double yi = p.y[i];
     const double ztw = yi * sw * c.inv_zs;
-    const double ztr = yi * sr * c.inv_zs;
     const double pres = ztw + sc->beta * yi + p.xi[i] - p.r[i];
-    const double a = p.alpha[i];
     acc[0] += pres * pres;
-    acc[1] += a * p.hG[i];
-    acc[2] += a * ztr;
   }
-  block_sum_k<NT1, 3>(acc);
+  for (int b = threadIdx.x; b < nblk; b += NT1) acc[1] += part_dres[b];
+  block_sum_k<NT1, 2>(acc);
   if (threadIdx.x == 0) {
     const double den = c.opC;
     const double* e = sc->eta;
     const double p1 = sqrt(acc[0]) / den;
-    const double rho2 = sc->red[R_RHO2];  // ||rho||^2 from the last d-space step
-    const double dres2 = acc[1] + 2.0 * c.sqmu * acc[2] + c.mu * rho2;
-    const double d3 = sqrt(fmax(dres2, 0.0)) / den;
+    const double d3 = sqrt(acc[1]) / den;
     sc->eta[E_PCHK] = fmax(p1, fmax(e[E_P2], e[E_P3]));
     sc->eta[E_DCHK] = fmax(e[E_D1], fmax(e[E_D2], c.rho_residual ? d3 : 0.0));
   }
 }
 
-hipError_t launch_check(const Consts& c, const IterPtrs& p, int nchunks, hipStream_t st) {
-  if (!iter_ptrs_ok(p)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(NT1), 0, st, c, p, nchunks);
+hipError_t launch_check(const Consts& c, const IterPtrs& p, int nchunks, const double* part_dres,
+                        int nblk, hipStream_t st) {
+  if (!iter_ptrs_ok(p) || !part_dres) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(NT1), 0, st, c, p, nchunks, part_dres, nblk);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Explicit ||Z~ alpha + D rho||^2 for the final check: za = Z~ alpha row by row
+// (label signs and 1/Z_scale folded into the staged alpha), then per-block
+// partial sums of (za_k + sqrt(mu) rho_k)^2 in d-space.  64 V rows per block
+// of 4 waves; the waves split the columns.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_dres(const T* __restrict__ X, Consts c,
+                                              const double* __restrict__ alpha,
+                                              const double* __restrict__ y,
+                                              const double* __restrict__ rho,
+                                              double* __restrict__ part) {
+  constexpr int V = Vec<T>::N;
+  constexpr int ROWS = 64 * V;
+  __shared__ double sv[EX_PANEL];
+  __shared__ double red[4][ROWS];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t rbase = (int64_t)blockIdx.x * ROWS;
+  const T* xrow = X + rbase + lane * V;
+  double acc[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) acc[e] = 0.0;
+  for (int pc = 0; pc < c.n; pc += EX_PANEL) {
+    const int pn = min(EX_PANEL, c.n - pc);
+    for (int i = threadIdx.x; i < pn; i += 256) sv[i] = y[pc + i] * c.inv_zs * alpha[pc + i];
+    __syncthreads();
+    const int per = (pn + 3) / 4;
+    const int j0 = wid * per, j1 = min(pn, j0 + per);
+    for (int j = j0; j < j1; ++j) {
+      double x[V];
+      Vec<T>::load(xrow + (int64_t)(pc + j) * c.ld, x);
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[e] = fma(x[e], sv[j], acc[e]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < V; ++e) red[wid][lane * V + e] = acc[e];
+  __syncthreads();
+  double s2 = 0.0;
+  for (int rr = threadIdx.x; rr < ROWS; rr += 256) {
+    const double za = (red[0][rr] + red[1][rr]) + (red[2][rr] + red[3][rr]);
+    const double dr = za + c.sqmu * rho[rbase + rr];
+    s2 += dr * dr;
+  }
+  s2 = block_sum<256>(s2);
+  if (threadIdx.x == 0) part[blockIdx.x] = s2;
+}
+
+int dres_blocks(int storage, int64_t ld) { return (int)(ld / (storage == DWD_FP64 ? 128 : 256)); }
+
+hipError_t launch_dres(const void* X, int storage, const Consts& c, const double* alpha,
+                       const double* y, const double* rho, double* part, hipStream_t st) {
+  if (!X || !alpha || !y || !rho || !part || c.ld % kLdAlign != 0) return hipErrorInvalidValue;
+  const int nb = dres_blocks(storage, c.ld);
+  if (storage == DWD_FP64)
+    hipLaunchKernelGGL(k_dres<double>, dim3(nb), dim3(256), 0, st, (const double*)X, c, alpha, y,
+                       rho, part);
+  else if (storage == DWD_FP32)
+    hipLaunchKernelGGL(k_dres<float>, dim3(nb), dim3(256), 0, st, (const float*)X, c, alpha, y,
+                       rho, part);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

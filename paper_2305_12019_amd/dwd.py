@@ -45,7 +45,7 @@ class Params(C.Structure):
                 ("rho_residual", C.c_int32), ("resync", C.c_int32), ("check_every", C.c_int32),
                 ("refine", C.c_int32), ("lowp_tol", C.c_double), ("profile", C.c_int32),
                 ("batch_fp32", C.c_int32), ("batch_tile", C.c_int32), ("graph", C.c_int32),
-                ("sigma_every", C.c_int32), ("reserved_p", C.c_int32)]
+                ("sigma_every", C.c_int32), ("representer", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -325,3 +325,70 @@ def test_large_bf16_full_size(dwd):
     Pr = float(np.sum(O.reduced_loss(_margins_by_rows(X, y, wr, ref["beta"]), wl.C, wl.q)))
     print("primal objective bf16 %.9g f32 %.9g" % (P, Pr))
     assert abs(P - Pr) <= 1e-4 * abs(Pr)
+
+
+# ---------------------------------------------------------------------------
+# Representer iteration (params.representer = 1): no pass over Z per
+# iteration; the same solution as the pass iteration and the oracle.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,n,q,C,storage", [(5000, 123, 2.0, 3.0, "f32"),
+                                             (3000, 200, 0.5, 0.2, "f64"),
+                                             (700, 50, 1.0, 1.0, "f32"),
+                                             (800, 1100, 1.0, 0.5, "f64")])
+def test_representer_matches_pass_iteration_and_oracle(dwd, d, n, q, C, storage):
+    X, y = synth.random_two_class(d, n, seed=d + n + 7, mean=0.6,
+                                  dtype="f64" if storage == "f64" else "f32")
+    ref = O.solve(X, y, C, q, tol=1e-9, max_iter=20000)
+    P = dwd.Problem(X, y, storage=storage)
+    rep = P.solve(C, q, tol=1e-8, max_iter=20000, representer=1)
+    assert rep["info"]["converged"] == 1 and rep["info"]["stream_launches"] == 0
+    _compare(X, y, C, q, rep, ref)
+    kkt, e = _recomputed_kkt(X, y, C, q, rep)
+    assert kkt <= 2e-8, e
+    # Same iteration as the pass form: at a working tolerance the counts agree
+    # (near 1e-8 the sigma sequence is sensitive to rounding order, and the
+    # counts of any two summation orders can differ by large factors: the
+    # oracle itself needs 603 iterations at 1e-7 and 4196 at 1e-8 on one of
+    # these cases).
+    rep6 = P.solve(C, q, tol=1e-6, max_iter=20000, representer=1)
+    pas6 = P.solve(C, q, tol=1e-6, max_iter=20000)
+    P.close()
+    a, b = rep6["info"]["iters"], pas6["info"]["iters"]
+    assert abs(a - b) <= max(3, 0.10 * b), (a, b)
+    assert np.linalg.norm(rep6["w"] - pas6["w"]) <= 1e-4 * np.linalg.norm(pas6["w"])
+
+
+def test_representer_first_iterates_follow_the_pass_iteration(dwd):
+    """The two forms are the same iteration: after k = 1, 2, 5, 20 iterations
+    the states agree to rounding."""
+    wl = synth.SMALL_F64
+    X, y = synth.two_class(wl.data)
+    P = dwd.Problem(X, y, storage="f64")
+    for k in (1, 2, 5, 20):
+        a = P.solve(wl.C, wl.q, tol=1e-12, max_iter=k, representer=1)
+        b = P.solve(wl.C, wl.q, tol=1e-12, max_iter=k)
+        for key in ("r", "xi", "alpha", "w", "u", "rho"):
+            assert np.allclose(a[key], b[key], rtol=1e-9, atol=1e-12), (k, key)
+        assert abs(a["beta"] - b["beta"]) <= 1e-9 * max(1.0, abs(b["beta"])), k
+    P.close()
+
+
+def test_representer_with_bf16_and_csr_inputs(dwd):
+    # BF16 storage: the iteration never reads Z, so there is no BF16 phase
+    X, y = synth.random_two_class(4000, 150, seed=41, mean=0.6, dtype="f32")
+    r = dwd.solve(X, y, 1.0, 2.0, tol=1e-7, storage="bf16", representer=1, max_iter=20000)
+    assert r["info"]["converged"] == 1 and r["info"]["iters_lowp"] == 0
+    f = dwd.solve(X, y, 1.0, 2.0, tol=1e-7, storage="f32", representer=1, max_iter=20000)
+    assert np.linalg.norm(r["w"] - f["w"]) <= 1e-9 * np.linalg.norm(f["w"])
+    # CSR input
+    req = synth.Request(0, 0.0, d=3000, n=140, q=1.0, C=1.0, layout="csr", storage="f32",
+                        seed=42)
+    ip, ix, val, yc = synth.request_csr_data(req, density=5e-3)
+    Xd = synth.csr_to_dense(ip, ix, val, 3000, np.float64)
+    ref = O.solve(Xd, yc, 1.0, 1.0, tol=1e-9, max_iter=20000)
+    P = dwd.Problem(csr=(ip, ix, val, 3000), y=yc, storage="f32")
+    got = P.solve(1.0, 1.0, tol=1e-8, max_iter=20000, representer=1)
+    P.close()
+    assert got["info"]["converged"] == 1
+    _compare(Xd, yc, 1.0, 1.0, got, ref)
