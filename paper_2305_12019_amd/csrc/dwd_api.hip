@@ -54,7 +54,7 @@ int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz
   b += (int64_t)n * 8 * 27 + ld * 8 * 3;                // vectors
   b += (ld / kLdAlign) * 2 * (int64_t)n * 8;            // pass partials
   const int splits = gram_splits(ld, n);
-  b += std::max<int64_t>((int64_t)splits * nn, nn);     // set-up scratch (Gram / inverse)
+  b += std::max<int64_t>({(int64_t)splits * nn, nn, (int64_t)spd_inverse_work(n) * 8});  // set-up scratch
   return b;
 }
 
@@ -341,7 +341,8 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
       return hip_fail(e2, "hipMalloc(Minv)");
     const int splits = csr ? 1 : gram_splits(ld, n);
     double* Gpart = nullptr;
-    if ((e2 = alloc_tmp((void**)&Gpart, std::max(nn * splits, nn) * 8)) != hipSuccess)
+    if ((e2 = alloc_tmp((void**)&Gpart, std::max({nn * splits, nn, spd_inverse_work(n)}) * 8)) !=
+        hipSuccess)
       return hip_fail(e2, "hipMalloc(Gram partials)");
     if (csr)
       e2 = launch_csr_gram(P->ipT, P->ixT, P->valT, P->csr_dtype, n, Gpart, st);
@@ -494,12 +495,13 @@ hipError_t Problem::queue_iteration(const Consts& c, const void* Xit, int st_it,
   if (c.representer) {
     // Representer iteration: no pass over Z.  A fresh start anchors
     // Z~^T u = G~ au and Z~^T rho = G~ arho exactly.
+    // (Otherwise t and x were formed by the previous tail kernel.)
     if (fresh) {
       if ((e = launch_ngemv(n, I.G, I.au, I.Pu, I.G, I.arho, I.Prho, nullptr, nullptr, I.sc, s)) !=
           hipSuccess)
         return e;
+      if ((e = launch_rhs(c, I, nchunks, 0, s)) != hipSuccess) return e;
     }
-    if ((e = launch_rhs(c, I, nchunks, 0, s)) != hipSuccess) return e;
     if ((e = launch_step1ab(c, I, s)) != hipSuccess) return e;
     if ((e = launch_step1c_rows(c, I, s)) != hipSuccess) return e;
     if ((e = launch_rep_step(c, I, s)) != hipSuccess) return e;

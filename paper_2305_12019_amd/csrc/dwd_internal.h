@@ -190,6 +190,7 @@ hipError_t launch_gram(const void* Xs, int storage, int64_t ld, int n, double* G
 hipError_t launch_gram_finish(const double* Gpart, int splits, int n, const double* y,
                               double inv_zs2, double mu, double* G, double* M, hipStream_t st);
 hipError_t spd_inverse_inplace(double* M, int n, double* work, int* d_status, hipStream_t st);
+size_t spd_inverse_work(int n);  // doubles of work space spd_inverse_inplace needs
 hipError_t launch_gemv_rows(const double* A, int n, const double* x, double* out,
                             hipStream_t st);
 hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipStream_t st);

@@ -393,41 +393,168 @@ static hipError_t gemm(int m, int n, int k, double alpha, const double* A, int l
   return hipGetLastError();
 }
 
-// M (n x n, ld) is overwritten by its inverse; work holds >= n*n doubles.
-static hipError_t spd_inv_rec(double* M, int ld, int n, double* work, int* d_status,
-                              hipStream_t st) {
-  if (n <= LEAF) {
-    hipLaunchKernelGGL(k_spd_leaf_inv, dim3(1), dim3(256), 0, st, M, ld, n, d_status);
-    return hipGetLastError();
+// ---------------------------------------------------------------------------
+// Inverse of the SPD matrix M (n x n, row-major) in place by block sweeps
+// (Gauss-Jordan elimination in the symmetric sign convention) over block
+// columns K of width GJB.  Sweep K, with P = A[K,K]^-1 and R = P A[K,:]:
+//   A[K,K] <- -P,  A[K,J] <- R[:,J],  A[I,K] <- A[I,K] P = R[:,I]^T,
+//   A[I,J] <- A[I,J] - A[I,K] R[:,J]      (I, J != K).
+// Each sweep keeps A symmetric, so one saved row panel serves as the column
+// panel too; sweeping every block leaves -M^-1, negated at the end.  No
+// pivoting: the pivot blocks are Schur complements of the SPD I + G~/mu.
+// ---------------------------------------------------------------------------
+constexpr int GJB = 32;  // pivot block width
+constexpr int GJT = 64;  // output tile edge of the panel and update kernels
+
+// P = A[K,K]^-1 by Gauss-Jordan in one wave: lane i < GJB holds row i of the
+// block in registers (rows beyond m are the identity; lanes >= GJB carry
+// identity rows that no result uses); the pivot row is broadcast by wave
+// shuffles.  Writes P into Pbuf (GJB x GJB, row-major) and -P into A[K,K].
+__global__ void __launch_bounds__(64) k_gj_pivot(double* __restrict__ M, int ld, int k0, int m,
+                                                 double* __restrict__ Pbuf,
+                                                 int* __restrict__ status) {
+  const int i = threadIdx.x;
+  double a[GJB];
+#pragma unroll
+  for (int j = 0; j < GJB; ++j)
+    a[j] = (i < m && j < m) ? M[(size_t)(k0 + i) * ld + k0 + j] : (i == j ? 1.0 : 0.0);
+  bool ok = true;
+#pragma unroll
+  for (int p = 0; p < GJB; ++p) {
+    double rowp[GJB];
+#pragma unroll
+    for (int j = 0; j < GJB; ++j) rowp[j] = __shfl(a[j], p, 64);
+    const double piv = rowp[p];
+    ok = ok && (piv > 0.0);
+    const double ip = 1.0 / piv;
+    if (i == p) {
+#pragma unroll
+      for (int j = 0; j < GJB; ++j) a[j] = (j == p) ? ip : a[j] * ip;
+    } else {
+      const double g = -a[p] * ip;
+#pragma unroll
+      for (int j = 0; j < GJB; ++j) a[j] = (j == p) ? g : fma(g, rowp[j], a[j]);
+    }
   }
-  const int n1 = LEAF * ((n / LEAF + 1) / 2);  // multiple of 64, about n/2
-  const int n2 = n - n1;
-  double* A = M;
-  double* B = M + n1;                  // n1 x n2
-  double* Cm = M + (size_t)n1 * ld + n1;  // n2 x n2
-  double* Lo = M + (size_t)n1 * ld;    // n2 x n1 (lower-left block)
-  double* T = work;                    // n1 x n2, ld n2
-  double* wrk = work + (size_t)n1 * n2;
-  hipError_t e;
-  if ((e = spd_inv_rec(A, ld, n1, wrk, d_status, st)) != hipSuccess) return e;
-  // T = A^-1 B
-  if ((e = gemm(n1, n2, n1, 1.0, A, ld, 0, B, ld, 0, 0.0, T, n2, st)) != hipSuccess) return e;
-  // C -= B^T T
-  if ((e = gemm(n2, n2, n1, -1.0, B, ld, 1, T, n2, 0, 1.0, Cm, ld, st)) != hipSuccess) return e;
-  if ((e = spd_inv_rec(Cm, ld, n2, wrk, d_status, st)) != hipSuccess) return e;
-  // B = -T S^-1
-  if ((e = gemm(n1, n2, n2, -1.0, T, n2, 0, Cm, ld, 0, 0.0, B, ld, st)) != hipSuccess) return e;
-  // A = A^-1 - B T^T  (= A^-1 + T S^-1 T^T)
-  if ((e = gemm(n1, n1, n2, -1.0, B, ld, 0, T, n2, 1, 1.0, A, ld, st)) != hipSuccess) return e;
-  // lower-left = B^T
-  const int64_t tot = (int64_t)n1 * n2;
-  hipLaunchKernelGGL(k_transpose, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, B, ld, Lo,
-                     ld, n1, n2);
-  return hipGetLastError();
+  if (i < GJB) {
+    if (!ok && i == 0) atomicExch(status, 1);
+#pragma unroll
+    for (int j = 0; j < GJB; ++j) {
+      Pbuf[i * GJB + j] = a[j];
+      if (i < m && j < m) M[(size_t)(k0 + i) * ld + k0 + j] = -a[j];
+    }
+  }
 }
 
+// Row panel: for every column gj outside K, R[:, gj] = P A[K, gj]; keeps the
+// old values in Rk and writes R into A[K, gj] and Rbuf.  Block = 64 columns.
+__global__ void __launch_bounds__(256) k_gj_panel(double* __restrict__ M, int ld, int n, int k0,
+                                                  int m, const double* __restrict__ Pbuf,
+                                                  double* __restrict__ Rbuf,
+                                                  double* __restrict__ Rk) {
+  const int j0 = blockIdx.x * GJT;
+  __shared__ double Ps[GJB][GJB + 1];
+  __shared__ double As[GJB][GJT + 1];
+  for (int e = threadIdx.x; e < GJB * GJB; e += 256) Ps[e / GJB][e % GJB] = Pbuf[e];
+  for (int e = threadIdx.x; e < GJB * GJT; e += 256) {
+    const int r = e / GJT, cc = e % GJT, gj = j0 + cc;
+    As[r][cc] = (r < m && gj < n) ? M[(size_t)(k0 + r) * ld + gj] : 0.0;
+  }
+  __syncthreads();
+  // thread: row r = t / 8 of R (GJB = 32 rows), columns 8 (t % 8) .. +7
+  const int r = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 8;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 4
+  for (int l = 0; l < GJB; ++l) {
+    const double pv = Ps[r][l];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = fma(pv, As[l][c0 + q], acc[q]);
+  }
+  if (r < m) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int gj = j0 + c0 + q;
+      if (gj < n && (gj < k0 || gj >= k0 + m)) {
+        Rbuf[(size_t)r * n + gj] = acc[q];
+        Rk[(size_t)r * n + gj] = As[r][c0 + q];
+        M[(size_t)(k0 + r) * ld + gj] = acc[q];
+      }
+    }
+  }
+}
+
+// For every element (gi, gj) with gi outside K:
+//   gj in K:   A[gi, gj] = R[gj - k0, gi]        (= (A[gi, K] P)_gj by symmetry)
+//   otherwise: A[gi, gj] -= sum_l Rk[l, gi] R[l, gj]   (A[gi, K] = Rk[:, gi]^T)
+// Block = 64 x 64 output tile, thread = 4 x 4 outputs.
+__global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ M, int ld, int n, int k0,
+                                                   int m, const double* __restrict__ Rbuf,
+                                                   const double* __restrict__ Rk) {
+  const int i0 = blockIdx.y * GJT, j0 = blockIdx.x * GJT;
+  if (i0 >= k0 && i0 + GJT <= k0 + m) return;  // tile rows all inside K (not for GJB < GJT)
+  __shared__ double Cs[GJB][GJT + 1];  // Cs[l][r] = Rk[l][i0 + r]
+  __shared__ double Bs[GJB][GJT + 1];  // Bs[l][c] = R[l][j0 + c]
+  for (int e = threadIdx.x; e < GJB * GJT; e += 256) {
+    const int l = e / GJT, cc = e % GJT;
+    const int gi = i0 + cc, gj = j0 + cc;
+    const bool gi_out = gi < n && (gi < k0 || gi >= k0 + m);
+    const bool gj_out = gj < n && (gj < k0 || gj >= k0 + m);
+    Cs[l][cc] = (l < m && gi_out) ? Rk[(size_t)l * n + gi] : 0.0;
+    Bs[l][cc] = (l < m && gj_out) ? Rbuf[(size_t)l * n + gj] : 0.0;
+  }
+  __syncthreads();
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  double acc[4][4] = {};
+#pragma unroll 4
+  for (int l = 0; l < GJB; ++l) {
+    double ca[4], bb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ca[q] = Cs[l][tr * 4 + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bb[q] = Bs[l][tc * 4 + q];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int yq = 0; yq < 4; ++yq) acc[x][yq] = fma(ca[x], bb[yq], acc[x][yq]);
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int yq = 0; yq < 4; ++yq) {
+      const int gi = i0 + tr * 4 + x, gj = j0 + tc * 4 + yq;
+      if (gi >= n || gj >= n || (gi >= k0 && gi < k0 + m)) continue;
+      if (gj >= k0 && gj < k0 + m)
+        M[(size_t)gi * ld + gj] = Rbuf[(size_t)(gj - k0) * n + gi];
+      else
+        M[(size_t)gi * ld + gj] -= acc[x][yq];
+    }
+}
+
+__global__ void k_negate(double* __restrict__ v, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) v[i] = -v[i];
+}
+
+size_t spd_inverse_work(int n) { return (size_t)GJB * GJB + 2 * (size_t)GJB * n; }
+
+// work holds >= spd_inverse_work(n) doubles.
 hipError_t spd_inverse_inplace(double* M, int n, double* work, int* d_status, hipStream_t st) {
-  return spd_inv_rec(M, n, n, work, d_status, st);
+  double* Pbuf = work;
+  double* Rbuf = work + GJB * GJB;
+  double* Rk = Rbuf + (size_t)GJB * n;
+  const int nt = (n + GJB - 1) / GJB;
+  const int nto = (n + GJT - 1) / GJT;
+  for (int kb = 0; kb < nt; ++kb) {
+    const int k0 = kb * GJB, m = std::min(GJB, n - k0);
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(64), 0, st, M, n, k0, m, Pbuf, d_status);
+    if (nt > 1) {
+      hipLaunchKernelGGL(k_gj_panel, dim3(nto), dim3(256), 0, st, M, n, n, k0, m, Pbuf, Rbuf, Rk);
+      hipLaunchKernelGGL(k_gj_update, dim3(nto, nto), dim3(256), 0, st, M, n, n, k0, m, Rbuf, Rk);
+    }
+  }
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(k_negate, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, M, nn);
+  return hipGetLastError();
 }
 
 // out = A x, A n x n row-major FP64; one wave per row.
