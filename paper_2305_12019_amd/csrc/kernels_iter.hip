@@ -261,7 +261,9 @@ hipError_t launch_ngemv(int n, const double* A1, const double* x1, double* o1, c
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_step1ab(Consts c, IterPtrs p) {
   Scal* sc = p.sc;
-  if (sc->done) return;
+  // (the stop flag, uniform over the launch, is tested once the first loads
+  // are in flight; nothing is written before the test)
+  const int done = sc->done;
   __shared__ double wy[4];
   __shared__ int ws[4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -279,6 +281,7 @@ __global__ void __launch_bounds__(256) k_step1ab(Consts c, IterPtrs p) {
   }
   const double sigma = sc->sigma;
   const int kk = sc->k;
+  if (done) return;
   double acc = 0.0;
   for (int j = threadIdx.x; j < c.n; j += 256) acc = fma(p.my[j], p.x[j], acc);
   double f = 0.0;
@@ -336,7 +339,7 @@ hipError_t launch_step1ab(const Consts& c, const IterPtrs& p, hipStream_t st) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_step1c_rows(Consts c, IterPtrs p) {
   Scal* sc = p.sc;
-  if (sc->done) return;
+  const int done = sc->done;  // tested after the first loads (see k_step1ab)
   __shared__ double wsum[4][NPC];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int row = blockIdx.x * 4 + wid;
@@ -358,6 +361,7 @@ __global__ void __launch_bounds__(256) k_step1c_rows(Consts c, IterPtrs p) {
   }
   const double sigma = sc->sigma;
   const double beta_bar = sc->beta_bar;
+  if (done) return;
   double acc = 0.0;
   for (int j = threadIdx.x; j < c.n; j += 256) acc = fma(p.my[j], p.dr[j], acc);
   double hg = 0.0, hm = 0.0;
@@ -435,7 +439,9 @@ constexpr int PANEL = 2048;
 template <typename T, int NW>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2)))
 k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
-  if (p.sc->done) return;
+  // The stop flag is tested after the prologue's loads are issued (nothing
+  // is written before the test), so its round trip overlaps theirs.
+  const int done = p.sc->done;
   constexpr int NT = NW * 64;
   constexpr int V = Vec<T>::N;
   constexpr int ROWS = 64 * V;
@@ -479,6 +485,7 @@ k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
   }
   const int k_it = p.sc->k;
   const double u2 = p.sc->u2;
+  if (done) return;
   auto stage = [&](int pc, int pn) {
     for (int i = threadIdx.x; i < pn; i += NT) {
       const double yz = p.y[pc + i] * c.inv_zs;
@@ -629,8 +636,9 @@ hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterP
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_rep_step(Consts c, IterPtrs p) {
   Scal* sc = p.sc;
-  if (sc->done) return;
+  const int done = sc->done;  // tested after the plan's loads (see k_step1ab)
   const Step2Plan pl = step2_plan<256>(c, p);
+  if (done) return;
   const int o = pl.redo;
   const double* al = o ? p.al1 : p.al0;
   const double* so = o ? p.s1 : p.s;
