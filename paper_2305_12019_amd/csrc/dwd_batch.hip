@@ -173,6 +173,10 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   bp.ld = ld;
   bp.nb = (n + 15) / 16;  // 16-row tiles of the n x n products
   bp.npb = batch_pass_row_blocks(ld);
+  // Representer iteration (params[0].representer): no pass; the element
+  // kernel writes the d-norm partials in blocks of 256 rows.
+  bp.rep = p[0].representer ? 1 : 0;
+  bp.npg = bp.rep ? (n + 255) / 256 : bp.npb;
   const size_t nB = (size_t)n * B;
   double* nv = nullptr;
   HIP_TRY_B(bb.dalloc((void**)&nv, nB * 19 * 8));
@@ -193,7 +197,16 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   HIP_TRY_B(bb.dalloc((void**)&bp.part_it, (size_t)B * bp.nb * 8));
   HIP_TRY_B(bb.dalloc((void**)&bp.part_ga, (size_t)B * bp.nb * 8));
   HIP_TRY_B(bb.dalloc((void**)&bp.part_c, (size_t)B * bp.nb * NPC * 8));
-  HIP_TRY_B(bb.dalloc((void**)&bp.part_g, (size_t)B * bp.npb * NP2 * 8));
+  HIP_TRY_B(bb.dalloc((void**)&bp.part_g, (size_t)B * std::max(bp.npb, bp.npg) * NP2 * 8));
+  if (bp.rep) {
+    double* rv = nullptr;
+    HIP_TRY_B(bb.dalloc((void**)&rv, nB * 4 * 8));
+    bp.AU = rv;
+    bp.ARHO = rv + nB;
+    bp.AW = rv + 2 * nB;
+    bp.CV = rv + 3 * nB;
+    HIP_TRY_B(bb.dalloc((void**)&bp.part_gc, (size_t)B * bp.nb * 8));
+  }
   HIP_TRY_B(bb.dalloc((void**)&bp.sc, (size_t)B * sizeof(Scal)));
   Consts* dcs = nullptr;
   HIP_TRY_B(bb.dalloc((void**)&dcs, (size_t)B * sizeof(Consts)));
@@ -239,7 +252,7 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   EvGuard guard{all_ev, 4};
   // Optional timing of every pass launch (params[0].profile): event pairs
   // around the Z~ [s_1..s_B] product, summed after the solve.
-  const bool profile = p[0].profile != 0;
+  const bool profile = p[0].profile != 0 && !p[0].representer;  // (no pass to time)
   std::vector<hipEvent_t> pev;
   struct PoolGuard {
     std::vector<hipEvent_t>& v;
@@ -294,7 +307,7 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   int graph_launches = 0, graph_captures = 0;
   int cur = 0;
   auto queue_chunk = [&](int bact, int len, int fp64, int cidx) -> dwd_status {
-    const int fixed = tuner.cached(slot_bucket(bact));
+    const int fixed = bp.rep ? 1 : tuner.cached(slot_bucket(bact));
     if (use_graph && fixed && len == chunk) {
       if (!(gc.exec && gc.bact == bact && gc.cur == cur && gc.tile == fixed && gc.fp64 == fp64)) {
         gc.drop();
@@ -326,8 +339,8 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
     for (int j = 0; j < len; ++j) {
       hipEvent_t pa, pb;
       HIP_TRY_B(pass_events(&pa, &pb));
-      int tile = 0;
-      HIP_TRY_B(tuner.pick(bact, cidx, &tile, &pa, &pb));
+      int tile = 1;
+      if (!bp.rep) HIP_TRY_B(tuner.pick(bact, cidx, &tile, &pa, &pb));
       HIP_TRY_B(launch_batch_iteration(P->X_rec, P->st_rec, fp64, bp, didx[cur], bact, tile, st,
                                        pa, pb));
     }
@@ -373,6 +386,11 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   auto check = [&](const int* list, int cnt) -> dwd_status {
     for (int i = 0; i < cnt; ++i) {
       const int j = list[i];
+      if (bp.rep)
+        HIP_TRY_B(launch_expand3(P->X_rec, P->st_rec, hcs[j], bp.AW + (size_t)j * n,
+                                 bp.AU + (size_t)j * n, bp.ARHO + (size_t)j * n, bp.y,
+                                 bp.W + (size_t)j * ld, bp.U + (size_t)j * ld,
+                                 bp.RHO + (size_t)j * ld, st));
       HIP_TRY_B(launch_gemvT(P->X_rec, P->st_rec, ld, n, bp.W + (size_t)j * ld,
                              bp.RHO + (size_t)j * ld, P->ip.partT, nullptr, st));
       int nblk = 0;

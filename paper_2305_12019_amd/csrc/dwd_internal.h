@@ -123,9 +123,15 @@ struct BatchPtrs {
   double *U, *RHO, *W;
   double* SB;          // n x B: column slot = y .* s / Z_scale of the chosen outcome
   double *part_n1, *part_it, *part_c, *part_g, *part_ga;
+  // representer mode: coefficients (u~ = Z~ AU, rho = Z~ ARHO, w~ = Z~ AW),
+  // CV = alpha' + sqrt(mu) ARHO' (coefficients of Z~ alpha' + D rho') and the
+  // block partials of CV^T G~ CV
+  double *AU, *ARHO, *AW, *CV, *part_gc;
   Scal* sc;
   const Consts* cs;
   int n, nb, npb;      // nb: row blocks of the n x n kernels; npb: row blocks of the pass
+  int npg;             // blocks of part_g per problem read by the tail (pass or element kernel)
+  int rep;             // 1: representer iteration
   int64_t ld;
 };
 

@@ -47,6 +47,9 @@ hipError_t launch_norm2(const double* v, int64_t m, double* out, hipStream_t st)
 hipError_t launch_rep_step(const Consts& c, const IterPtrs& p, hipStream_t st);
 hipError_t launch_expand(const void* X, int storage, const Consts& c, const IterPtrs& p,
                          hipStream_t st);
+hipError_t launch_expand3(const void* X, int storage, const Consts& c, const double* a0,
+                          const double* a1, const double* a2, const double* y, double* o0,
+                          double* o1, double* o2, hipStream_t st);
 hipError_t launch_csr_expand(const int64_t* ip, const int32_t* ix, const void* val, int dtype,
                              int64_t d, const Consts& c, const IterPtrs& p, hipStream_t st);
 

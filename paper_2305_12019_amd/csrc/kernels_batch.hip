@@ -33,6 +33,11 @@ __global__ void k_init_b(BatchPtrs P, int B) {
     P.PR[on + i] = 0.0;
     P.T[on + i] = 0.0;
     P.XX[on + i] = 0.0;
+    if (P.rep) {
+      P.AU[on + i] = 0.0;
+      P.ARHO[on + i] = 0.0;
+      P.AW[on + i] = 0.0;
+    }
   }
   if (i < P.ld) {
     const size_t od = (size_t)p * P.ld;
@@ -362,6 +367,7 @@ __global__ void __launch_bounds__(256) k_plan_b(BatchPtrs P, const int* __restri
     sc->redo = pl.redo;
     sc->gamma = pl.gamma;
   }
+  if (P.rep) return;  // no pass in the representer iteration
   // the pass's right-hand operand for this slot, dense and pre-scaled
   const double* src = (pl.redo ? P.S1 : P.S) + (size_t)pr * P.n;
   double* dst = P.SB + (size_t)blockIdx.x * P.n;
@@ -635,15 +641,16 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P,
 // ||Z~ alpha + D rho||^2 (eta_D3).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(NM_T) k_ga_mm(BatchPtrs P, const int* __restrict__ idx,
-                                                int bact) {
+                                                int bact, int mode) {
+  // mode 0: G~ alpha' (HA, part_ga); mode 1: G~ CV (part_gc, representer)
   int bx, by;
   if (!nm_tile((P.n + 15) / 16, (bact + 15) / 16, bx, by)) return;
   __shared__ double red[1][NM_W][256];
   const int r0 = bx * 16, c0 = by * 16;
   const double* A[1] = {P.G};
   double h;
-  nm_products<1, false>(A, nm_col(P, idx, bact, c0, nullptr, 1), nullptr, P.n, r0, red, nullptr,
-                        &h, nullptr);
+  nm_products<1, false>(A, nm_col(P, idx, bact, c0, mode ? P.CV : nullptr, mode ? 0 : 1),
+                        nullptr, P.n, r0, red, nullptr, &h, nullptr);
   if (threadIdx.x >= 256) return;
   const int e = threadIdx.x, row = r0 + (e & 15), slot = c0 + (e >> 4);
   int pr = -1;
@@ -655,12 +662,63 @@ __global__ void __launch_bounds__(NM_T) k_ga_mm(BatchPtrs P, const int* __restri
   double contrib = 0.0;
   if (live && row < P.n) {
     const size_t on = (size_t)pr * P.n;
-    const double* al = (P.sc[pr].redo ? P.AL1 : P.AL0) + on;
-    P.HA[on + row] = h;
-    contrib = al[row] * h;
+    if (mode) {
+      contrib = P.CV[on + row] * h;
+    } else {
+      const double* al = (P.sc[pr].redo ? P.AL1 : P.AL0) + on;
+      P.HA[on + row] = h;
+      contrib = al[row] * h;
+    }
   }
   contrib = sum16(contrib);
-  if (live && (e & 15) == 0) P.part_ga[(size_t)pr * P.nb + bx] = contrib;
+  if (live && (e & 15) == 0) (mode ? P.part_gc : P.part_ga)[(size_t)pr * P.nb + bx] = contrib;
+}
+
+// ---------------------------------------------------------------------------
+// Representer iteration, element part (in place of the pass): per (row,
+// problem) the coefficient updates of Steps 2-3 (see k_rep_step), CV and the
+// NP2 partials of the d-space norms as n-space dot products; slots 2 and 3
+// (||Z~ a + D rho||^2, ||Z~ a||^2) come from the two G~ products.
+// Block = 256 rows of one active problem.
+// ---------------------------------------------------------------------------
+constexpr int RB_T = 256;
+
+__global__ void __launch_bounds__(RB_T) k_rep_b(BatchPtrs P, const int* __restrict__ idx) {
+  const int pr = idx[blockIdx.y];
+  const Scal* sc = P.sc + pr;
+  if (sc->done) return;
+  const Consts c = P.cs[pr];
+  const int o = sc->redo;
+  const double sigma = sc->sigma, gamma = sc->gamma;
+  const double beta = o ? sc->beta1 : sc->beta_bar;
+  const double gr = 1.0 / (sigma * c.sqmu);
+  const double rs = c.tau * sigma * c.sqmu;
+  const size_t on = (size_t)pr * P.n;
+  const int i = blockIdx.x * RB_T + threadIdx.x;
+  double acc[NP2] = {0, 0, 0, 0, 0, 0};
+  if (i < P.n) {
+    const double s = (o ? P.S1 : P.S)[on + i];
+    const double v = (o ? P.V1 : P.V)[on + i];
+    const double al = (o ? P.AL1 : P.AL0)[on + i];
+    const double au = P.AU[on + i], ar = P.ARHO[on + i], prv = P.PR[on + i];
+    const double aw = au + gr * ar - s / c.mu;
+    const double gaw = v - beta * P.y[i];
+    const double au1 = gamma * (aw - gr * ar);
+    const double pu1 = gamma * (gaw - gr * prv);
+    const double ar1 = ar - rs * (aw - au1);
+    const double pr1 = prv - rs * (gaw - pu1);
+    P.AW[on + i] = aw;
+    P.AU[on + i] = au1;
+    P.ARHO[on + i] = ar1;
+    P.CV[on + i] = al + c.sqmu * ar1;
+    acc[0] = (aw - au1) * (gaw - pu1);
+    acc[1] = aw * gaw;
+    acc[4] = ar1 * pr1;
+    acc[5] = au1 * pu1;
+  }
+  block_sum_k<RB_T, NP2>(acc);
+  if (threadIdx.x < NP2)
+    P.part_g[((size_t)pr * P.npg + blockIdx.x) * NP2 + threadIdx.x] = acc[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -697,9 +755,12 @@ __global__ void __launch_bounds__(NTB) k_tail_b(BatchPtrs P, const int* __restri
     acc[9 + NP2] += P.part_ga[(size_t)pr * P.nb + b];
     nmax = fmax(nmax, P.part_it[(size_t)pr * P.nb + b]);
   }
-  for (int b = threadIdx.x; b < P.npb; b += NTB)
+  double cgc = 0.0;  // representer: CV^T G~ CV = ||Z~ alpha' + D rho'||^2
+  for (int b = threadIdx.x; b < P.npg; b += NTB)
 #pragma unroll
-    for (int j = 0; j < NP2; ++j) acc[9 + j] += P.part_g[((size_t)pr * P.npb + b) * NP2 + j];
+    for (int j = 0; j < NP2; ++j) acc[9 + j] += P.part_g[((size_t)pr * P.npg + b) * NP2 + j];
+  if (P.rep)
+    for (int b = threadIdx.x; b < P.nb; b += NTB) cgc += P.part_gc[(size_t)pr * P.nb + b];
   // commit and recurrences (old sigma), with a^T Z~^T rho^{k+1}
   const double gr = 1.0 / (sigma * c.sqmu);
   const double rs = c.tau * sigma * c.sqmu;
@@ -726,11 +787,12 @@ __global__ void __launch_bounds__(NTB) k_tail_b(BatchPtrs P, const int* __restri
     P.PR[on + i] = prn;
     apr += al * prn;
   }
-  double all[K + 1];
+  double all[K + 2];
 #pragma unroll
   for (int j = 0; j < K; ++j) all[j] = acc[j];
   all[K] = apr;
-  block_sum_k<NTB, K + 1>(all);
+  all[K + 1] = cgc;
+  block_sum_k<NTB, K + 2>(all);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) nmax = fmax(nmax, __shfl_xor(nmax, off, 64));
   if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = nmax;
@@ -744,7 +806,8 @@ __global__ void __launch_bounds__(NTB) k_tail_b(BatchPtrs P, const int* __restri
     for (int j = 0; j < 9; ++j) red[R_PRES2 + j] = all[j];
     red[R_WU2] = all[9 + 0];
     red[R_W2] = all[9 + 1];
-    red[R_DRES2] = fmax(aGa + 2.0 * c.sqmu * all[K] + c.mu * rho2, 0.0);
+    red[R_DRES2] = P.rep ? fmax(all[K + 1], 0.0)
+                         : fmax(aGa + 2.0 * c.sqmu * all[K] + c.mu * rho2, 0.0);
     red[R_ZA2] = aGa;
     red[R_G2] = 0.0;
     red[R_RHO2] = rho2;
@@ -831,11 +894,19 @@ hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, con
   hipLaunchKernelGGL(k_s1ab_mm, gnm, dim3(NM_T), 0, st, P, idx, bact);
   hipLaunchKernelGGL(k_s1c_mm, gnm, dim3(NM_T), 0, st, P, idx, bact);
   hipLaunchKernelGGL(k_plan_b, dim3(bact), dim3(256), 0, st, P, idx);
-  if (ev0) (void)hipEventRecord(ev0, st);
-  hipError_t e = launch_pass_b(X, storage, fp64_mfma, P, idx, bact, tile, st);
-  if (e != hipSuccess) return e;
-  if (ev1) (void)hipEventRecord(ev1, st);
-  hipLaunchKernelGGL(k_ga_mm, gnm, dim3(NM_T), 0, st, P, idx, bact);
+  if (P.rep) {
+    if (!P.AU || !P.ARHO || !P.AW || !P.CV || !P.part_gc || P.npg < (P.n + RB_T - 1) / RB_T)
+      return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rep_b, dim3((P.n + RB_T - 1) / RB_T, bact), dim3(RB_T), 0, st, P, idx);
+    hipLaunchKernelGGL(k_ga_mm, gnm, dim3(NM_T), 0, st, P, idx, bact, 1);
+  } else {
+    if (P.npg != P.npb) return hipErrorInvalidValue;
+    if (ev0) (void)hipEventRecord(ev0, st);
+    hipError_t e = launch_pass_b(X, storage, fp64_mfma, P, idx, bact, tile, st);
+    if (e != hipSuccess) return e;
+    if (ev1) (void)hipEventRecord(ev1, st);
+  }
+  hipLaunchKernelGGL(k_ga_mm, gnm, dim3(NM_T), 0, st, P, idx, bact, 0);
   hipLaunchKernelGGL(k_tail_b, dim3(bact), dim3(NTB), 0, st, P, idx);
   return hipGetLastError();
 }

@@ -784,19 +784,28 @@ __global__ void __launch_bounds__(256) k_expand(const T* __restrict__ X, Consts 
   }
 }
 
-// w~ = Z~ aw, u~ = Z~ au, rho = Z~ arho over dense storage.
-hipError_t launch_expand(const void* X, int storage, const Consts& c, const IterPtrs& p,
-                         hipStream_t st) {
-  if (!X || !iter_ptrs_ok(p) || c.ld % kLdAlign != 0) return hipErrorInvalidValue;
+// out_j = Z~ a_j (j < 3) over dense storage.
+hipError_t launch_expand3(const void* X, int storage, const Consts& c, const double* a0,
+                          const double* a1, const double* a2, const double* y, double* o0,
+                          double* o1, double* o2, hipStream_t st) {
+  if (!X || !a0 || !a1 || !a2 || !y || !o0 || !o1 || !o2 || c.ld % kLdAlign != 0)
+    return hipErrorInvalidValue;
   if (storage == DWD_FP64)
     hipLaunchKernelGGL(k_expand<double>, dim3((unsigned)(c.ld / 128)), dim3(256), 0, st,
-                       (const double*)X, c, p.aw, p.au, p.arho, p.y, p.w, p.u, p.rho);
+                       (const double*)X, c, a0, a1, a2, y, o0, o1, o2);
   else if (storage == DWD_FP32)
     hipLaunchKernelGGL(k_expand<float>, dim3((unsigned)(c.ld / 256)), dim3(256), 0, st,
-                       (const float*)X, c, p.aw, p.au, p.arho, p.y, p.w, p.u, p.rho);
+                       (const float*)X, c, a0, a1, a2, y, o0, o1, o2);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// w~ = Z~ aw, u~ = Z~ au, rho = Z~ arho over dense storage.
+hipError_t launch_expand(const void* X, int storage, const Consts& c, const IterPtrs& p,
+                         hipStream_t st) {
+  if (!iter_ptrs_ok(p)) return hipErrorInvalidValue;
+  return launch_expand3(X, storage, c, p.aw, p.au, p.arho, p.y, p.w, p.u, p.rho, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -128,3 +128,47 @@ def test_batch_tile_widths_and_graph_replay_are_bit_identical(dwd, fp32, tol):
         for a, b in zip(r["info"], ref["info"]):
             assert a["iters"] == b["iters"] and a["beta"] == b["beta"], key
     P.close()
+
+
+def test_batch_representer_matches_oracle_and_single_representer(dwd):
+    """Batched representer iteration (no pass over Z per iteration): every
+    problem matches the oracle, passes the FP64 check, and takes the same
+    iterations as the single representer solve; graph replay and eager
+    launches agree bit for bit."""
+    X, y = synth.random_two_class(4000, 180, seed=23, mean=0.6, dtype="f32")
+    grid = [(0.3, 1.0), (3.0, 2.0), (1.0, 0.5), (10.0, 4.0), (0.05, 1.0), (1.0, 1.0)]
+    P = dwd.Problem(X, y, storage="f32")
+    res = P.solve_batch([dict(C=C, q=q, tol=1e-8, max_iter=20000, representer=1)
+                         for C, q in grid])
+    eager = P.solve_batch([dict(C=C, q=q, tol=1e-8, max_iter=20000, representer=1, graph=0)
+                           for C, q in grid])
+    assert np.array_equal(res["W"], eager["W"])
+    assert res["info"][0]["graph_launches"] > 0 and eager["info"][0]["graph_launches"] == 0
+    for j, (C, q) in enumerate(grid):
+        info = res["info"][j]
+        assert info["converged"] == 1 and info["kkt_check"] <= 2e-8, (j, info)
+        ref = O.solve(X, y, C, q, tol=1e-9, max_iter=20000)
+        f = _obj(X, y, res["W"][j], info["beta"], C, q)
+        fr = _obj(X, y, ref["w"], ref["beta"], C, q)
+        assert abs(f - fr) <= 1e-6 * abs(fr), (j, f, fr)
+        assert np.linalg.norm(res["W"][j] - ref["w"]) <= 1e-4 * np.linalg.norm(ref["w"]), j
+    res6 = P.solve_batch([dict(C=C, q=q, tol=1e-6, representer=1) for C, q in grid])
+    for j, (C, q) in enumerate(grid):
+        alone = P.solve(C, q, tol=1e-6, want_state=False, representer=1)
+        a, b = alone["info"]["iters"], res6["info"][j]["iters"]
+        assert abs(a - b) <= max(3, 0.10 * a), (j, a, b)
+    P.close()
+
+
+def test_batch_representer_sweep_full_size(dwd):
+    X, y = synth.two_class(synth.SWEEP_DATA)
+    P = dwd.Problem(X, y, storage="f32")
+    grid = synth.sweep_grid()
+    res = P.solve_batch([dict(C=C, q=q, tol=1e-5, representer=1) for C, q in grid])
+    infos = res["info"]
+    print("representer sweep: converged %d/64, iters max %d, solve_ms %.1f, resumed %d" % (
+        sum(i["converged"] for i in infos), max(i["iters"] for i in infos), infos[0]["solve_ms"],
+        sum(i["resumed"] for i in infos)))
+    for j, i in enumerate(infos):
+        assert i["converged"] == 1 and i["kkt_check"] <= 1.2e-5, (j, i)
+    P.close()
