@@ -136,6 +136,23 @@ def batched_leg(dwd, Xd, y, tol, grid):
     achieved = flops / pass_s / 1e12 if pass_s > 0 else None
     wdiff = max(np.linalg.norm(rb["W"][j] - plain[j]["w"]) / np.linalg.norm(plain[j]["w"])
                 for j in range(len(grid)))
+    # the same 64 problems in the representer mode, batched and one by one
+    P = dwd.Problem(Xd, y, storage="f32")
+    P.solve_batch([dict(C=grid[0][0], q=grid[0][1], tol=tol, max_iter=20, representer=1)])
+    t = time.perf_counter()
+    rr = P.solve_batch([dict(C=C, q=q, tol=tol, representer=1) for C, q in grid])
+    t_rb = time.perf_counter() - t
+    t = time.perf_counter()
+    rp = [P.solve(C, q, tol=tol, want_state=False, representer=1) for C, q in grid]
+    t_rp = time.perf_counter() - t
+    P.close()
+    rep = {"batched_solves_per_s": len(grid) / t_rb, "batched_s": t_rb,
+           "plain_solves_per_s": len(grid) / t_rp, "plain_s": t_rp, "gain": t_rp / t_rb,
+           "gain_vs_pass_plain": t_plain / t_rb,
+           "converged_batched": sum(i["converged"] for i in rr["info"]),
+           "converged_plain": sum(r["info"]["converged"] for r in rp),
+           "kkt_check_max_batched": max(i["kkt_check"] for i in rr["info"]),
+           "kkt_check_max_plain": max(r["info"]["kkt_check"] for r in rp)}
     return {
         "problems": len(grid), "grid": "C = 10^(-2+4a/15), a=0..15, x q in {0.5,1,2,4}",
         "batched_solves_per_s": len(grid) / t_batch, "batched_s": t_batch,
@@ -148,6 +165,7 @@ def batched_leg(dwd, Xd, y, tol, grid):
         "max_rel_w_diff_batched_vs_plain": wdiff,
         "iters_max": max(i["iters"] for i in ib), "iters_sum": it_total,
         "resumed": sum(i["resumed"] for i in ib),
+        "representer": rep,
         "mfma": {"kernel": "k_pass_b<float,float,NB> (Z~ [s_1..s_B], FP32 MFMA, FP64 sums over "
                            "K tiles; resumed problems continue on the FP64 MFMA variant)",
                  "achieved": achieved, "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s",
@@ -205,6 +223,13 @@ def serving_leg(dwd, torch, dev, count, tol):
     out0 = dwd.serve(reqs)
     t_sat = time.perf_counter() - t
     lat0 = np.array([o["latency"] for o in out0]) * 1e3
+    # the same requests in the representer mode, all queued at t = 0
+    for rq in reqs:
+        rq["params"] = dict(rq["params"], representer=1)
+    t = time.perf_counter()
+    outr = dwd.serve(reqs)
+    t_rep = time.perf_counter() - t
+    latr = np.array([o["latency"] for o in outr]) * 1e3
     kinds = {"dense_f32": 0, "dense_bf16": 0, "csr": 0}
     for r in base:
         kinds["csr" if r.layout == "csr" else "dense_" + r.storage] += 1
@@ -221,6 +246,12 @@ def serving_leg(dwd, torch, dev, count, tol):
                       "p99_ms": float(np.percentile(lat0, 99)),
                       "ok": sum(o["status"] == 0 for o in out0),
                       "kkt_check_max": max(o["info"]["kkt_check"] for o in out0)},
+        "representer_saturated": {"solves_per_s": len(reqs) / t_rep,
+                                  "gain_vs_plain": (len(reqs) / t_rep) / cap,
+                                  "p50_ms": float(np.percentile(latr, 50)),
+                                  "p99_ms": float(np.percentile(latr, 99)),
+                                  "ok": sum(o["status"] == 0 for o in outr),
+                                  "kkt_check_max": max(o["info"]["kkt_check"] for o in outr)},
     }
 
 
