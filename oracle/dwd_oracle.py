@@ -7,7 +7,9 @@ does, and this module imports nothing from the solver.
 
 It follows the paper (arXiv 2305.12019) step by step, in its notation:
 
-* problem: generalized DWD primal (Section 2, eq-primal) with e = 1;
+* problem: generalized DWD primal (Section 2, eq-primal), with a general
+  positive penalty vector e (default 1) and, optionally, the class weights
+  of Section 4.5 on the loss terms;
 * reformulation with u = w and D (w - u) = 0 (Section 3, eq-gen);
 * Algorithm 1 (Steps 1a, 1b, 1c, 2, 3) with the inexactness sequence
   eps_k = c / (k + 1)^1.5;
@@ -78,6 +80,48 @@ def kappa(q):
     return (q + 1.0) / q * q ** (1.0 / (q + 1.0))
 
 
+def class_weights(y, q):
+    """Section 4.5 class weights for unbalanced classes: the loss term of
+    sample i becomes tau_i^q theta_q(r_i) with
+    tau_i = tau_- / max(tau_+, tau_-) if y_i = +1, tau_+ / max(tau_+, tau_-)
+    if y_i = -1, tau_+- = (n_+- / K)^(1/(1+q)), K = n / log(n).
+    Returns w_i = tau_i^q (the factor on theta_q)."""
+    y = np.asarray(y, dtype=np.float64)
+    n = y.size
+    K = n / math.log(n)
+    tp = (np.sum(y > 0) / K) ** (1.0 / (1.0 + q))
+    tm = (np.sum(y < 0) / K) ** (1.0 / (1.0 + q))
+    m = max(tp, tm)
+    tau = np.where(y > 0, tm / m, tp / m)
+    return tau ** q
+
+
+def loss_weights(y, q, weights):
+    """Loss weights for :func:`solve`: ones (False), the class weights of
+    Section 4.5 (True), or a given array."""
+    y = np.asarray(y, dtype=np.float64)
+    if weights is True:
+        return class_weights(y, q)
+    if weights is False or weights is None:
+        return np.ones(y.size)
+    return np.asarray(weights, np.float64)
+
+
+def suggest_C(X, y, q):
+    """Section 4.1 choice of the penalty: with dist the median of the
+    Euclidean distances between the samples of the two classes,
+    C = 10^(q+1) max{1, 10^(q-1) log(n) max{1000, d}^(1/3) / dist^(q+1)}."""
+    X = np.asarray(X, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n, d = X.shape
+    P, N = X[y > 0], X[y < 0]
+    D = np.sqrt(np.maximum(np.sum(P * P, 1)[:, None] + np.sum(N * N, 1)[None, :]
+                           - 2.0 * P @ N.T, 0.0))
+    dist = float(np.median(D))
+    return 10.0 ** (q + 1) * max(1.0, 10.0 ** (q - 1) * math.log(n) * max(1000.0, d) ** (1.0 / 3.0)
+                                 / dist ** (q + 1))
+
+
 def scale_data(X, y):
     """Z = X diag(y) (eq-r), Z_scale = sqrt(||X||_F), Z~ = Z / Z_scale
     (Section 4.2).  ``X`` has shape (n, d) with row i = x_i; the returned
@@ -95,38 +139,45 @@ def margins(X, y, w, beta):
     return y * (X @ w + beta)
 
 
-def reduced_loss(m, C, q):
-    """min over xi >= 0 (with r = m + xi > 0) of theta_q(r) + C xi.
+def reduced_loss(m, C, q, wt=None, e=None):
+    """min over xi >= 0 (with r = m + xi > 0) of wt theta_q(r) + C e xi
+    (wt = e = 1 by default; in general the threshold t* below is
+    (q wt / (C e))^(1/(q+1))).
 
     The minimiser is xi = max(0, t* - m) with t* = (q / C)^(1/(q+1)), where
     the derivative -q r^(-q-1) + C of the one-dimensional problem vanishes.
     This is the primal eq-primal with (r, xi) eliminated for fixed (w, beta).
     """
     m = np.asarray(m, dtype=np.float64)
-    ts = (q / C) ** (1.0 / (q + 1.0))
+    wt = np.ones_like(m) if wt is None else np.broadcast_to(np.asarray(wt, np.float64), m.shape)
+    ce = C * (np.ones_like(m) if e is None else np.broadcast_to(np.asarray(e, np.float64), m.shape))
+    ts = (q * wt / ce) ** (1.0 / (q + 1.0))
     out = np.empty_like(m)
     hi = m >= ts
-    out[hi] = m[hi] ** (-q)
-    out[~hi] = ts ** (-q) + C * (ts - m[~hi])
+    out[hi] = wt[hi] * m[hi] ** (-q)
+    out[~hi] = wt[~hi] * ts[~hi] ** (-q) + ce[~hi] * (ts[~hi] - m[~hi])
     return out
 
 
-def reduced_objective(X, y, w, beta, C, q):
-    """Primal objective of eq-primal (e = 1) at (w, beta) with the optimal
-    (r, xi) for that (w, beta); requires ||w|| <= 1 to be feasible."""
-    return float(np.sum(reduced_loss(margins(X, y, w, beta), C, q)))
+def reduced_objective(X, y, w, beta, C, q, wt=None, e=None):
+    """Primal objective of eq-primal at (w, beta) with the optimal (r, xi)
+    for that (w, beta); requires ||w|| <= 1 to be feasible."""
+    return float(np.sum(reduced_loss(margins(X, y, w, beta), C, q, wt, e)))
 
 
-def primal_objective(r, xi, C, q):
+def primal_objective(r, xi, C, q):  # e = 1, no class weights
     """Phi(r, xi) = sum theta_q(r_i) + C <e, xi> (eq-primal, e = 1)."""
     return float(np.sum(theta(r, q)) + C * np.sum(xi))
 
 
-def dual_objective_unscaled(X, y, alpha, q):
-    """-Psi(alpha) = kappa sum alpha_i^(q/(q+1)) - ||Z alpha|| (eq-dual)."""
+def dual_objective_unscaled(X, y, alpha, q, wt=None):
+    """-Psi(alpha) = kappa sum wt_i^(1/(q+1)) alpha_i^(q/(q+1)) - ||Z alpha||
+    (eq-dual; wt = 1 without class weights: inf_r wt theta_q(r) + a r =
+    kappa wt^(1/(q+1)) a^(q/(q+1)))."""
     Zalpha = np.asarray(X, dtype=np.float64).T @ (y * alpha)
     a = np.maximum(alpha, 0.0)
-    return float(kappa(q) * np.sum(a ** (q / (q + 1.0))) - np.linalg.norm(Zalpha))
+    wd = 1.0 if wt is None else np.asarray(wt, np.float64) ** (1.0 / (q + 1.0))
+    return float(kappa(q) * np.sum(wd * a ** (q / (q + 1.0))) - np.linalg.norm(Zalpha))
 
 
 def training_error(X, y, w, beta):
@@ -153,15 +204,17 @@ def prox_bracket(a, sigma, q):
     and the monotonicity of its two sides.
     """
     a = np.asarray(a, dtype=np.float64)
-    s0 = (q / sigma) ** (1.0 / (q + 2.0))
+    sg = np.broadcast_to(np.asarray(sigma, np.float64), a.shape)  # per element allowed
+    s0 = (q / sg) ** (1.0 / (q + 2.0))
     lo = np.empty_like(a)
     hi = np.empty_like(a)
     pos = a >= 0
-    lo[pos] = np.maximum(a[pos], s0)
-    hi[pos] = a[pos] + s0
+    lo[pos] = np.maximum(a[pos], s0[pos])
+    hi[pos] = a[pos] + s0[pos]
     na = -a[~pos]
-    lo[~pos] = (q / (sigma * (s0 + na))) ** (1.0 / (q + 1.0))
-    hi[~pos] = np.minimum(s0, (q / (sigma * na)) ** (1.0 / (q + 1.0)))
+    sn = sg[~pos]
+    lo[~pos] = (q / (sn * (s0[~pos] + na))) ** (1.0 / (q + 1.0))
+    hi[~pos] = np.minimum(s0[~pos], (q / (sn * na)) ** (1.0 / (q + 1.0)))
     return lo, hi
 
 
@@ -177,28 +230,38 @@ def prox_newton(a, sigma, q, s_init, tol, max_steps=MAX_NEWTON):
     """
     a = np.asarray(a, dtype=np.float64)
     s = np.array(s_init, dtype=np.float64, copy=True)
-    lo, _ = prox_bracket(a, sigma, q)
+    sg = np.broadcast_to(np.asarray(sigma, np.float64), a.shape)  # per element allowed
+    tl = np.broadcast_to(np.asarray(tol, np.float64), a.shape)
+    lo, _ = prox_bracket(a, sg, q)
     bad = ~(np.isfinite(s) & (s > 0))
     s[bad] = lo[bad]
     steps = np.zeros(a.shape, dtype=np.int64)
-    done = np.abs(prox_grad(s, a, sigma, q)) <= tol
-    c1 = q * (q + 2.0) / sigma
-    c2 = q * (q + 1.0) / sigma
+    done = np.abs(prox_grad(s, a, sg, q)) <= tl
+    c1 = q * (q + 2.0) / sg
+    c2 = q * (q + 1.0) / sg
     for _ in range(max_steps):
         act = ~done
         if not act.any():
             break
         sa = s[act]
         aa = a[act]
-        s_new = sa * (c1 + aa * sa ** (q + 1.0)) / (c2 + sa ** (q + 2.0))
+        s_new = sa * (c1[act] + aa * sa ** (q + 1.0)) / (c2[act] + sa ** (q + 2.0))
         out = ~(np.isfinite(s_new) & (s_new > 0))
         s_new[out] = lo[act][out]
         tiny = np.abs(s_new - sa) <= 4.0 * np.finfo(np.float64).eps * sa
         s[act] = s_new
         steps[act] += 1
-        g_new = np.abs(prox_grad(s_new, aa, sigma, q)) <= tol
+        g_new = np.abs(prox_grad(s_new, aa, sg[act], q)) <= tl[act]
         done[act] = g_new | tiny
     return s, steps
+
+
+def prox_weighted(a, sigma, q, wt, s_init, tol):
+    """argmin_{s>0} wt s^-q + sigma/2 (s-a)^2 with the accuracy test
+    |phi_wt'(s)| <= tol: dividing by wt gives the unweighted prox at
+    sigma / wt with the test |phi'(s)| <= tol / wt."""
+    wt = np.asarray(wt, np.float64)
+    return prox_newton(a, sigma / wt, q, s_init, tol / wt)
 
 
 def prox_cubic_q1(a, sigma):
@@ -311,30 +374,34 @@ def linsys_rhs(Zt, y, mu, sigma, r, xi, u, alpha, rho):
 # ---------------------------------------------------------------------------
 
 def kkt_residuals(Zt, zscale, y, C, q, mu, r, w, beta, xi, u, alpha, rho=None,
-                  Ztw=None, rho_residual=True):
+                  Ztw=None, rho_residual=True, wt=None, e=None):
     """Relative residuals of Section 4.3 on the scaled problem eq-gen-scale.
     eta_C3 uses the squared norm as printed.  With ``rho`` given and
     ``rho_residual`` set, eta_D3 = ||Z~ alpha + D rho|| / (1 + C) joins
     eta_D.  Returns a dict with every eta, the maxima eta_P, eta_D, eta_C,
-    the objectives and eta_gap."""
+    the objectives and eta_gap.  ``wt``: loss weights (theta_q term of
+    sample i times wt_i), ``e``: penalty vector; both default to 1."""
     if Ztw is None:
         Ztw = Zt.T @ w
     den = 1.0 + C
+    ce = C * (np.ones(len(r)) if e is None else np.asarray(e, np.float64))
     e = {}
     e["P1"] = np.linalg.norm(Ztw + beta * y + xi - r) / den
     e["P2"] = math.sqrt(mu) * np.linalg.norm(w - u) / den
     e["P3"] = max(np.linalg.norm(w) - zscale, 0.0) / den
     e["D1"] = np.linalg.norm(np.minimum(0.0, alpha)) / den
-    e["D2"] = np.linalg.norm(np.maximum(0.0, alpha - C)) / den
+    e["D2"] = np.linalg.norm(np.maximum(0.0, alpha - ce)) / den
     e["C1"] = abs(float(y @ alpha)) / den
-    e["C2"] = abs(float(xi @ (C - alpha))) / den
-    s = q / r ** (q + 1.0)
+    e["C2"] = abs(float(xi @ (ce - alpha))) / den
+    wt = np.ones_like(r) if wt is None else np.asarray(wt, np.float64)
+    s = q * wt / r ** (q + 1.0)
     e["C3"] = float(np.sum((alpha - s) ** 2)) / den
     Zalpha = Zt @ alpha
     if rho is not None:
         e["D3"] = np.linalg.norm(Zalpha + math.sqrt(mu) * rho) / den
-    primobj = float(np.sum(r ** (-q)) + C * np.sum(xi))
-    dualobj = float(kappa(q) * np.sum(np.maximum(alpha, 0.0) ** (q / (q + 1.0)))
+    primobj = float(np.sum(wt * r ** (-q)) + np.sum(ce * xi))
+    dualobj = float(kappa(q) * np.sum(wt ** (1.0 / (q + 1.0))
+                                      * np.maximum(alpha, 0.0) ** (q / (q + 1.0)))
                     - zscale * np.linalg.norm(Zalpha))
     e["primobj"] = primobj
     e["dualobj"] = dualobj
@@ -367,14 +434,14 @@ def sigma_update(sigma, eta_p, eta_d):
     return sigma
 
 
-def step2(w, beta, r, alpha, rho, Ztw, y, C, sigma, mu, radius):
+def step2(w, beta, r, alpha, rho, Ztw, y, C, sigma, mu, radius, e=1.0):
     """Step 2 of Algorithm 1: u = projection of g = w - sigma^-1 D^-1 rho onto
     the ball of radius ``radius``; xi = projection onto R^n_+ of
     r - Z~^T w - y beta + sigma^-1 alpha - sigma^-1 C e."""
     g = w - rho / (sigma * math.sqrt(mu))
     ng = np.linalg.norm(g)
     u = g if ng <= radius else g * (radius / ng)
-    xi = np.maximum(0.0, r - Ztw - y * beta + (alpha - C) / sigma)
+    xi = np.maximum(0.0, r - Ztw - y * beta + (alpha - C * e) / sigma)
     return u, xi
 
 
@@ -398,7 +465,8 @@ def default_sigma0(C, q, n):
 def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
           sigma0: Optional[float] = None, eps_c: Optional[float] = None,
           record: bool = False, start: Optional[Dict] = None,
-          scale: bool = True, rho_residual: bool = True, sigma_every: int = 2) -> Dict:
+          scale: bool = True, rho_residual: bool = True, sigma_every: int = 2,
+          weights=False, e=None) -> Dict:
     """Run Algorithm 1 on eq-gen-scale and return the unscaled solution.
 
     ``X`` has shape (n, d) (row i = sample x_i), ``y`` is +-1.  Returns a dict
@@ -411,7 +479,10 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
     not change the solution.  ``sigma_every``: the sigma rule of Section 4.4
     is applied after iterations whose count is a multiple of it (the paper
     gives no cadence; the default reading is every second iteration, 1 =
-    every iteration).
+    every iteration).  ``weights``: True for the class weights of
+    Section 4.5 (:func:`class_weights`) on the loss terms, or an array of n
+    positive loss weights; ``e``: the positive penalty vector of eq-primal
+    (n values; default 1).
     """
     y = np.asarray(y, dtype=np.float64)
     if scale:
@@ -421,6 +492,8 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
     d, n = Zt.shape
     F = SMWFactor(Zt, y, mu)
     R = zscale
+    wt = loss_weights(y, q, weights)
+    ev = np.ones(n) if e is None else np.asarray(e, np.float64)
     if start is None:
         r = np.ones(n)
         xi = np.ones(n)
@@ -452,7 +525,7 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
         wbar, bbar = F.solve(hw, hb)
         # Step 1b
         c = Zt.T @ wbar + y * bbar + xi - alpha / sigma
-        r_new, steps = prox_newton(c, sigma, q, r, eps_k / math.sqrt(n))
+        r_new, steps = prox_weighted(c, sigma, q, wt, r, eps_k / math.sqrt(n))
         newton_max = max(newton_max, int(steps.max()))
         # Step 1c
         hw1, hb1 = linsys_rhs(Zt, y, mu, sigma, r_new, xi, u, alpha, rho)
@@ -466,12 +539,12 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
         r = r_new
         # Step 2
         Ztw = Zt.T @ w
-        u, xi = step2(w, beta, r, alpha, rho, Ztw, y, C, sigma, mu, R)
+        u, xi = step2(w, beta, r, alpha, rho, Ztw, y, C, sigma, mu, R, ev)
         # Step 3
         alpha, rho = step3(alpha, rho, Ztw, y, beta, xi, r, w, u, sigma, mu, tau)
         # Section 4.3
         e = kkt_residuals(Zt, zscale, y, C, q, mu, r, w, beta, xi, u, alpha, rho=rho,
-                          Ztw=Ztw, rho_residual=rho_residual)
+                          Ztw=Ztw, rho_residual=rho_residual, wt=wt, e=ev)
         it = k + 1
         if record:
             hist.append(dict(k=k, sigma=sigma, P=e["P"], D=e["D"], C=e["C"], gap=e["gap"],
@@ -488,7 +561,7 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
                 converged=converged, history=hist)
 
 
-def kkt_of_solution(X, y, C, q, sol, mu=1.0, rho_residual=True):
+def kkt_of_solution(X, y, C, q, sol, mu=1.0, rho_residual=True, weights=False, e=None):
     """Recompute every residual of Section 4.3 in FP64 from a returned state
     (w and u unscaled, rho of the scaled problem, as :func:`solve` and the
     GPU solver return them)."""
@@ -501,4 +574,5 @@ def kkt_of_solution(X, y, C, q, sol, mu=1.0, rho_residual=True):
                          np.asarray(sol["u"], np.float64) * zscale,
                          np.asarray(sol["alpha"], np.float64),
                          rho=None if rho is None else np.asarray(rho, np.float64),
-                         rho_residual=rho_residual)
+                         rho_residual=rho_residual,
+                         wt=loss_weights(y, q, weights), e=e)

@@ -31,7 +31,8 @@ class TwoClassSpec:
 
     x_i = diag(s) (mean * y_true_i * u + N(0, I_d)), with u a seeded random
     unit vector and s_j = 10**U(-log_scale, log_scale) (s = 1 if log_scale is
-    0).  A fraction ``flip`` of the labels is then flipped (chosen without
+    0).  floor(pos_frac * n) samples have y_true = +1 (0.5: balanced classes).
+    A fraction ``flip`` of the labels is then flipped (chosen without
     replacement), so the observed y differs from y_true.
     """
 
@@ -42,13 +43,14 @@ class TwoClassSpec:
     flip: float = 0.0
     log_scale: float = 0.0
     dtype: str = "f64"  # storage type of record: "f64" or "f32"
+    pos_frac: float = 0.5
 
 
 def _draw_two_class(spec: TwoClassSpec):
     rng = np.random.default_rng(spec.seed)
     g = rng.standard_normal(spec.d)
     u = g / np.linalg.norm(g)
-    n_pos = spec.n // 2
+    n_pos = int(math.floor(spec.pos_frac * spec.n))
     y_true = np.concatenate([np.ones(n_pos), -np.ones(spec.n - n_pos)])
     y_true = y_true[rng.permutation(spec.n)]
     if spec.log_scale > 0:
@@ -207,13 +209,28 @@ def csr_to_dense(indptr, indices, values, d: int, dtype=np.float64):
     return X
 
 
+# Unbalanced classes (about one positive in ten, Section 4.5 class weights):
+# the high-dimension, low-sample-size shape of the main workload.
+UNBALANCED_F32 = Workload(
+    "unbalanced_f32", TwoClassSpec(d=100_000, n=1000, seed=6, mean=0.5, flip=0.05,
+                                   pos_frac=0.1, dtype="f32"),
+    C=10.0, q=1.0, tol=1e-5, storage="f32")
+
+
+def penalty_vector(n: int, seed: int, low: float = 0.2):
+    """Positive penalty weights e (eq-primal) drawn U(low, 1) and divided by
+    their maximum, so that ||e||_inf = 1."""
+    e = np.random.default_rng(seed).uniform(low, 1.0, n)
+    return e / e.max()
+
+
 def tiny_2d(seed: int = 11, n: int = 16):
     """Two-dimensional toy data for brute-force checks (d = 2)."""
     return two_class(TwoClassSpec(d=2, n=n, seed=seed, mean=1.0, flip=0.125, dtype="f64"))
 
 
 def random_two_class(d: int, n: int, seed: int, mean: float = 0.8, flip: float = 0.1,
-                     log_scale: float = 0.0, dtype: str = "f64"):
+                     log_scale: float = 0.0, dtype: str = "f64", pos_frac: float = 0.5):
     """Convenience wrapper used by tests for ad-hoc shapes."""
     return two_class(TwoClassSpec(d=d, n=n, seed=seed, mean=mean, flip=flip,
-                                  log_scale=log_scale, dtype=dtype))
+                                  log_scale=log_scale, dtype=dtype, pos_frac=pos_frac))
