@@ -3,11 +3,13 @@
  * weighted discrimination (DWD) by the inexact symmetric Gauss-Seidel ADMM
  * (arXiv 2305.12019), Sherman-Morrison-Woodbury branch.
  *
- * Problem (Section 2, eq-primal, with e = 1):
- *     min  sum_i theta_q(r_i) + C <1, xi>
+ * Problem (Section 2, eq-primal):
+ *     min  sum_i v_i theta_q(r_i) + C <e, xi>
  *     s.t. Z^T w + beta y + xi - r = 0,  ||w|| <= 1,  xi >= 0,
  * with Z = X diag(y), theta_q(t) = t^-q for t > 0 (+inf otherwise), q > 0,
- * C > 0.  X is d x n (column i is the sample x_i), y in {-1,+1}^n.
+ * C > 0, a positive penalty vector e (default 1) and loss weights v_i
+ * (default 1; the class weights of Section 4.5 on request).  X is d x n
+ * (column i is the sample x_i), y in {-1,+1}^n.
  *
  * The solver scales the data as in Section 4.2 (Z~ = Z / sqrt(||X||_F)),
  * runs Algorithm 1 of Section 3 (Steps 1a, 1b, 1c, 2, 3) with the linear
@@ -121,6 +123,19 @@ typedef struct {
                         iterates as 0 in exact arithmetic.  0 (default) = one
                         pass over Z per iteration.  BF16 storage is not used
                         by the iteration in this mode.                         */
+  int32_t class_weights; /* 1: weight the loss term of sample i by tau_i^q, the
+                        class weights of Section 4.5 (tau_i = tau_-/max(tau_+,
+                        tau_-) for y_i = +1, tau_+/max(tau_+, tau_-) for
+                        y_i = -1, tau_+- = (n_+- log(n) / n)^(1/(1+q))); the
+                        prox of Step 1b, eta_C3 (alpha_i - q v_i / r_i^(q+1))
+                        and the objectives (sum v_i r_i^-q; kappa sum
+                        v_i^(1/(q+1)) alpha_i^(q/(q+1))) carry the weight.
+                        0 (default) = all weights 1.                         */
+  const double* e;   /* host array of n positive finite penalty weights e_i of
+                        eq-primal (the paper normalises ||e||_inf = 1), read
+                        during the call; NULL (default) = e = 1.  C e replaces
+                        C in Step 2, eta_D2, eta_C2 and the primal objective.
+                        dwd_solve_batch takes each problem's own e.           */
 } dwd_params;
 
 /* Per-solve report.  Residuals are those of Section 4.3 on the scaled
@@ -230,6 +245,19 @@ typedef struct {
  * budget gets status DWD_E_BUSY and is skipped.                                */
 dwd_status dwd_serve(const dwd_request* reqs, int32_t nreq, const dwd_serve_opts* opts,
                      dwd_response* out);
+
+/* The penalty parameter of Section 4.1 for exponent q on P's data:
+ *     C = 10^(q+1) max{1, 10^(q-1) log(n) max{1000, d}^(1/3) / dist^(q+1)},
+ * dist = the median of the n_+ n_- Euclidean distances ||x_i - x_j|| between
+ * a sample of each class (the mean of the two middle values for an even
+ * count).  The distances come from the FP64 Gram matrix of dwd_setup
+ * (||x_i - x_j||^2 = Z_scale^2 (G~_ii + G~_jj + 2 G~_ij) for y_i = -y_j) and
+ * the median is an exact selection on the device (radix select on the
+ * IEEE bit patterns of the squared distances), without storing the pairs.
+ *   q: exponent (> 0).   C: receives the value.
+ * Errors: DWD_E_INVALID (NULL handle or output, q <= 0), DWD_E_NOMEM,
+ * DWD_E_DEVICE.                                                                */
+dwd_status dwd_suggest_C(dwd_problem P, double q, double* C);
 
 /* Diagnostics: copy a set-up quantity of P to the host array out (count
  * doubles, must equal the quantity's size).  what is one of

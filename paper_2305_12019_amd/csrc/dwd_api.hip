@@ -51,7 +51,7 @@ int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz
   const int64_t nn = (int64_t)n * n * 8;
   b += 2 * nn;                                          // G~, M^-1
   if (storage == DWD_BF16 && layout != DWD_CSR) b += 2 * nn + (int64_t)n * 8;  // BF16 factor
-  b += (int64_t)n * 8 * 27 + ld * 8 * 3;                // vectors
+  b += (int64_t)n * 8 * 28 + ld * 8 * 3;                // vectors (incl. y, e)
   b += (ld / kLdAlign) * 2 * (int64_t)n * 8;            // pass partials
   const int splits = gram_splits(ld, n);
   b += std::max<int64_t>({(int64_t)splits * nn, nn, (int64_t)spd_inverse_work(n) * 8});  // set-up scratch
@@ -76,6 +76,16 @@ dwd_status validate_params(const dwd_params* p, bool for_solve) {
   if (p->batch_tile != 0 && p->batch_tile != 1 && p->batch_tile != 2 && p->batch_tile != 4)
     return fail(DWD_E_INVALID, "batch_tile must be 0, 1, 2 or 4");
   if (p->sigma_every < 1) return fail(DWD_E_INVALID, "sigma_every must be >= 1");
+  if (p->class_weights != 0 && p->class_weights != 1)
+    return fail(DWD_E_INVALID, "class_weights must be 0 or 1");
+  return DWD_OK;
+}
+
+dwd_status validate_penalty(const dwd_params* p, int64_t n) {
+  if (!p->e) return DWD_OK;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(p->e[i] > 0.0) || !std::isfinite(p->e[i]))
+      return fail(DWD_E_INVALID, "penalty weights e must be positive and finite");
   return DWD_OK;
 }
 
@@ -301,6 +311,10 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   if ((e = P->alloc((void**)&P->y, (size_t)n * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
   if ((e = hipMemcpyAsync(P->y, y, (size_t)n * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
     return cleanup(hip_fail(e, "H2D y"));
+  for (int i = 0; i < n; ++i) (y[i] > 0.0 ? P->npos : P->nneg) += 1;
+  if ((e = P->alloc((void**)&P->e, (size_t)n * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  P->e_ones = false;
+  if ((e = P->set_penalty(nullptr)) != hipSuccess) return cleanup(hip_fail(e, "H2D e"));
 
   // a0: copy + ||X||_F^2
   const int ychunks = (int)std::max<int64_t>(1, std::min<int64_t>(64, ld / 8192));
@@ -422,6 +436,7 @@ hipError_t Problem::alloc_iter_buffers() {
   if ((e = alloc((void**)&ip.part_c, (size_t)ngemv_blocks(n_) * NPC * 8)) != hipSuccess) return e;
   if ((e = alloc((void**)&ip.sc, sizeof(Scal))) != hipSuccess) return e;
   ip.y = y;
+  ip.e = this->e;
   ip.my = my;
   ip.Minv = Minv;
   ip.G = G;
@@ -443,6 +458,19 @@ static int qkind_of(double q) {
   if (q == 4.0) return 4;
   if (q == 0.5) return 5;
   return 0;
+}
+
+hipError_t Problem::set_penalty(const double* eh) {
+  if (!eh && e_ones) return hipSuccess;
+  std::vector<double> ones;
+  if (!eh) {
+    ones.assign(n, 1.0);
+    eh = ones.data();
+  }
+  // synchronous: eh is borrowed for the duration of the call only
+  const hipError_t r = hipMemcpy(e, eh, (size_t)n * 8, hipMemcpyHostToDevice);
+  if (r == hipSuccess) e_ones = !ones.empty();
+  return r;
 }
 
 Consts make_consts(const Problem* P, const dwd_params* p) {
@@ -471,6 +499,20 @@ Consts make_consts(const Problem* P, const dwd_params* p) {
   c.qkind = qkind_of(p->q);
   c.sigma_every = p->sigma_every;
   c.representer = p->representer ? 1 : 0;
+  // Section 4.5: tau_+- = (n_+- / K)^(1/(1+q)), K = n / log(n); the loss term
+  // of class +1 carries tau_-/max(tau_+, tau_-), of class -1
+  // tau_+/max(tau_+, tau_-), raised to q.
+  c.wpos = c.wneg = 1.0;
+  if (p->class_weights) {
+    const double K = (double)P->n / log((double)P->n);
+    const double tp = pow((double)P->npos / K, 1.0 / (1.0 + p->q));
+    const double tm = pow((double)P->nneg / K, 1.0 / (1.0 + p->q));
+    const double m = std::max(tp, tm);
+    c.wpos = pow(tm / m, p->q);
+    c.wneg = pow(tp / m, p->q);
+  }
+  c.wdpos = pow(c.wpos, 1.0 / (p->q + 1.0));
+  c.wdneg = pow(c.wneg, 1.0 / (p->q + 1.0));
   return c;
 }
 
@@ -646,8 +688,11 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
   dwd_status s;
   if (!P) return fail(DWD_E_INVALID, "problem is NULL");
   if ((s = validate_params(p, true)) != DWD_OK) return s;
+  if ((s = validate_penalty(p, P->n)) != DWD_OK) return s;
   HIP_TRY(hipSetDevice(P->device));
   const hipStream_t st = P->stream;
+  HIP_TRY(hipStreamSynchronize(st));  // (e may still be read by a previous solve)
+  HIP_TRY(P->set_penalty(p->e));
   HIP_TRY(hipEventRecord(P->ev_a, st));
   Consts c = make_consts(P, p);
   if (!iter_ptrs_ok(P->ip)) return fail(DWD_E_DEVICE, "iteration buffers are not allocated");
@@ -753,6 +798,69 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
   return hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
 }
 
+// Section 4.1: C = 10^(q+1) max{1, 10^(q-1) log(n) max{1000, d}^(1/3) / dist^(q+1)}
+// with dist the median between-class Euclidean distance, selected exactly on
+// the device from G~ (eight radix steps of 8 bits per order statistic).
+dwd_status suggest_C(Problem* P, double q, double* C) {
+  if (!(q > 0.0) || !std::isfinite(q)) return fail(DWD_E_INVALID, "q must be > 0");
+  HIP_TRY(hipSetDevice(P->device));
+  const hipStream_t st = P->stream;
+  const int n = P->n;
+  std::vector<double> hy(n);
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(hy.data(), P->y, (size_t)n * 8, hipMemcpyDeviceToHost));
+  std::vector<int> idx;
+  idx.reserve(n);
+  for (int i = 0; i < n; ++i)
+    if (hy[i] > 0.0) idx.push_back(i);
+  const int npos = (int)idx.size();
+  for (int i = 0; i < n; ++i)
+    if (!(hy[i] > 0.0)) idx.push_back(i);
+  const int nneg = n - npos;
+  int* didx = nullptr;
+  unsigned int* hist = nullptr;
+  HIP_TRY(hipMalloc((void**)&didx, (size_t)n * 4));
+  hipError_t e = hipMalloc((void**)&hist, 256 * 4);
+  if (e == hipSuccess) e = hipMemcpy(didx, idx.data(), (size_t)n * 4, hipMemcpyHostToDevice);
+  const int64_t total = (int64_t)npos * nneg;
+  // k-th smallest key (0-based) by radix selection from the top digit down
+  auto select = [&](int64_t k, unsigned long long* key) -> hipError_t {
+    unsigned long long prefix = 0;
+    unsigned int hh[256];
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      hipError_t r;
+      if ((r = hipMemsetAsync(hist, 0, 256 * 4, st)) != hipSuccess) return r;
+      if ((r = launch_pair_hist(P->G, n, didx, npos, didx + npos, nneg, prefix, shift, hist,
+                                st)) != hipSuccess)
+        return r;
+      if ((r = hipMemcpyAsync(hh, hist, 256 * 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return r;
+      if ((r = hipStreamSynchronize(st)) != hipSuccess) return r;
+      int64_t cum = 0;
+      int b = 0;
+      for (; b < 255 && k >= cum + (int64_t)hh[b]; ++b) cum += hh[b];
+      k -= cum;
+      prefix |= (unsigned long long)b << shift;
+    }
+    *key = prefix;
+    return hipSuccess;
+  };
+  unsigned long long k1 = 0, k2 = 0;
+  if (e == hipSuccess) e = select((total - 1) / 2, &k1);
+  if (e == hipSuccess) e = (total % 2) ? (k2 = k1, hipSuccess) : select(total / 2, &k2);
+  (void)hipFree(didx);
+  (void)hipFree(hist);
+  if (e != hipSuccess) return hip_fail(e, "suggest_C");
+  double v1, v2;
+  memcpy(&v1, &k1, 8);
+  memcpy(&v2, &k2, 8);
+  const double dist = 0.5 * (P->zscale * sqrt(v1) + P->zscale * sqrt(v2));
+  if (!(dist > 0.0)) return fail(DWD_E_INVALID, "the median between-class distance is zero");
+  const double t = pow(10.0, q - 1.0) * log((double)n) *
+                   cbrt(std::max(1000.0, (double)P->d)) / pow(dist, q + 1.0);
+  *C = pow(10.0, q + 1.0) * std::max(1.0, t);
+  return DWD_OK;
+}
+
 }  // namespace dwd
 
 // ---------------------------------------------------------------------------
@@ -841,6 +949,17 @@ void dwd_free(dwd_problem H) {
     delete H->P;
   }
   delete H;
+}
+
+dwd_status dwd_suggest_C(dwd_problem H, double q, double* C) {
+  if (!H || !H->P || !C) return fail(DWD_E_INVALID, "NULL argument");
+  try {
+    return suggest_C(H->P, q, C);
+  } catch (const std::bad_alloc&) {
+    return fail(DWD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(DWD_E_DEVICE, "unexpected exception in dwd_suggest_C");
+  }
 }
 
 dwd_status dwd_inspect(dwd_problem H, const char* what, double* out, int64_t count) {

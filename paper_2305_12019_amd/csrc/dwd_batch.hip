@@ -156,6 +156,7 @@ struct BatchBuffers {
 dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_info* info) {
   for (int j = 0; j < B; ++j) {
     dwd_status s = validate_params(&p[j], true);
+    if (s == DWD_OK) s = validate_penalty(&p[j], P->n);
     if (s != DWD_OK) return s;
   }
   if (P->layout != DWD_DENSE) return fail(DWD_E_INVALID, "dwd_solve_batch needs dense X");
@@ -193,6 +194,15 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   bp.RHO = dv + (size_t)ld * B;
   bp.W = dv + 2 * (size_t)ld * B;
   HIP_TRY_B(bb.dalloc((void**)&bp.SB, nB * 8));
+  {  // penalty weights of each problem (column j = p[j].e or ones)
+    double* E = nullptr;
+    HIP_TRY_B(bb.dalloc((void**)&E, nB * 8));
+    std::vector<double> he(nB, 1.0);
+    for (int j = 0; j < B; ++j)
+      if (p[j].e) std::copy(p[j].e, p[j].e + n, he.begin() + (size_t)j * n);
+    HIP_TRY_B(hipMemcpy(E, he.data(), nB * 8, hipMemcpyHostToDevice));
+    bp.E = E;
+  }
   HIP_TRY_B(bb.dalloc((void**)&bp.part_n1, (size_t)B * bp.nb * 8));
   HIP_TRY_B(bb.dalloc((void**)&bp.part_it, (size_t)B * bp.nb * 8));
   HIP_TRY_B(bb.dalloc((void**)&bp.part_ga, (size_t)B * bp.nb * 8));

@@ -129,6 +129,19 @@ __device__ double prox_newton(double a, double sigma, double s, double tol, cons
   return s;
 }
 
+// Step 1b with a loss weight v on theta_q: v s^-q + sigma/2 (s - a)^2 has
+// the minimiser of the unweighted problem at sigma / v, and its derivative
+// is v times the unweighted one at sigma / v, so the accuracy test scales
+// by 1 / v (v = 1: the unweighted prox, bit for bit).
+__device__ __forceinline__ double loss_weight(const Consts& c, double yi) {
+  return yi > 0.0 ? c.wpos : c.wneg;
+}
+
+__device__ __forceinline__ double prox_weighted(double a, double sigma, double s, double tol,
+                                                double v, const Consts& c, int& steps) {
+  return prox_newton(a, sigma / v, s, tol / v, c, steps);
+}
+
 __device__ __forceinline__ double eps_k(const Consts& c, int k) {
   const double k1 = (double)k + 1.0;
   return c.eps_c / (k1 * sqrt(k1));
@@ -186,18 +199,26 @@ __device__ __forceinline__ void wave_row_dot2(const double* __restrict__ a,
 }
 
 
+// Per-row terms of the Section 4.3 residuals and objectives, with the loss
+// weight v_i of the row's class and the penalty weight e_i: alpha - q v / r^(q+1)
+// (eta_C3), max(0, alpha - C e) (eta_D2), xi (C e - alpha) (eta_C2),
+// v r^-q and e xi (primal), v^(1/(q+1)) alpha^(q/(q+1)) (dual).
 __device__ __forceinline__ void nspace_sums(const Consts& c, double rq, double rq1, double a1,
-                                            double xi, double pres, double yi, double* acc) {
-  const double comp = a1 - c.q / rq1;
+                                            double xi, double pres, double yi, double ei,
+                                            double* acc) {
+  const bool pos = yi > 0.0;
+  const double v = pos ? c.wpos : c.wneg, vd = pos ? c.wdpos : c.wdneg;
+  const double ce = c.C * ei;
+  const double comp = a1 - c.q * v / rq1;
   acc[0] = pres * pres;
   acc[1] = fmin(0.0, a1) * fmin(0.0, a1);
-  acc[2] = fmax(0.0, a1 - c.C) * fmax(0.0, a1 - c.C);
+  acc[2] = fmax(0.0, a1 - ce) * fmax(0.0, a1 - ce);
   acc[3] = yi * a1;
-  acc[4] = xi * (c.C - a1);
+  acc[4] = xi * (ce - a1);
   acc[5] = comp * comp;
-  acc[6] = 1.0 / rq;
-  acc[7] = xi;
-  acc[8] = a1 > 0.0 ? pow(a1, c.qexp) : 0.0;
+  acc[6] = v / rq;
+  acc[7] = ei * xi;
+  acc[8] = a1 > 0.0 ? vd * pow(a1, c.qexp) : 0.0;
 }
 
 
@@ -238,7 +259,7 @@ __device__ __forceinline__ void finish_etas(const Consts& c, const double* r, do
   e[E_C1] = fabs(r[R_YA]) / den;
   e[E_C2] = fabs(r[R_XCA]) / den;
   e[E_C3] = r[R_COMP2] / den;
-  const double prim = r[R_SUMRQ] + c.C * r[R_SUMXI];
+  const double prim = r[R_SUMRQ] + c.C * r[R_SUMXI];  // sums carry v and e
   const double dual = c.kappa * r[R_SUMAQ] - c.R * sqrt(fmax(r[R_ZA2], 0.0));
   e[E_PRIM] = prim;
   e[E_DUAL] = dual;

@@ -33,13 +33,13 @@ __host__ __device__ inline int ngemv_blocks(int n) { return (n + 3) / 4; }
 enum RedIdx {
   R_PRES2 = 0,     // ||Z~^T w + beta y + xi - r||^2
   R_AMIN2,         // ||min(0, alpha)||^2
-  R_AMAX2,         // ||max(0, alpha - C)||^2
+  R_AMAX2,         // ||max(0, alpha - C e)||^2
   R_YA,            // y^T alpha
-  R_XCA,           // xi^T (C - alpha)
-  R_COMP2,         // ||alpha - q / r^(q+1)||^2
-  R_SUMRQ,         // sum r^-q
-  R_SUMXI,         // sum xi
-  R_SUMAQ,         // sum max(alpha,0)^(q/(q+1))
+  R_XCA,           // xi^T (C e - alpha)
+  R_COMP2,         // ||alpha - q v / r^(q+1)||^2
+  R_SUMRQ,         // sum v r^-q (v: loss weight)
+  R_SUMXI,         // sum e xi
+  R_SUMAQ,         // sum v^(1/(q+1)) max(alpha,0)^(q/(q+1))
   R_WU2,           // ||w - u||^2
   R_W2,            // ||w||^2
   R_DRES2,         // ||Z~ alpha + sqrt(mu) rho||^2
@@ -89,6 +89,9 @@ struct Consts {
   int32_t sigma_every; // the sigma rule runs after iterations k with k % sigma_every == 0
   int32_t representer; // 1: d-vectors carried as n-vector coefficients (w~ = Z~ a_w, ...)
   double sigma0;       // initial sigma (used by the batched initialiser)
+  // loss weights of the theta_q terms by class (1 without class weights) and
+  // their (q+1)-th roots, which enter the dual objective
+  double wpos, wneg, wdpos, wdneg;
 };
 
 // Pointers of one problem's iteration state (all device).
@@ -97,6 +100,7 @@ struct IterPtrs {
   const double* my;     // M^-1 y
   const double* Minv;
   const double* G;
+  const double* e;      // penalty weights of eq-primal (ones by default)
   double *r, *xi, *alpha, *Pu, *Prho, *t, *x, *f, *s, *v, *dr, *hG, *rn;
   double *s1, *v1, *xi0, *xi1, *al0, *al1;  // the two outcomes of Step 1c
   double *au, *arho, *aw;  // representer coefficients: u~ = Z~ au, rho = Z~ arho, w~ = Z~ aw
@@ -118,6 +122,7 @@ struct BatchPtrs {
   const double* my;
   const double* Minv;
   const double* G;
+  const double* E;     // n x B penalty weights (column = problem)
   double *R, *XI, *AL, *PU, *PR, *T, *XX, *F, *S, *V, *DR, *RN, *S1, *V1, *XI0, *XI1, *AL0,
       *AL1, *HA;
   double *U, *RHO, *W;
@@ -200,6 +205,11 @@ size_t spd_inverse_work(int n);  // doubles of work space spd_inverse_inplace ne
 hipError_t launch_gemv_rows(const double* A, int n, const double* x, double* out,
                             hipStream_t st);
 hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipStream_t st);
+// Histogram step of the radix selection over between-class squared distances
+// (hist[256] must be zero on entry; see k_pair_hist).
+hipError_t launch_pair_hist(const double* G, int n, const int* ipos, int npos, const int* ineg,
+                            int nneg, unsigned long long prefix, int shift, unsigned int* hist,
+                            hipStream_t st);
 int gram_splits(int64_t ld, int n);
 
 }  // namespace dwd

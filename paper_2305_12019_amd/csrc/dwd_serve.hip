@@ -191,6 +191,7 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
       return fail(DWD_E_INVALID, "requests must be sorted by t_arrival");
   for (int i = 0; i < nreq; ++i) {
     dwd_status s = validate_params(&reqs[i].params, true);
+    if (s == DWD_OK) s = validate_penalty(&reqs[i].params, reqs[i].X.n);
     if (s != DWD_OK) return s;
     memset(&out[i].info, 0, sizeof(dwd_info));
     out[i].status = DWD_E_BUSY;
@@ -279,7 +280,8 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
       s.c = make_consts(s.P, &s.prm);
       s.c_lowp = s.P->storage == DWD_BF16 ? lowp_consts(s.P, &s.prm) : s.c;
       memset(s.hs, 0, sizeof(Scal));
-      if (launch_init(s.c, s.P->ip, default_sigma0(&s.prm, s.P->n), s.stream) != hipSuccess ||
+      if (s.P->set_penalty(s.prm.e) != hipSuccess ||
+          launch_init(s.c, s.P->ip, default_sigma0(&s.prm, s.P->n), s.stream) != hipSuccess ||
           queue_chunk(s, chunk) != hipSuccess) {
         out[r].status = DWD_E_DEVICE;
         fatal = DWD_E_DEVICE;

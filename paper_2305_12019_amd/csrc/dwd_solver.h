@@ -68,6 +68,9 @@ struct Problem {
   int st_rec = DWD_FP32;
   const void* X_lowp = nullptr;  // BF16 image (storage == BF16)
   double* y = nullptr;
+  double* e = nullptr;         // penalty weights of eq-primal (n)
+  bool e_ones = true;          // e currently holds all ones
+  int64_t npos = 0, nneg = 0;  // class sizes (Section 4.5 weights)
   double* G = nullptr;
   double* Minv = nullptr;
   double* my = nullptr;
@@ -103,6 +106,9 @@ struct Problem {
 
   hipError_t alloc(void** ptr, size_t bytes);
   hipError_t alloc_iter_buffers();
+  // Load the penalty weights e of eq-primal for the next solve (host array
+  // of n values, validated by the caller; NULL = all ones).
+  hipError_t set_penalty(const double* eh);
   hipError_t queue_iteration(const Consts& c, const void* Xit, int st_it, bool fresh,
                              bool profile, int k);
   hipError_t run_loop(const Consts& c, const void* Xit, int st_it, int resync, int check_every,
@@ -124,6 +130,8 @@ struct Problem {
 dwd_status fail(dwd_status s, const std::string& msg);
 dwd_status hip_fail(hipError_t e, const char* where);
 dwd_status validate_params(const dwd_params* p, bool for_solve);
+// p->e, when given, must hold n positive finite values.
+dwd_status validate_penalty(const dwd_params* p, int64_t n);
 Consts make_consts(const Problem* P, const dwd_params* p);
 // Constants of the BF16 phase: its own y^T M^-1 y and the looser tolerance.
 Consts lowp_consts(const Problem* P, const dwd_params* p);
@@ -132,6 +140,7 @@ int64_t padded_ld(int64_t d);
 int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz);
 dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params* p,
                          hipStream_t st, Problem** out);
+dwd_status suggest_C(Problem* P, double q, double* C);
 dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* info,
                          double* alpha, double* r, double* xi, double* u, double* rho);
 dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_info* info);

@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(NM_T) k_s1ab_mm(BatchPtrs P, const int* __rest
       const double cc = v + P.XI[on + row] - P.AL[on + row] / sigma;
       const double r0v = P.R[on + row];
       int steps = 0;
-      const double rn = prox_newton(cc, sigma, r0v, tolN, c, steps);
+      const double rn = prox_weighted(cc, sigma, r0v, tolN, loss_weight(c, P.y[row]), c, steps);
       const double dr = rn - r0v;
       P.F[on + row] = f;
       P.S[on + row] = s;
@@ -300,31 +300,31 @@ __global__ void __launch_bounds__(NM_T) k_s1c_mm(BatchPtrs P, const int* __restr
       const double dr = P.DR[on + row], rn = P.RN[on + row], a0 = P.AL[on + row];
       const double yi = P.y[row], xr = P.XX[on + row], pu = P.PU[on + row];
       const double s0 = P.S[on + row], v0 = P.V[on + row], f0 = P.F[on + row];
-      const double my0 = P.my[row], t0 = P.T[on + row];
+      const double my0 = P.my[row], t0 = P.T[on + row], ei = P.E[on + row];
       const double rq1 = pow_qp1(rn, c);
       const double rq = pow_q(rn, c);
       out[0] = dr * hg;
       {
-        const double xi = fmax(0.0, rn - v0 + (a0 - c.C) / sigma);
+        const double xi = fmax(0.0, rn - v0 + (a0 - c.C * ei) / sigma);
         const double pres = v0 + xi - rn;
         const double a1 = a0 - c.tau * sigma * pres;
         P.XI0[on + row] = xi;
         P.AL0[on + row] = a1;
-        nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1);
+        nspace_sums(c, rq, rq1, a1, xi, pres, yi, ei, out + 1);
         out[1 + 9] = s0 * (c.mu * (xr + beta_bar * yi - s0));
         out[1 + 10] = pu * s0;
       }
       {
         const double s = f0 - hm + beta1 * my0;
         const double v = s - (t0 - dr);
-        const double xi = fmax(0.0, rn - v + (a0 - c.C) / sigma);
+        const double xi = fmax(0.0, rn - v + (a0 - c.C * ei) / sigma);
         const double pres = v + xi - rn;
         const double a1 = a0 - c.tau * sigma * pres;
         P.S1[on + row] = s;
         P.V1[on + row] = v;
         P.XI1[on + row] = xi;
         P.AL1[on + row] = a1;
-        nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1 + NPO);
+        nspace_sums(c, rq, rq1, a1, xi, pres, yi, ei, out + 1 + NPO);
         out[1 + NPO + 9] = s * (c.mu * (xr - dr + beta1 * yi - s));
         out[1 + NPO + 10] = pu * s;
       }

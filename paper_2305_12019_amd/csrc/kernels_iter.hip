@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(256) k_step1ab(Consts c, IterPtrs p) {
     const double s = f + beta_bar * myr;
     const double v = s - tr;
     const double cc = v + xir - alr / sigma;
-    const double rn = prox_newton(cc, sigma, r0, tolN, c, steps);
+    const double rn = prox_weighted(cc, sigma, r0, tolN, loss_weight(c, yr), c, steps);
     const double dr = rn - r0;
     p.f[row] = f;
     p.s[row] = s;
@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(256) k_step1c_rows(Consts c, IterPtrs p) {
   const int row = blockIdx.x * 4 + wid;
   const bool mine = row < c.n && lane == 0;
   double dr = 0.0, rn = 1.0, a0 = 0.0, yi = 0.0, xr = 0.0, pu = 0.0, s0 = 0.0, v0 = 0.0;
-  double f0 = 0.0, my0 = 0.0, t0 = 0.0;
+  double f0 = 0.0, my0 = 0.0, t0 = 0.0, ei = 1.0;
   if (mine) {
     dr = p.dr[row];
     rn = p.rn[row];
@@ -358,6 +358,7 @@ __global__ void __launch_bounds__(256) k_step1c_rows(Consts c, IterPtrs p) {
     f0 = p.f[row];
     my0 = p.my[row];
     t0 = p.t[row];
+    ei = p.e[row];
   }
   const double sigma = sc->sigma;
   const double beta_bar = sc->beta_bar;
@@ -379,26 +380,26 @@ __global__ void __launch_bounds__(256) k_step1c_rows(Consts c, IterPtrs p) {
     {  // outcome 0
       const double s = s0;
       const double v = v0;
-      const double xi = fmax(0.0, rn - v + (a0 - c.C) / sigma);
+      const double xi = fmax(0.0, rn - v + (a0 - c.C * ei) / sigma);
       const double pres = v + xi - rn;
       const double a1 = a0 - c.tau * sigma * pres;
       p.xi0[row] = xi;
       p.al0[row] = a1;
-      nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1);
+      nspace_sums(c, rq, rq1, a1, xi, pres, yi, ei, out + 1);
       out[1 + 9] = s * (c.mu * (xr + beta_bar * yi - s));
       out[1 + 10] = pu * s;
     }
     {  // outcome 1
       const double s = f0 - hm + beta1 * my0;
       const double v = s - (t0 - dr);
-      const double xi = fmax(0.0, rn - v + (a0 - c.C) / sigma);
+      const double xi = fmax(0.0, rn - v + (a0 - c.C * ei) / sigma);
       const double pres = v + xi - rn;
       const double a1 = a0 - c.tau * sigma * pres;
       p.s1[row] = s;
       p.v1[row] = v;
       p.xi1[row] = xi;
       p.al1[row] = a1;
-      nspace_sums(c, rq, rq1, a1, xi, pres, yi, out + 1 + NPO);
+      nspace_sums(c, rq, rq1, a1, xi, pres, yi, ei, out + 1 + NPO);
       out[1 + NPO + 9] = s * (c.mu * (xr - dr + beta1 * yi - s));
       out[1 + NPO + 10] = pu * s;
     }

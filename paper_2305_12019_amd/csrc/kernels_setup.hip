@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "dwd_internal.h"
 
 namespace dwd {
@@ -586,6 +588,51 @@ __global__ void __launch_bounds__(1024) k_dot(const double* __restrict__ a,
 
 hipError_t launch_dot(const double* a, const double* b, int n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_dot, dim3(1), dim3(1024), 0, st, a, b, n, out);
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Section 4.1 choice of C: one histogram step of an exact radix selection over
+// the squared between-class distances, scaled by 1/Z_scale^2,
+//     ||x_i - x_j||^2 / Z_scale^2 = G~_ii + G~_jj + 2 G~_ij   (y_i = +1, y_j = -1),
+// keyed by their IEEE-754 bit patterns, which order non-negative doubles as
+// unsigned integers.  Pairs whose key equals `prefix` in the bits above
+// shift + 8 are counted into hist[256] by the digit (key >> shift) & 255.
+// Nothing is stored per pair; each step re-evaluates them from G~.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_pair_hist(const double* __restrict__ G, int n,
+                                                   const int* __restrict__ ipos, int npos,
+                                                   const int* __restrict__ ineg, int nneg,
+                                                   unsigned long long prefix, int shift,
+                                                   unsigned int* __restrict__ hist) {
+  __shared__ unsigned int h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t total = (int64_t)npos * nneg;
+  const int hi = shift + 8;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int a = (int)(t / nneg);
+    const int b = (int)(t - (int64_t)a * nneg);
+    const size_t i = (size_t)ipos[a], j = (size_t)ineg[b];
+    const double s = G[i * n + i] + G[j * n + j] + 2.0 * G[i * n + j];
+    const double v = s > 0.0 ? s : 0.0;  // (+0 for rounding below zero and for -0)
+    const unsigned long long key = (unsigned long long)__double_as_longlong(v);
+    if (hi < 64 && (key >> hi) != (prefix >> hi)) continue;
+    atomicAdd(&h[(key >> shift) & 255ull], 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+hipError_t launch_pair_hist(const double* G, int n, const int* ipos, int npos, const int* ineg,
+                            int nneg, unsigned long long prefix, int shift, unsigned int* hist,
+                            hipStream_t st) {
+  const int64_t total = (int64_t)npos * nneg;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (total + 255) / 256));
+  hipLaunchKernelGGL(k_pair_hist, dim3(blocks), dim3(256), 0, st, G, n, ipos, npos, ineg, nneg,
+                     prefix, shift, hist);
   return hipGetLastError();
 }
 

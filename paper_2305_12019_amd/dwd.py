@@ -45,7 +45,8 @@ class Params(C.Structure):
                 ("rho_residual", C.c_int32), ("resync", C.c_int32), ("check_every", C.c_int32),
                 ("refine", C.c_int32), ("lowp_tol", C.c_double), ("profile", C.c_int32),
                 ("batch_fp32", C.c_int32), ("batch_tile", C.c_int32), ("graph", C.c_int32),
-                ("sigma_every", C.c_int32), ("representer", C.c_int32)]
+                ("sigma_every", C.c_int32), ("representer", C.c_int32),
+                ("class_weights", C.c_int32), ("e", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -102,6 +103,8 @@ def _load():
     lib.dwd_serve.restype = C.c_int
     lib.dwd_footprint.argtypes = [C.POINTER(Matrix), C.POINTER(Params)]
     lib.dwd_footprint.restype = C.c_int64
+    lib.dwd_suggest_C.argtypes = [C.c_void_p, C.c_double, dp]
+    lib.dwd_suggest_C.restype = C.c_int
     lib.dwd_inspect.argtypes = [C.c_void_p, C.c_char_p, dp, C.c_int64]
     lib.dwd_inspect.restype = C.c_int
     lib.dwd_status_str.argtypes = [C.c_int]
@@ -136,14 +139,25 @@ def _check(status: int, allow_not_converged: bool = True) -> int:
 
 def params(**kw) -> Params:
     """Default parameters (dwd_default_params) with keyword overrides;
-    ``storage`` may be a string ("f64", "f32", "bf16")."""
+    ``storage`` may be a string ("f64", "f32", "bf16"); ``e`` an array of n
+    penalty weights (kept alive as ``p.keep``; a copy of the structure does
+    not keep it, so callers that copy hold ``p.keep`` themselves)."""
     p = Params()
     _lib.dwd_default_params(C.byref(p))
+    p.keep = None
     for k, v in kw.items():
         if k == "storage" and isinstance(v, str):
             v = _STORAGE[v]
         if not hasattr(p, k):
             raise TypeError(f"unknown parameter {k}")
+        if k == "e":
+            if v is None:
+                p.e = None
+                continue
+            v = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+            p.keep = v
+            p.e = v.ctypes.data
+            continue
         setattr(p, k, v)
     return p
 
@@ -201,6 +215,11 @@ def csr_matrix(indptr, indices, values, d: int, keep: List) -> Matrix:
                   indices=indices.ctypes.data, nnz=len(values), on_device=0)
 
 
+def _check_e(e, n: int):
+    if e is not None and np.shape(e) != (n,):
+        raise ValueError("e must have n entries")
+
+
 def _dptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
@@ -228,6 +247,7 @@ class Problem:
 
     def solve(self, C_: float = 1.0, q: float = 1.0, tol: float = 1e-5, want_state: bool = True,
               **kw) -> Dict:
+        _check_e(kw.get("e"), self.n)
         p = params(C=C_, q=q, tol=tol, storage=self.storage, mu=self.mu, **kw)
         w = np.empty(self.d)
         info = Info()
@@ -249,17 +269,27 @@ class Problem:
     def solve_batch(self, plist: Sequence[Dict]) -> Dict:
         B = len(plist)
         arr = (Params * B)()
+        keep = []
         for j, kw in enumerate(plist):
             kw = dict(kw)
             kw.setdefault("storage", self.storage)
             kw.setdefault("mu", self.mu)
             if "C_" in kw:
                 kw["C"] = kw.pop("C_")
-            arr[j] = params(**kw)
+            _check_e(kw.get("e"), self.n)
+            pj = params(**kw)
+            keep.append(pj.keep)
+            arr[j] = pj
         W = np.empty((B, self.d))  # row j = w of problem j (d x B column-major)
         infos = (Info * B)()
         st = _check(_lib.dwd_solve_batch(self._h, B, arr, _dptr(W), infos))
         return dict(status=st, W=W, info=[infos[j].to_dict() for j in range(B)])
+
+    def suggest_C(self, q: float = 1.0) -> float:
+        """The Section 4.1 choice of C for exponent q (dwd_suggest_C)."""
+        out = np.empty(1)
+        _check(_lib.dwd_suggest_C(self._h, q, _dptr(out)))
+        return float(out[0])
 
     def inspect(self, what: str) -> np.ndarray:
         """Copy a set-up quantity to the host (dwd_inspect)."""
@@ -321,7 +351,10 @@ def serve(requests: Sequence[Dict], hbm_budget_bytes: float = 0.0, max_slots: in
             kw["C"] = kw.pop("C_")
         arr[j].X = m
         arr[j].y = yy.ctypes.data
-        arr[j].params = params(**kw)
+        _check_e(kw.get("e"), int(m.n))
+        pj = params(**kw)
+        keep.append(pj.keep)
+        arr[j].params = pj
         arr[j].t_arrival = float(rq.get("t_arrival", 0.0))
         w = np.empty(int(m.d))
         ws.append(w)
