@@ -26,6 +26,10 @@ Beside it, on the same data and to the same tolerance, the line carries
             n x n matrices and Z is streamed once at the end and by the FP64
             check): a separate mode, since it bypasses the pass; the large
             leg runs it too;
+  weighted  unbalanced classes (d = 1e5, n = 1e3, one positive in ten): the
+            Section 4.1 choice of C on the device, then whole solves with the
+            Section 4.5 class weights, pass and representer iterations
+            (--no-weighted skips it);
   cpu_baseline  one whole solve of the FP64 oracle on the host cores.
 Prints one JSON line.
 """
@@ -255,6 +259,53 @@ def serving_leg(dwd, torch, dev, count, tol):
     }
 
 
+def weighted_leg(dwd, torch, dev, steps):
+    """Unbalanced classes (d=1e5, n=1000, one positive in ten, FP32 storage):
+    the Section 4.1 choice of C on the device, then whole solves with the
+    Section 4.5 class weights (set-up included, like the plain leg), in the
+    pass and the representer iteration."""
+    import numpy as np
+    import synth
+    wl = synth.UNBALANCED_F32
+    X, y = synth.two_class(wl.data)
+    Xd = torch.from_numpy(X).to(dev)
+    del X
+    torch.cuda.synchronize()
+    P = dwd.Problem(Xd, y, storage="f32")
+    P.suggest_C(wl.q)
+    t = time.perf_counter()
+    C = P.suggest_C(wl.q)
+    c_ms = (time.perf_counter() - t) * 1e3
+    P.close()
+    out = {"workload": wl.name, "d": wl.data.d, "n": wl.data.n, "n_pos": int((y > 0).sum()),
+           "q": wl.q, "tol": wl.tol, "C_suggested": C, "suggest_C_ms": c_ms}
+
+    def one(rep, cw):
+        P = dwd.Problem(Xd, y, storage="f32")
+        r = P.solve(C, wl.q, tol=wl.tol, want_state=False, class_weights=cw, representer=rep)
+        P.close()
+        return r["info"]
+
+    for rep in (0, 1):
+        one(rep, 1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos = [one(rep, 1) for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        out["representer" if rep else "pass"] = {
+            "solves_per_s": steps / el, "ms_per_solve": el / steps * 1e3,
+            "iters": int(np.median([i["iters"] for i in infos])),
+            "converged": all(i["converged"] == 1 for i in infos),
+            "kkt_check_max": max(i["kkt_check"] for i in infos),
+            "eta_gap": infos[-1]["eta_gap"]}
+    u = one(0, 0)
+    out["unweighted_iters"] = u["iters"]
+    del Xd
+    torch.cuda.empty_cache()
+    return out
+
+
 def large_leg(dwd, torch, dev):
     """Mixed precision on one large problem: BF16 storage against FP32."""
     import synth
@@ -293,6 +344,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64, help="0 to skip the serving leg")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-weighted", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration) and one solve")
     args = ap.parse_args()
@@ -403,6 +455,9 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_leg(dwd, Xd, y, wl.tol, synth.sweep_grid())
         print(f"[bench] batched: gain {out['batched']['gain']:.2f}", file=sys.stderr, flush=True)
+    if not args.no_weighted:
+        out["weighted"] = weighted_leg(dwd, torch, dev, args.steps)
+        print("[bench] weighted done", file=sys.stderr, flush=True)
     if args.serve_requests > 0:
         del Xd
         torch.cuda.empty_cache()
