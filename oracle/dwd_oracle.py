@@ -16,8 +16,9 @@ It follows the paper (arXiv 2305.12019) step by step, in its notation:
 * Step 1a/1c linear system eq-linsys with T = 0, solved by the
   Sherman-Morrison-Woodbury form of Section 3.3.2 (eq-Anew, eq-Ainv, eq-H)
   with a Cholesky factor of I_n + Z^T D^-1 Z and the rank-one formula for
-  H^-1.  Every product with Z is an explicit product, as the paper counts
-  them (three per solve);
+  H^-1, or (d much smaller than n) by a Cholesky factor of the whole
+  (d+1) x (d+1) matrix (Section 3.3.1).  Every product with Z is an
+  explicit product, as the paper counts them (three per SMW solve);
 * Step 1b prox of theta_q by the Newton map of Section 3.2 (eq-varphi),
   warm-started at r^k;
 * data scaling Z~ = Z / sqrt(||X||_F) (Section 4.2, eq-gen-scale);
@@ -351,6 +352,40 @@ class SMWFactor:
         return w, float(beta)
 
 
+class DirectFactor:
+    """Section 3.3.1 (d much smaller than n): T = 0 and a Cholesky factor of
+    the whole eq-linsys matrix
+        A = [[Z~ Z~^T + mu I, Z~ y], [(Z~ y)^T, y^T y]]   ((d+1) x (d+1)),
+    formed once; each solve is two triangular solves."""
+
+    def __init__(self, Zt, y, mu=1.0):
+        y = np.asarray(y, dtype=np.float64)
+        d = Zt.shape[0]
+        Zy = Zt @ y
+        A = np.empty((d + 1, d + 1))
+        A[:d, :d] = Zt @ Zt.T + float(mu) * np.eye(d)
+        A[:d, d] = Zy
+        A[d, :d] = Zy
+        A[d, d] = y @ y
+        self.cho = sla.cho_factor(A, lower=True)
+
+    def solve(self, hw, hb):
+        x = sla.cho_solve(self.cho, np.concatenate([hw, [hb]]))
+        return x[:-1], float(x[-1])
+
+
+def select_solver(d, n):
+    """The solver choice printed with the paper's pseudo-code: the SMW form
+    when d > 5000, n < 0.2 d and n <= 2500; the iterative solver (PSQMR,
+    Section 3.3.3) for the other cases with d > 5000; the direct Cholesky
+    factor (Section 3.3.1) when d <= 5000."""
+    if d > 5000 and n < 0.2 * d and n <= 2500:
+        return "smw"
+    if d > 5000:
+        return "iterative"
+    return "direct"
+
+
 def linsys_matrix_apply(Zt, y, mu, w, beta):
     """A [w; beta] for the eq-linsys matrix with T = 0:
     A = [[Z~ Z~^T + mu I, Z~ y], [(Z~ y)^T, y^T y]]."""
@@ -466,7 +501,7 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
           sigma0: Optional[float] = None, eps_c: Optional[float] = None,
           record: bool = False, start: Optional[Dict] = None,
           scale: bool = True, rho_residual: bool = True, sigma_every: int = 2,
-          weights=False, e=None) -> Dict:
+          weights=False, e=None, solver: str = "smw") -> Dict:
     """Run Algorithm 1 on eq-gen-scale and return the unscaled solution.
 
     ``X`` has shape (n, d) (row i = sample x_i), ``y`` is +-1.  Returns a dict
@@ -482,7 +517,9 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
     every iteration).  ``weights``: True for the class weights of
     Section 4.5 (:func:`class_weights`) on the loss terms, or an array of n
     positive loss weights; ``e``: the positive penalty vector of eq-primal
-    (n values; default 1).
+    (n values; default 1).  ``solver``: "smw" (Section 3.3.2) or "direct"
+    (Section 3.3.1) for the eq-linsys solves; both give the same iterates in
+    exact arithmetic.
     """
     y = np.asarray(y, dtype=np.float64)
     if scale:
@@ -490,7 +527,12 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
     else:
         Zt, zscale = (np.asarray(X, np.float64) * y[:, None]).T.copy(), 1.0
     d, n = Zt.shape
-    F = SMWFactor(Zt, y, mu)
+    if solver == "smw":
+        F = SMWFactor(Zt, y, mu)
+    elif solver == "direct":
+        F = DirectFactor(Zt, y, mu)
+    else:
+        raise ValueError(f"unknown solver {solver}")
     R = zscale
     wt = loss_weights(y, q, weights)
     ev = np.ones(n) if e is None else np.asarray(e, np.float64)
