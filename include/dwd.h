@@ -50,6 +50,20 @@ typedef enum {
 typedef enum { DWD_FP64 = 0, DWD_FP32 = 1, DWD_BF16 = 2 } dwd_dtype;
 typedef enum { DWD_DENSE = 0, DWD_CSR = 1 } dwd_layout;
 
+/* How eq-linsys is solved (chosen at dwd_setup):
+ *   DWD_SOLVER_SMW    Sherman-Morrison-Woodbury form (Section 3.3.2) with the
+ *                     n x n factor; n <= 65536; every mode and input format.
+ *   DWD_SOLVER_DIRECT the whole (d+1) x (d+1) matrix of eq-linsys, formed
+ *                     and inverted once (Section 3.3.1); d <= 5120, dense X,
+ *                     FP32 or FP64 storage, n limited only by memory; single
+ *                     solves (not dwd_solve_batch, dwd_serve, representer).
+ *   DWD_SOLVER_AUTO   the paper's choice: direct when d <= 5000, else the SMW
+ *                     form (the paper's iterative solver for d > 5000 with
+ *                     n >= 0.2 d or n > 2500 is not built; the SMW form takes
+ *                     those cases while n <= 65536).  CSR input or BF16
+ *                     storage resolve to SMW.                                */
+typedef enum { DWD_SOLVER_SMW = 0, DWD_SOLVER_DIRECT = 1, DWD_SOLVER_AUTO = 2 } dwd_solver;
+
 /* The data matrix X (d x n), Section 2 "X Matrix".
  * DWD_DENSE: values is d x n column-major with leading dimension d, i.e.
  *            sample i occupies values[i*d .. i*d+d-1]; dtype FP64 or FP32.
@@ -131,6 +145,7 @@ typedef struct {
                         and the objectives (sum v_i r_i^-q; kappa sum
                         v_i^(1/(q+1)) alpha_i^(q/(q+1))) carry the weight.
                         0 (default) = all weights 1.                         */
+  int32_t solver;    /* dwd_solver, used by dwd_setup; default DWD_SOLVER_SMW  */
   const double* e;   /* host array of n positive finite penalty weights e_i of
                         eq-primal (the paper normalises ||e||_inf = 1), read
                         during the call; NULL (default) = e = 1.  C e replaces

@@ -78,6 +78,8 @@ dwd_status validate_params(const dwd_params* p, bool for_solve) {
   if (p->sigma_every < 1) return fail(DWD_E_INVALID, "sigma_every must be >= 1");
   if (p->class_weights != 0 && p->class_weights != 1)
     return fail(DWD_E_INVALID, "class_weights must be 0 or 1");
+  if (p->solver != DWD_SOLVER_SMW && p->solver != DWD_SOLVER_DIRECT && p->solver != DWD_SOLVER_AUTO)
+    return fail(DWD_E_INVALID, "solver must be DWD_SOLVER_SMW, _DIRECT or _AUTO");
   return DWD_OK;
 }
 
@@ -92,7 +94,7 @@ dwd_status validate_penalty(const dwd_params* p, int64_t n) {
 static dwd_status validate_matrix(const dwd_matrix* X) {
   if (!X) return fail(DWD_E_INVALID, "X is NULL");
   if (X->d < 1 || X->n < 1) return fail(DWD_E_INVALID, "d and n must be >= 1");
-  if (X->n > 65536) return fail(DWD_E_INVALID, "n > 65536 is not supported by the n x n factor");
+  if (X->n > 2147483647LL) return fail(DWD_E_INVALID, "n must fit in 32 bits");
   if (X->d > ((int64_t)1 << 40)) return fail(DWD_E_INVALID, "d too large");
   if (X->dtype != DWD_FP64 && X->dtype != DWD_FP32)
     return fail(DWD_E_INVALID, "X dtype must be DWD_FP64 or DWD_FP32");
@@ -148,13 +150,25 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   dwd_status s;
   if ((s = validate_matrix(X)) != DWD_OK) return s;
   if ((s = validate_params(p, false)) != DWD_OK) return s;
+  if (p->solver != DWD_SOLVER_SMW && p->solver != DWD_SOLVER_DIRECT && p->solver != DWD_SOLVER_AUTO)
+    return fail(DWD_E_INVALID, "solver must be DWD_SOLVER_SMW, _DIRECT or _AUTO");
+  const int solver = resolve_solver(p, X);
+  if (solver == DWD_SOLVER_DIRECT) {
+    if (X->layout != DWD_DENSE) return fail(DWD_E_INVALID, "the direct solver needs dense X");
+    if (p->storage == DWD_BF16)
+      return fail(DWD_E_INVALID, "the direct solver needs FP32 or FP64 storage");
+    if (X->d > kDirectMaxD) return fail(DWD_E_INVALID, "the direct solver needs d <= 5120");
+  } else if (X->n > 65536) {
+    return fail(DWD_E_INVALID, "n > 65536 is not supported by the n x n factor");
+  }
   if ((s = validate_labels(y, X->n)) != DWD_OK) return s;
   auto t0 = std::chrono::steady_clock::now();
   Problem* P = new Problem();
   P->stream = st;
   P->d = X->d;
   P->n = (int)X->n;
-  P->ld = padded_ld(X->d);
+  P->solver = solver;
+  P->ld = solver == DWD_SOLVER_DIRECT ? direct_ld(X->d) : padded_ld(X->d);
   P->storage = p->storage;
   P->mu = p->mu;
   P->layout = X->layout;
@@ -341,6 +355,20 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   if (!std::isfinite(frob2)) return cleanup(fail(DWD_E_INVALID, "X has non-finite entries"));
   if (!(frob2 > 0.0)) return cleanup(fail(DWD_E_INVALID, "X is all zero"));
   P->zscale = sqrt(sqrt(frob2));  // Z_scale = sqrt(||X||_F)
+  if (P->solver == DWD_SOLVER_DIRECT) {
+    if ((s = setup_direct(P, st)) != DWD_OK) return cleanup(s);
+    if ((e = hipHostMalloc((void**)&P->h_flags, 4096, 0)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipHostMalloc"));
+    if ((e = hipEventCreate(&P->ev_a)) != hipSuccess) return cleanup(hip_fail(e, "event"));
+    if ((e = hipEventCreate(&P->ev_b)) != hipSuccess) return cleanup(hip_fail(e, "event"));
+    for (auto& ev : P->ev_chunk)
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+        return cleanup(hip_fail(e, "event"));
+    P->setup_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = P;
+    return DWD_OK;
+  }
 
   // a1-a2: Gram G~ = Z~^T Z~ of the streamed image, M = I + G~/mu, M^-1 in
   // place, M^-1 y and y^T M^-1 y.  BF16 storage factors the BF16 image too:
@@ -687,6 +715,7 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
                          double* alpha, double* r, double* xi, double* u, double* rho) {
   dwd_status s;
   if (!P) return fail(DWD_E_INVALID, "problem is NULL");
+  if (P->solver == DWD_SOLVER_DIRECT) return solve_direct(P, p, w, info, alpha, r, xi, u, rho);
   if ((s = validate_params(p, true)) != DWD_OK) return s;
   if ((s = validate_penalty(p, P->n)) != DWD_OK) return s;
   HIP_TRY(hipSetDevice(P->device));
@@ -803,6 +832,8 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
 // the device from G~ (eight radix steps of 8 bits per order statistic).
 dwd_status suggest_C(Problem* P, double q, double* C) {
   if (!(q > 0.0) || !std::isfinite(q)) return fail(DWD_E_INVALID, "q must be > 0");
+  if (P->solver != DWD_SOLVER_SMW)
+    return fail(DWD_E_INVALID, "dwd_suggest_C needs the n x n Gram matrix of the SMW set-up");
   HIP_TRY(hipSetDevice(P->device));
   const hipStream_t st = P->stream;
   const int n = P->n;
@@ -967,17 +998,19 @@ dwd_status dwd_inspect(dwd_problem H, const char* what, double* out, int64_t cou
   Problem* P = H->P;
   const std::string w(what);
   const int64_t nn = (int64_t)P->n * P->n;
-  if (w == "zscale" || w == "ymy") {
+  if (w == "zscale" || w == "ymy" || w == "solver") {
     if (count != 1) return fail(DWD_E_INVALID, "count must be 1");
-    out[0] = w == "zscale" ? P->zscale : P->ymy;
+    out[0] = w == "zscale" ? P->zscale : (w == "ymy" ? P->ymy : (double)P->solver);
     return DWD_OK;
   }
   const double* src = nullptr;
   int64_t m = 0;
-  if (w == "G") { src = P->G; m = nn; }
-  else if (w == "Minv") { src = P->Minv; m = nn; }
-  else if (w == "my") { src = P->my; m = P->n; }
-  else return fail(DWD_E_INVALID, "unknown quantity");
+  const bool direct = P->solver == DWD_SOLVER_DIRECT;
+  if (w == "G" && !direct) { src = P->G; m = nn; }
+  else if (w == "Minv" && !direct) { src = P->Minv; m = nn; }
+  else if (w == "my" && !direct) { src = P->my; m = P->n; }
+  else if (w == "Ainv" && direct) { src = P->Ainv; m = (P->d + 1) * (P->d + 1); }
+  else return fail(DWD_E_INVALID, "unknown quantity for this problem's solver");
   if (count != m) return fail(DWD_E_INVALID, "wrong count");
   hipError_t e = hipSetDevice(P->device);
   if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
@@ -988,6 +1021,8 @@ dwd_status dwd_inspect(dwd_problem H, const char* what, double* out, int64_t cou
 
 int64_t dwd_footprint(const dwd_matrix* X, const dwd_params* p) {
   if (!X || !p || X->d < 1 || X->n < 1) return 0;
+  if (resolve_solver(p, X) == DWD_SOLVER_DIRECT)
+    return direct_footprint(X->d, (int)X->n, p->storage);
   return problem_footprint(X->d, (int)X->n, p->storage, X->layout, X->nnz);
 }
 

@@ -160,6 +160,8 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
     if (s != DWD_OK) return s;
   }
   if (P->layout != DWD_DENSE) return fail(DWD_E_INVALID, "dwd_solve_batch needs dense X");
+  if (P->solver != DWD_SOLVER_SMW)
+    return fail(DWD_E_INVALID, "dwd_solve_batch needs the SMW set-up");
   HIP_TRY_B(hipSetDevice(P->device));
   const hipStream_t st = P->stream;
   const int n = P->n;

@@ -140,6 +140,24 @@ struct BatchPtrs {
   int64_t ld;
 };
 
+// Direct branch (Section 3.3.1): pointers of one problem's iteration state.
+// d-vectors have length ld (ld + 1 for wbar and h, whose last entry is the
+// beta component); zz holds [Z~ dr | Z~ (xi - r) | Z~ alpha], each ld long.
+constexpr int NPD = 12;  // scalar partials per sweep block
+struct DirPtrs {
+  const double* y;
+  const double* e;
+  const double* Ainv;   // (d+1) x (d+1) row-major
+  double *r, *xi, *alpha, *zb, *rn, *dr;   // n
+  double *wbar, *w, *u, *rho, *h, *zz;     // d-space
+  double* part_d;       // nblk x 2 ld: sweep partials of the d-vector sums
+  double* part_n;       // nblk x NPD: sweep 1 scalar partials (y^T dr, Newton steps)
+  double* part_n2;      // nblk x NPD: sweep 2 scalar partials (Section 4.3 terms)
+  double* part_r;       // reduce-kernel partials of ||Z~ dr||^2
+  Scal* sc;
+  int nblk, per_block, nred;
+};
+
 // ---------------------------------------------------------------------------
 // Reductions (fixed order, hence deterministic).
 // ---------------------------------------------------------------------------
@@ -211,5 +229,13 @@ hipError_t launch_pair_hist(const double* G, int n, const int* ipos, int npos, c
                             int nneg, unsigned long long prefix, int shift, unsigned int* hist,
                             hipStream_t st);
 int gram_splits(int64_t ld, int n);
+// Direct branch (kernels_direct.hip).
+int fgram_splits(int d, int n);
+hipError_t launch_fgram(const void* X, int storage, int64_t ld, int n, int d, double* Kpart,
+                        int splits, hipStream_t st);
+hipError_t launch_fgram_finish(const double* Kpart, int splits, int d, int n, const double* zy,
+                               double inv_zs2, double mu, double* A, hipStream_t st);
+int dir_sweep_samples_per_block(int64_t ld, int n);
+int dir_reduce_blocks(int d, int nvec);
 
 }  // namespace dwd

@@ -192,6 +192,8 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
   for (int i = 0; i < nreq; ++i) {
     dwd_status s = validate_params(&reqs[i].params, true);
     if (s == DWD_OK) s = validate_penalty(&reqs[i].params, reqs[i].X.n);
+    if (s == DWD_OK && reqs[i].params.solver == DWD_SOLVER_DIRECT)
+      s = fail(DWD_E_INVALID, "dwd_serve runs the SMW form (solver must be SMW or AUTO)");
     if (s != DWD_OK) return s;
     memset(&out[i].info, 0, sizeof(dwd_info));
     out[i].status = DWD_E_BUSY;
@@ -266,7 +268,9 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
           hipHostMalloc((void**)&s.hs, sizeof(Scal), 0) != hipSuccess) {
         st = DWD_E_DEVICE;
       } else {
-        st = setup_problem(&q.X, q.y, &q.params, s.stream, &s.P);
+        dwd_params ps = q.params;
+        ps.solver = DWD_SOLVER_SMW;  // the serving loop steps SMW problems
+        st = setup_problem(&q.X, q.y, &ps, s.stream, &s.P);
       }
       if (st != DWD_OK) {
         out[r].status = st;

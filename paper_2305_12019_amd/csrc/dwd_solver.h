@@ -33,6 +33,14 @@ hipError_t launch_csr_dres(const int64_t* ip, const int32_t* ix, const void* val
                            int64_t d, const Consts& c, const double* alpha, const double* y,
                            const double* rho, double* part, hipStream_t st);
 bool iter_ptrs_ok(const IterPtrs& p);
+// launchers of the direct branch (kernels_direct.hip)
+hipError_t launch_dir_init(const Consts& c, const DirPtrs& p, double sigma0, hipStream_t st);
+hipError_t launch_dir_gemv(const Consts& c, const DirPtrs& p, int mode, hipStream_t st);
+hipError_t launch_dir_sweep(const void* X, int storage, const Consts& c, const DirPtrs& p,
+                            int mode, hipStream_t st);
+hipError_t launch_dir_reduce(const Consts& c, const DirPtrs& p, int v0, int nvec, double scale,
+                             hipStream_t st);
+hipError_t launch_dir_tail(const Consts& c, const DirPtrs& p, hipStream_t st);
 hipError_t launch_csr_frob(const void* val, int dtype, int64_t nnz, double* part, int nblk,
                            hipStream_t st);
 hipError_t launch_csr_gram(const int64_t* ip, const int32_t* ix, const void* val, int dtype, int n,
@@ -67,6 +75,9 @@ struct Problem {
   const void* X_rec = nullptr; // data of record (FP64 or FP32 image)
   int st_rec = DWD_FP32;
   const void* X_lowp = nullptr;  // BF16 image (storage == BF16)
+  int solver = DWD_SOLVER_SMW;  // factor built at set-up (SMW or direct)
+  double* Ainv = nullptr;      // direct: inverse of the (d+1)^2 eq-linsys matrix
+  DirPtrs dp{};                // direct: iteration state
   double* y = nullptr;
   double* e = nullptr;         // penalty weights of eq-primal (n)
   bool e_ones = true;          // e currently holds all ones
@@ -141,6 +152,16 @@ int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz
 dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params* p,
                          hipStream_t st, Problem** out);
 dwd_status suggest_C(Problem* P, double q, double* C);
+// Direct branch (dwd_direct.hip): the factor and buffers after the data are
+// staged (Z_scale known), and the solve loop.
+constexpr int64_t kDirectMaxD = 5120;
+int64_t direct_ld(int64_t d);
+dwd_status setup_direct(Problem* P, hipStream_t st);
+dwd_status solve_direct(Problem* P, const dwd_params* p, double* w, dwd_info* info,
+                        double* alpha, double* r, double* xi, double* u, double* rho);
+int64_t direct_footprint(int64_t d, int n, int storage);
+// The factor a set-up request resolves to (DWD_SOLVER_SMW or DWD_SOLVER_DIRECT).
+int resolve_solver(const dwd_params* p, const dwd_matrix* X);
 dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* info,
                          double* alpha, double* r, double* xi, double* u, double* rho);
 dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_info* info);

@@ -1,0 +1,730 @@
+// Direct branch of eq-linsys (Section 3.3.1, d much smaller than n): T = 0
+// and the whole (d+1) x (d+1) matrix
+//     A = [[Z~ Z~^T + mu I, Z~ y], [(Z~ y)^T, y^T y]]
+// formed once and inverted explicitly (one (d+1)^2 GEMV per solve in place
+// of two triangular solves).  One iteration of Algorithm 1 reads Z twice,
+// each time in one fused sweep over the samples:
+//
+//   sweep 1: z_i = (Z~^T wbar)_i, Step 1b prox c_i -> r_i^+, dr_i, and the
+//            partial sums of Z~ dr (Step 1c residual and re-solve);
+//   sweep 2: z_i = (Z~^T w)_i (reused from sweep 1 when Step 1c kept wbar),
+//            Step 2 xi_i, Step 3 alpha_i, the n-space terms of Section 4.3,
+//            and the partial sums of Z~ (xi - r) and Z~ alpha (the next
+//            right-hand side and eta_D3).
+//
+// A sample's data is read once per sweep and used both for its dot product
+// and for its share of the d-vector sums.  Samples are split over blocks;
+// inside a block, groups of TPS threads each take one sample at a time, a
+// thread holding NF feature quads (4 consecutive features) of it.  The
+// block partials of the d-vector sums are reduced by a separate kernel in a
+// fixed order (results do not depend on timing).
+//
+// Data layout: X is d x n, sample-contiguous, leading dimension ld = d
+// rounded up to 16 (padding rows 0), FP32 or FP64.  Every kernel returns at
+// once when the problem's stop flag is set.
+#include <float.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "dwd_device.h"
+#include "dwd_internal.h"
+
+namespace dwd {
+
+// ---------------------------------------------------------------------------
+// Feature Gram X X^T (d x d) in FP64 on FP64 MFMA 16x16x4: upper 64x64 tiles
+// over features, the sum over samples split into `splits` partial tiles.
+// ---------------------------------------------------------------------------
+typedef double d4v_t __attribute__((ext_vector_type(4)));
+constexpr int FT = 64;  // tile edge (features)
+constexpr int FK = 32;  // samples per LDS stage
+
+template <typename T>
+__device__ __forceinline__ void fgram_stage(const T* __restrict__ X, int64_t ld, int n, int f0,
+                                            int s0, int s1, double (*S)[FT + 1]) {
+  constexpr int V = 16 / sizeof(T);  // elements per 16-byte load
+  constexpr int PER = FT / V;        // loads per sample row of the tile
+  for (int e = threadIdx.x; e < FK * PER; e += 256) {
+    const int k = e / PER, c = (e % PER) * V;
+    const int s = s0 + k;
+    const int64_t f = (int64_t)f0 + c;
+    if (s < s1 && f < ld) {
+      if constexpr (sizeof(T) == 8) {
+        const double2 v = *reinterpret_cast<const double2*>(X + (int64_t)s * ld + f);
+        S[k][c] = v.x;
+        S[k][c + 1] = v.y;
+      } else {
+        const float4 v = *reinterpret_cast<const float4*>(X + (int64_t)s * ld + f);
+        S[k][c] = v.x;
+        S[k][c + 1] = v.y;
+        S[k][c + 2] = v.z;
+        S[k][c + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < V; ++q) S[k][c + q] = 0.0;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fgram_mfma(const T* __restrict__ X, int64_t ld, int n,
+                                                    int d, int ntile, int splits,
+                                                    double* __restrict__ Kpart) {
+  int t = blockIdx.x;
+  int ti = 0;
+  while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
+  const int tj = ti + t;
+  const int per = ((n + FK - 1) / FK + splits - 1) / splits * FK;
+  const int s_lo = blockIdx.y * per;
+  const int s_hi = min(n, s_lo + per);
+  __shared__ double As[FK][FT + 1];
+  __shared__ double Bs[FK][FT + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = (wid >> 1) * 32, wc = (wid & 1) * 32;
+  const int f0 = ti * FT, g0 = tj * FT;
+  d4v_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (d4v_t){0.0, 0.0, 0.0, 0.0};
+  for (int s0 = s_lo; s0 < s_hi; s0 += FK) {
+    fgram_stage<T>(X, ld, n, f0, s0, s_hi, As);
+    fgram_stage<T>(X, ld, n, g0, s0, s_hi, Bs);
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < FK; ks += 4) {
+      const int li = lane & 15, lk = lane >> 4;
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[ks + lk][wr + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[ks + lk][wc + b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* out = Kpart + (size_t)blockIdx.y * d * d;
+  const int lj = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = f0 + wr + a * 16 + v * 4 + lg;
+        const int gj = g0 + wc + b * 16 + lj;
+        if (gi < d && gj < d) out[(size_t)gi * d + gj] = acc[a][b][v];
+      }
+}
+
+int fgram_splits(int d, int n) {
+  const int nt = (d + FT - 1) / FT;
+  const int tiles = nt * (nt + 1) / 2;
+  int s = (2048 + tiles - 1) / tiles;
+  const int kmax = (n + FK - 1) / FK;
+  s = std::min(s, kmax);
+  s = std::min(s, 256);
+  return std::max(s, 1);
+}
+
+hipError_t launch_fgram(const void* X, int storage, int64_t ld, int n, int d, double* Kpart,
+                        int splits, hipStream_t st) {
+  const int nt = (d + FT - 1) / FT;
+  dim3 grid(nt * (nt + 1) / 2, splits);
+  if (storage == DWD_FP64)
+    hipLaunchKernelGGL(k_fgram_mfma<double>, grid, dim3(256), 0, st, (const double*)X, ld, n, d,
+                       nt, splits, Kpart);
+  else
+    hipLaunchKernelGGL(k_fgram_mfma<float>, grid, dim3(256), 0, st, (const float*)X, ld, n, d,
+                       nt, splits, Kpart);
+  return hipGetLastError();
+}
+
+// A ((d+1) x (d+1), row-major): the split partials summed in order, scaled
+// by 1/Z_scale^2 (y_i^2 = 1), mu on the diagonal, Z~ y in the last row and
+// column, y^T y = n in the corner.
+__global__ void __launch_bounds__(256) k_fgram_finish(const double* __restrict__ Kpart,
+                                                      int splits, int d, int n,
+                                                      const double* __restrict__ zy,
+                                                      double inv_zs2, double mu,
+                                                      double* __restrict__ A) {
+  const int64_t m = (int64_t)(d + 1) * (d + 1);
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * 256) {
+    const int a = (int)(t / (d + 1)), b = (int)(t % (d + 1));
+    double v;
+    if (a < d && b < d) {
+      const int lo = min(a, b), hi = max(a, b);
+      double s = 0.0;
+      for (int k = 0; k < splits; ++k) s += Kpart[(size_t)k * d * d + (size_t)lo * d + hi];
+      v = s * inv_zs2 + (a == b ? mu : 0.0);
+    } else if (a < d) {
+      v = zy[a];
+    } else if (b < d) {
+      v = zy[b];
+    } else {
+      v = (double)n;
+    }
+    A[t] = v;
+  }
+}
+
+hipError_t launch_fgram_finish(const double* Kpart, int splits, int d, int n, const double* zy,
+                               double inv_zs2, double mu, double* A, hipStream_t st) {
+  const int64_t m = (int64_t)(d + 1) * (d + 1);
+  const int blocks = (int)std::min<int64_t>(4096, (m + 255) / 256);
+  hipLaunchKernelGGL(k_fgram_finish, dim3(blocks), dim3(256), 0, st, Kpart, splits, d, n, zy,
+                     inv_zs2, mu, A);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Initial point (r, xi, w, beta, u) = (1, 1, 0, 0, 0), (alpha, rho) = (0, 0);
+// the first right-hand side is then 0.
+// ---------------------------------------------------------------------------
+__global__ void k_dir_init(Consts c, DirPtrs p, double sigma0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < c.n) {
+    p.r[i] = 1.0;
+    p.xi[i] = 1.0;
+    p.alpha[i] = 0.0;
+  }
+  if (i <= c.ld) {
+    p.h[i] = 0.0;
+    p.wbar[i] = 0.0;
+  }
+  if (i < c.ld) {
+    p.w[i] = 0.0;
+    p.u[i] = 0.0;
+    p.rho[i] = 0.0;
+  }
+  if (i == 0) {
+    Scal* s = p.sc;
+    s->sigma = sigma0;
+    s->beta = 0.0;
+    s->beta_bar = 0.0;
+    s->gamma = 1.0;
+    s->ytdr = 0.0;
+    s->beta1 = 0.0;
+    s->u2 = 0.0;
+    s->k = 0;
+    s->done = 0;
+    s->converged = 0;
+    s->n_double = 0;
+    s->newton_max = 0;
+    s->doubled = 0;
+    s->status = 0;
+    s->frozen_iter = 0;
+    s->redo = 0;
+    for (int j = 0; j < R_COUNT; ++j) s->red[j] = 0.0;
+    for (int j = 0; j < E_COUNT; ++j) s->eta[j] = 0.0;
+  }
+}
+
+hipError_t launch_dir_init(const Consts& c, const DirPtrs& p, double sigma0, hipStream_t st) {
+  const int64_t m = std::max<int64_t>(c.n, c.ld + 1);
+  hipLaunchKernelGGL(k_dir_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, c, p,
+                     sigma0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Solves with A^-1 ((d+1)^2 row-major), one wave per row.
+//   mode 0 (Step 1a): wbar = A^-1 h   (h = [h_w; h_beta], written by the tail).
+//   mode 1 (Step 1c): the residual ||[Z~ dr; y^T dr]|| (the right-hand side
+//     grows by exactly that vector when r moves by dr, and A [wbar; betabar]
+//     = h) is summed by every wave in the same order; above 5 eps_k,
+//     [w; beta] = [wbar; betabar] + A^-1 [Z~ dr; y^T dr], else [wbar; betabar].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_dir_gemv(Consts c, DirPtrs p, int mode) {
+  Scal* sc = p.sc;
+  const int done = sc->done;
+  const int k = sc->k;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int d = (int)c.d;
+  const int m = d + 1;
+  if (done) return;
+  int redo = 1;
+  double ydr = 0.0;
+  if (mode == 1) {
+    double s2 = 0.0, sy = 0.0;
+    for (int b = lane; b < p.nred; b += 64) s2 += p.part_r[b];
+    for (int b = lane; b < p.nblk; b += 64) sy += p.part_n[(size_t)b * NPD + 0];
+    s2 = wave_sum(s2);
+    ydr = wave_sum(sy);
+    const double res = sqrt(fmax(s2 + ydr * ydr, 0.0));
+    redo = res > 5.0 * eps_k(c, k) ? 1 : 0;
+  }
+  if (row >= m) return;
+  double acc = 0.0;
+  if (redo) {
+    const double* Ar = p.Ainv + (size_t)row * m;
+    const double* rhs = mode == 0 ? p.h : p.zz;  // zz[0..d) = Z~ dr
+    for (int j = lane; j < m; j += 64) {
+      const double v = (mode == 1 && j == d) ? ydr : rhs[j];
+      acc = fma(Ar[j], v, acc);
+    }
+    acc = wave_sum(acc);
+  }
+  if (lane != 0) return;
+  if (mode == 0) {
+    p.wbar[row] = acc;
+  } else {
+    const double x = p.wbar[row] + acc;
+    if (row < d) {
+      p.w[row] = x;
+    } else {
+      sc->beta = x;
+      sc->doubled = redo;
+      sc->n_double += redo;
+    }
+  }
+}
+
+hipError_t launch_dir_gemv(const Consts& c, const DirPtrs& p, int mode, hipStream_t st) {
+  const int m = (int)c.d + 1;
+  hipLaunchKernelGGL(k_dir_gemv, dim3((m + 3) / 4), dim3(256), 0, st, c, p, mode);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The fused sweeps.
+//   MODE 0: sum_i x_i                                (set-up: Z~ y = that / Z_scale)
+//   MODE 1: sweep 1 of the iteration (see the file comment)
+//   MODE 2: sweep 2
+// Partials: part_d[b][v*ld + f] (v = 0, 1), part_n[b][0..NPD).
+// ---------------------------------------------------------------------------
+// (ordinary cached loads: in the regime of this branch X is often small
+// enough to stay in the last-level cache between the two sweeps)
+template <typename T>
+struct Quad;
+template <>
+struct Quad<float> {
+  __device__ static void load(const float* p, double (&o)[4]) {
+    const nt_f4 v = *reinterpret_cast<const nt_f4*>(p);
+    o[0] = v[0];
+    o[1] = v[1];
+    o[2] = v[2];
+    o[3] = v[3];
+  }
+};
+template <>
+struct Quad<double> {
+  __device__ static void load(const double* p, double (&o)[4]) {
+    const nt_d2 a = *reinterpret_cast<const nt_d2*>(p);
+    const nt_d2 b = *(reinterpret_cast<const nt_d2*>(p) + 1);
+    o[0] = a[0];
+    o[1] = a[1];
+    o[2] = b[0];
+    o[3] = b[1];
+  }
+};
+
+template <int TPS>
+__device__ __forceinline__ double group_sum(double v, double* lds) {
+  if constexpr (TPS <= 64) {
+#pragma unroll
+    for (int off = TPS / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+  } else {
+    // the whole block is one group
+    return block_sum<256>(v);
+  }
+}
+
+template <typename T, int TPS, int NF, int MODE>
+__global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Consts c, DirPtrs p) {
+  constexpr int G = 256 / TPS;
+  constexpr int NV = MODE == 2 ? 2 : 1;
+  Scal* sc = p.sc;
+  const int done = MODE == 0 ? 0 : sc->done;
+  const int lg = threadIdx.x % TPS, g = threadIdx.x / TPS;
+  const int64_t ld = c.ld;
+  const int n = c.n;
+  const int i0 = blockIdx.x * p.per_block;
+  const int i1 = min(n, i0 + p.per_block);
+  // the d-vector this sweep multiplies, in registers
+  double wv[NF][4];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    const int64_t f = 4 * (int64_t)(lg + j * TPS);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double v = 0.0;
+      if (MODE != 0 && f < ld) v = (MODE == 1 ? p.wbar : p.w)[f + q];
+      wv[j][q] = v;
+    }
+  }
+  const double sigma = MODE == 0 ? 1.0 : sc->sigma;
+  const double beta = MODE == 1 ? p.wbar[c.d] : (MODE == 2 ? sc->beta : 0.0);
+  const int redo = MODE == 2 ? sc->doubled : 1;
+  const int kk = MODE == 0 ? 0 : sc->k;
+  if (done) return;
+  const double tolN = eps_k(c, kk) / sqrt((double)n);
+  double acc[NV][NF][4];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[v][j][q] = 0.0;
+  constexpr int KS = MODE == 2 ? 10 : 2;
+  double ssum[KS];
+#pragma unroll
+  for (int j = 0; j < KS; ++j) ssum[j] = 0.0;
+  __shared__ double lds_red[4];
+  for (int ib = i0; ib < i1; ib += G) {
+    const int i = ib + g;
+    const bool live = i < i1;
+    double xv[NF][4];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      const int64_t f = 4 * (int64_t)(lg + j * TPS);
+      if (live && f < ld) {
+        Quad<T>::load(X + (int64_t)i * ld + f, xv[j]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xv[j][q] = 0.0;
+      }
+    }
+    double cf0 = 1.0, cf1 = 0.0;
+    if constexpr (MODE != 0) {
+      double dot = 0.0;
+      if (MODE == 1 || redo) {
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dot = fma(xv[j][q], wv[j][q], dot);
+        dot = group_sum<TPS>(dot, lds_red);
+      }
+      if (live) {
+        const double yi = p.y[i];
+        const double al = p.alpha[i];
+        if constexpr (MODE == 1) {
+          const double z = yi * dot * c.inv_zs;
+          const double r0 = p.r[i];
+          const double cc = z + yi * beta + p.xi[i] - al / sigma;
+          int steps = 0;
+          const double rn = prox_weighted(cc, sigma, r0, tolN, loss_weight(c, yi), c, steps);
+          const double dr = rn - r0;
+          cf0 = yi * dr;
+          if (lg == 0) {
+            p.zb[i] = z;
+            p.rn[i] = rn;
+            p.dr[i] = dr;
+            ssum[0] += yi * dr;
+            ssum[1] = fmax(ssum[1], (double)steps);
+          }
+        } else {
+          const double z = redo ? yi * dot * c.inv_zs : p.zb[i];
+          const double rn = p.rn[i];
+          const double ei = p.e[i];
+          const double xin = fmax(0.0, rn - z - yi * beta + (al - c.C * ei) / sigma);
+          const double pres = z + yi * beta + xin - rn;
+          const double a1 = al - c.tau * sigma * pres;
+          cf0 = yi * (xin - rn);
+          cf1 = yi * a1;
+          if (lg == 0) {
+            p.r[i] = rn;
+            p.xi[i] = xin;
+            p.alpha[i] = a1;
+            double s9[9];
+            nspace_sums(c, pow_q(rn, c), pow_qp1(rn, c), a1, xin, pres, yi, ei, s9);
+#pragma unroll
+            for (int j = 0; j < 9; ++j) ssum[j] += s9[j];
+            ssum[9] += yi * (xin - rn);
+          }
+        }
+      } else {
+        cf0 = 0.0;
+        cf1 = 0.0;
+      }
+    } else {
+      if (!live) cf0 = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[0][j][q] = fma(cf0, xv[j][q], acc[0][j][q]);
+        if constexpr (NV == 2) acc[1][j][q] = fma(cf1, xv[j][q], acc[1][j][q]);
+      }
+  }
+  // d-vector partials: the groups of the block summed in order
+  double* out = p.part_d + (size_t)blockIdx.x * 2 * ld;
+  if constexpr (G == 1) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) {
+        const int64_t f = 4 * (int64_t)(lg + j * TPS);
+        if (f < ld) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) out[v * ld + f + q] = acc[v][j][q];
+        }
+      }
+  } else {
+    __shared__ double buf[NV][TPS * NF * 4];
+    for (int gg = 0; gg < G; ++gg) {
+      if (g == gg) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int j = 0; j < NF; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int o = 4 * (lg + j * TPS) + q;
+              buf[v][o] = gg == 0 ? acc[v][j][q] : buf[v][o] + acc[v][j][q];
+            }
+      }
+      __syncthreads();
+    }
+    for (int v = 0; v < NV; ++v)
+      for (int o = threadIdx.x; o < TPS * NF * 4 && o < ld; o += 256) out[v * ld + o] = buf[v][o];
+  }
+  // scalar partials: the group leaders summed in order
+  if constexpr (MODE != 0) {
+    __shared__ double sbuf[G][KS];
+    if (lg == 0) {
+#pragma unroll
+      for (int j = 0; j < KS; ++j) sbuf[g][j] = ssum[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < KS) {
+      const int j = threadIdx.x;
+      double s = sbuf[0][j];
+      for (int gg = 1; gg < G; ++gg)
+        s = (MODE == 1 && j == 1) ? fmax(s, sbuf[gg][j]) : s + sbuf[gg][j];
+      (MODE == 1 ? p.part_n : p.part_n2)[(size_t)blockIdx.x * NPD + j] = s;
+    }
+  }
+}
+
+// threads per sample and feature quads per thread for a leading dimension
+static void sweep_shape(int64_t ld, int* tps, int* nf) {
+  const int64_t quads = ld / 4;
+  if (quads <= 32) {
+    *tps = 16;
+    *nf = (int)((quads + 15) / 16);
+  } else if (quads <= 256) {
+    *tps = 64;
+    *nf = (int)((quads + 63) / 64);
+  } else {
+    *tps = 256;
+    *nf = (int)((quads + 255) / 256);
+  }
+}
+
+int dir_sweep_samples_per_block(int64_t ld, int n) {
+  int tps, nf;
+  sweep_shape(ld, &tps, &nf);
+  const int G = 256 / tps;
+  // about 8 samples per group, at most 1024 blocks
+  int per = std::max(G * 8, (n + 1023) / 1024);
+  per = (per + G - 1) / G * G;
+  return per;
+}
+
+template <typename T, int MODE>
+static hipError_t sweep_t(const T* X, const Consts& c, const DirPtrs& p, hipStream_t st) {
+  int tps, nf;
+  sweep_shape(c.ld, &tps, &nf);
+  const dim3 grid((unsigned)p.nblk), blk(256);
+#define DWD_SWEEP(TP, NFV)                                                                 \
+  if (tps == TP && nf == NFV) {                                                            \
+    hipLaunchKernelGGL((k_dir_sweep<T, TP, NFV, MODE>), grid, blk, 0, st, X, c, p);        \
+    return hipGetLastError();                                                              \
+  }
+  DWD_SWEEP(16, 1) DWD_SWEEP(16, 2)
+  DWD_SWEEP(64, 1) DWD_SWEEP(64, 2) DWD_SWEEP(64, 3) DWD_SWEEP(64, 4)
+  DWD_SWEEP(256, 2) DWD_SWEEP(256, 3) DWD_SWEEP(256, 4) DWD_SWEEP(256, 5)
+#undef DWD_SWEEP
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dir_sweep(const void* X, int storage, const Consts& c, const DirPtrs& p,
+                            int mode, hipStream_t st) {
+  if (storage == DWD_FP64) {
+    const double* Xd = (const double*)X;
+    if (mode == 0) return sweep_t<double, 0>(Xd, c, p, st);
+    if (mode == 1) return sweep_t<double, 1>(Xd, c, p, st);
+    return sweep_t<double, 2>(Xd, c, p, st);
+  }
+  const float* Xf = (const float*)X;
+  if (mode == 0) return sweep_t<float, 0>(Xf, c, p, st);
+  if (mode == 1) return sweep_t<float, 1>(Xf, c, p, st);
+  return sweep_t<float, 2>(Xf, c, p, st);
+}
+
+// ---------------------------------------------------------------------------
+// Sum the sweep partials over blocks (fixed order) into zz[v0 + v] (v < nvec),
+// times `scale`; with nvec = 1 also the block partials of the squared norm
+// (the Step 1c residual).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_dir_reduce(Consts c, DirPtrs p, int v0, int nvec,
+                                                    double scale) {
+  const int done = p.sc->done;
+  const int64_t ld = c.ld;
+  const int d = (int)c.d;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int v = (int)(t / d), f = (int)(t % d);
+  if (done) return;
+  double s = 0.0;
+  if (v < nvec) {
+    const double* src = p.part_d + (size_t)v * ld + f;
+    for (int b = 0; b < p.nblk; ++b) s += src[(size_t)b * 2 * ld];
+    s *= scale;
+    p.zz[(size_t)(v0 + v) * ld + f] = s;
+  }
+  if (nvec == 1) {
+    const double sq = block_sum<256>(v < nvec ? s * s : 0.0);
+    if (threadIdx.x == 0) p.part_r[blockIdx.x] = sq;
+  }
+}
+
+int dir_reduce_blocks(int d, int nvec) { return (nvec * d + 255) / 256; }
+
+hipError_t launch_dir_reduce(const Consts& c, const DirPtrs& p, int v0, int nvec, double scale,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_dir_reduce, dim3(dir_reduce_blocks((int)c.d, nvec)), dim3(256), 0, st, c,
+                     p, v0, nvec, scale);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// End of the iteration (one block): Step 2 u, Step 3 rho, the d-space terms
+// of Section 4.3, the residuals, the stopping and sigma rules, and the next
+// right-hand side h = -Z~ t + mu u + sqrt(mu) rho / sigma, h_beta = -y^T t
+// with t = xi - r - alpha / sigma (sigma the updated one).
+// ---------------------------------------------------------------------------
+constexpr int NTD = 1024;
+constexpr int MAXF = 8;  // d <= NTD * MAXF
+
+__global__ void __launch_bounds__(NTD) k_dir_tail(Consts c, DirPtrs p) {
+  Scal* sc = p.sc;
+  if (sc->done) return;
+  const int d = (int)c.d;
+  const int64_t ld = c.ld;
+  const int k0 = sc->k;
+  const double sigma = sc->sigma;
+  const int nm = sc->newton_max;
+  __shared__ double s_sig;
+  // n-space sums of sweep 2, the Newton-step maximum of sweep 1
+  constexpr int K = 10;
+  double ns[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) ns[j] = 0.0;
+  double nmax = 0.0;
+  for (int b = threadIdx.x; b < p.nblk; b += NTD) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) ns[j] += p.part_n2[(size_t)b * NPD + j];
+    nmax = fmax(nmax, p.part_n[(size_t)b * NPD + 1]);
+  }
+  block_sum_k<NTD, K>(ns);
+  {
+    __shared__ double smax[NTD / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nmax = fmax(nmax, __shfl_xor(nmax, off, 64));
+    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = nmax;
+    __syncthreads();
+    double m = smax[0];
+    for (int w = 1; w < NTD / 64; ++w) m = fmax(m, smax[w]);
+    nmax = m;
+  }
+  // Step 2: g = w - rho / (sigma sqrt(mu)), u = g min(1, R / ||g||)
+  double wv[MAXF], rv[MAXF], gv[MAXF];
+  double g2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < MAXF; ++j) {
+    const int f = threadIdx.x + j * NTD;
+    wv[j] = f < d ? p.w[f] : 0.0;
+    rv[j] = f < d ? p.rho[f] : 0.0;
+    gv[j] = wv[j] - rv[j] / (sigma * c.sqmu);
+    g2 = fma(gv[j], gv[j], g2);
+  }
+  g2 = block_sum<NTD>(g2);
+  const double ng = sqrt(g2);
+  const double gamma = ng <= c.R ? 1.0 : c.R / ng;
+  // Step 3: rho' = rho - tau sigma sqrt(mu) (w - u); d-space sums
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // ||w-u||^2, ||w||^2, ||Z~a + D rho'||^2, ||Z~a||^2
+  const double* za = p.zz + 2 * ld;
+#pragma unroll
+  for (int j = 0; j < MAXF; ++j) {
+    const int f = threadIdx.x + j * NTD;
+    const double u = gamma * gv[j];
+    const double rn = rv[j] - c.tau * sigma * c.sqmu * (wv[j] - u);
+    gv[j] = u;
+    rv[j] = rn;
+    if (f < d) {
+      const double zf = za[f];
+      const double dres = zf + c.sqmu * rn;
+      acc[0] = fma(wv[j] - u, wv[j] - u, acc[0]);
+      acc[1] = fma(wv[j], wv[j], acc[1]);
+      acc[2] = fma(dres, dres, acc[2]);
+      acc[3] = fma(zf, zf, acc[3]);
+    }
+  }
+  block_sum_k<NTD, 4>(acc);
+  if (threadIdx.x == 0) {
+    double red[R_COUNT];
+    for (int j = 0; j < 9; ++j) red[R_PRES2 + j] = ns[j];
+    red[R_WU2] = acc[0];
+    red[R_W2] = acc[1];
+    red[R_DRES2] = acc[2];
+    red[R_ZA2] = acc[3];
+    red[R_G2] = g2;
+    red[R_RHO2] = 0.0;
+    double e[E_COUNT];
+    finish_etas(c, red, e);
+    // every residual here comes from explicit passes of this iteration
+    e[E_PCHK] = e[E_P];
+    e[E_DCHK] = e[E_D];
+    for (int j = 0; j < R_COUNT; ++j) sc->red[j] = red[j];
+    for (int j = 0; j < E_COUNT; ++j) sc->eta[j] = e[j];
+    sc->gamma = gamma;
+    if ((int)nmax > nm) sc->newton_max = (int)nmax;
+    const int k1 = k0 + 1;
+    sc->k = k1;
+    bool stop = false;
+    const double sig = stop_and_sigma(c, e, sigma, k1, &stop);
+    if (stop) {
+      sc->converged = 1;
+      sc->done = 1;
+    } else if (k1 >= c.max_iter) {
+      sc->done = 1;
+    }
+    sc->sigma = sig;
+    s_sig = sig;
+  }
+  __syncthreads();
+  const double sig1 = s_sig;
+  const double* zxr = p.zz + ld;
+#pragma unroll
+  for (int j = 0; j < MAXF; ++j) {
+    const int f = threadIdx.x + j * NTD;
+    if (f < d) {
+      p.u[f] = gv[j];
+      p.rho[f] = rv[j];
+      p.h[f] = -(zxr[f] - za[f] / sig1) + c.mu * gv[j] + c.sqmu * rv[j] / sig1;
+    }
+  }
+  if (threadIdx.x == 0) {
+    // h_beta = -y^T t = -(y^T (xi - r) - y^T alpha / sigma')
+    p.h[d] = -(ns[9] - ns[3] / sig1);
+  }
+}
+
+hipError_t launch_dir_tail(const Consts& c, const DirPtrs& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_dir_tail, dim3(1), dim3(NTD), 0, st, c, p);
+  return hipGetLastError();
+}
+
+}  // namespace dwd

@@ -1,0 +1,196 @@
+"""Parity of the direct branch (Section 3.3.1: the whole (d+1) x (d+1) matrix
+of eq-linsys, formed and inverted once) with the FP64 oracle's direct branch,
+through the C ABI.  Shapes cover every sweep configuration (16, 64 and 256
+threads per sample, 1 to 5 feature quads per thread), ragged n, and n beyond
+the SMW factor's limit.  Bar as in the other parity tests."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dwd_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dwd():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_12019_amd import dwd as D
+    return D
+
+
+def _obj(X, y, C, q, s, wt=None, e=None):
+    w = np.asarray(s["w"], np.float64)
+    return O.reduced_objective(X, y, w / max(1.0, np.linalg.norm(w)), s["beta"], C, q, wt, e)
+
+
+def _oracle_A(X, y, mu=1.0):
+    Zt, _ = O.scale_data(X, y)
+    d = Zt.shape[0]
+    A = np.empty((d + 1, d + 1))
+    A[:d, :d] = Zt @ Zt.T + mu * np.eye(d)
+    A[:d, d] = A[d, :d] = Zt @ y
+    A[d, d] = y @ y
+    return A
+
+
+@pytest.mark.parametrize("d,n,storage", [(5, 40, "f64"), (30, 500, "f64"), (300, 2000, "f32"),
+                                         (1500, 3000, "f32"), (77, 1031, "f32"),
+                                         (3000, 4000, "f32")])
+def test_direct_setup_matches_oracle(dwd, d, n, storage):
+    X, y = synth.random_two_class(d, n, seed=d + n, dtype="f64" if storage == "f64" else "f32")
+    P = dwd.Problem(X, y, storage=storage, solver="direct", mu=1.3)
+    assert P.inspect("solver")[0] == 1
+    Ai = P.inspect("Ainv")
+    P.close()
+    A = _oracle_A(X, y, mu=1.3)
+    ref = np.linalg.inv(A)
+    assert np.max(np.abs(Ai - ref)) <= 1e-9 * np.max(np.abs(ref))
+    # and it is the inverse of the oracle's matrix
+    assert np.max(np.abs(Ai @ A - np.eye(d + 1))) <= 1e-8
+
+
+@pytest.mark.parametrize("d,n,storage", [(40, 300, "f64"), (600, 1000, "f32"), (9, 700, "f32"),
+                                         (5000, 6000, "f32"), (2100, 2500, "f64")])
+def test_direct_trajectory_follows_oracle(dwd, d, n, storage):
+    X, y = synth.random_two_class(d, n, seed=3 * d + n, mean=0.5, pos_frac=0.3,
+                                  dtype="f64" if storage == "f64" else "f32")
+    e = synth.penalty_vector(n, seed=n + 1)
+    C, q = 1.5, 1.0
+    P = dwd.Problem(X, y, storage=storage, solver="direct")
+    for k in (1, 2, 5, 20):
+        o = O.solve(X, y, C, q, tol=1e-300, max_iter=k, solver="direct", weights=True, e=e)
+        g = P.solve(C, q, tol=1e-300, max_iter=k, class_weights=1, e=e)
+        assert g["info"]["iters"] == k
+        for key in ("alpha", "r", "xi"):
+            assert np.allclose(g[key], o[key], rtol=1e-9, atol=1e-12), (k, key)
+        for key in ("w", "u", "rho"):
+            assert np.allclose(g[key], o[key], rtol=1e-9,
+                               atol=1e-12 * max(1e-300, np.abs(o[key]).max())), (k, key)
+        assert abs(g["beta"] - o["beta"]) <= 1e-9 * max(1.0, abs(o["beta"])), k
+        assert abs(g["info"]["sigma"] - o["sigma"]) <= 1e-12 * o["sigma"]
+        assert g["info"]["n_double"] == o["n_double"], k
+    P.close()
+
+
+@pytest.mark.parametrize("d,n,q,C,storage", [
+    (10, 5000, 1.0, 1.0, "f32"),
+    (54, 20000, 2.0, 0.5, "f32"),
+    (300, 3000, 0.5, 0.2, "f64"),
+    (1200, 4000, 1.0, 2.0, "f32"),
+    (130, 777, 4.0, 10.0, "f32"),
+])
+def test_direct_solves_match_oracle(dwd, d, n, q, C, storage):
+    # With d < n these problems have many margin violations and the ADMM tail
+    # is slow (tens of thousands of iterations to 1e-9), so both sides stop at
+    # 1e-7 and 1e-6 and are compared at the same stopping point; the
+    # objective is checked against a library solver where d is small.
+    X, y = synth.random_two_class(d, n, seed=d * 7 + n, mean=0.4, flip=0.1,
+                                  dtype="f64" if storage == "f64" else "f32")
+    P = dwd.Problem(X, y, storage=storage, solver="direct")
+    for tol in (1e-7, 1e-6):
+        ref = O.solve(X, y, C, q, tol=tol, max_iter=20000, solver="direct")
+        assert ref["converged"]
+        got = P.solve(C, q, tol=tol, max_iter=20000)
+        assert got["info"]["converged"] == 1, got["info"]
+        assert abs(got["info"]["iters"] - ref["iters"]) <= max(3, 0.1 * ref["iters"])
+        fg, fr = _obj(X, y, C, q, got), _obj(X, y, C, q, ref)
+        assert abs(fg - fr) <= 1e-6 * abs(fr), (tol, fg, fr)
+        assert np.linalg.norm(got["w"] - ref["w"]) <= 1e-4 * np.linalg.norm(ref["w"]), tol
+        k = O.kkt_of_solution(X, y, C, q, got)
+        assert max(k["P"], k["D"]) <= 2 * tol, k
+        assert got["info"]["kkt_check"] <= 2 * tol
+    P.close()
+    if d <= 130:
+        import scipy.optimize as sopt
+        ts = (q / C) ** (1 / (q + 1))
+        Xd = X.astype(np.float64)
+
+        def f(v):
+            w, b = v[:d], v[d]
+            m = y * (Xd @ w + b)
+            hi = m >= ts
+            mm = np.where(hi, m, 1.0)
+            val = np.where(hi, mm ** -q, ts ** -q + C * (ts - m))
+            dv = np.where(hi, -q * mm ** (-q - 1), -C) * y
+            return val.sum(), np.concatenate([Xd.T @ dv, [dv.sum()]])
+
+        cons = [{"type": "ineq", "fun": lambda v: 1.0 - v[:d] @ v[:d],
+                 "jac": lambda v: np.concatenate([-2 * v[:d], [0.0]])}]
+        res = sopt.minimize(f, np.zeros(d + 1), jac=True, method="SLSQP", constraints=cons,
+                            options={"ftol": 1e-15, "maxiter": 3000})
+        assert abs(_obj(X, y, C, q, got) - res.fun) <= 1e-5 * abs(res.fun)
+
+
+def test_direct_and_smw_give_the_same_solution(dwd):
+    X, y = synth.random_two_class(200, 900, seed=31, mean=0.5, dtype="f32")
+    a = dwd.solve(X, y, 1.0, 1.0, tol=1e-8, solver="direct", max_iter=20000)
+    b = dwd.solve(X, y, 1.0, 1.0, tol=1e-8, solver="smw", max_iter=20000)
+    assert a["info"]["converged"] == 1 and b["info"]["converged"] == 1
+    assert np.linalg.norm(a["w"] - b["w"]) <= 1e-5 * np.linalg.norm(b["w"])
+    assert abs(a["info"]["iters"] - b["info"]["iters"]) <= max(3, 0.1 * b["info"]["iters"])
+
+
+def test_direct_beyond_the_smw_limit(dwd):
+    # n = 200000 > 65536: only the direct branch takes it
+    d, n = 54, 200_000
+    X, y = synth.random_two_class(d, n, seed=37, mean=0.3, flip=0.05, pos_frac=0.2,
+                                  dtype="f32")
+    with pytest.raises(dwd.DwdError):
+        dwd.Problem(X, y, storage="f32", solver="smw")
+    P = dwd.Problem(X, y, storage="f32", solver="auto")
+    assert P.inspect("solver")[0] == 1
+    got = P.solve(1.0, 1.0, tol=1e-6, class_weights=1)
+    P.close()
+    assert got["info"]["converged"] == 1, got["info"]
+    ref = O.solve(X, y, 1.0, 1.0, tol=1e-6, max_iter=20000, solver="direct", weights=True)
+    assert ref["converged"]
+    assert abs(got["info"]["iters"] - ref["iters"]) <= max(3, 0.1 * ref["iters"])
+    wt = O.class_weights(y, 1.0)
+    fg, fr = _obj(X, y, 1.0, 1.0, got, wt), _obj(X, y, 1.0, 1.0, ref, wt)
+    assert abs(fg - fr) <= 1e-6 * abs(fr), (fg, fr)
+    assert np.linalg.norm(got["w"] - ref["w"]) <= 1e-4 * np.linalg.norm(ref["w"])
+    k = O.kkt_of_solution(X, y, 1.0, 1.0, got, weights=True)
+    assert max(k["P"], k["D"]) <= 1.5e-6, k
+
+
+def test_auto_solver_choice(dwd):
+    X, y = synth.random_two_class(100, 50, seed=41, dtype="f32")
+    P = dwd.Problem(X, y, storage="f32", solver="auto")
+    assert P.inspect("solver")[0] == 1            # d <= 5000: direct
+    P.close()
+    X, y = synth.random_two_class(6000, 100, seed=42, dtype="f32")
+    P = dwd.Problem(X, y, storage="f32", solver="auto")
+    assert P.inspect("solver")[0] == 0            # d > 5000, n < 0.2 d: SMW
+    P.close()
+    X, y = synth.random_two_class(100, 50, seed=43, dtype="f32")
+    P = dwd.Problem(X, y, storage="bf16", solver="auto")
+    assert P.inspect("solver")[0] == 0            # BF16 storage: SMW
+    P.close()
+
+
+def test_direct_rejections_and_cap(dwd):
+    X, y = synth.random_two_class(60, 400, seed=47, dtype="f32")
+    P = dwd.Problem(X, y, storage="f32", solver="direct")
+    with pytest.raises(dwd.DwdError):
+        P.solve_batch([dict(C=1.0, q=1.0)])
+    with pytest.raises(dwd.DwdError):
+        P.solve(1.0, 1.0, representer=1)
+    with pytest.raises(dwd.DwdError):
+        P.suggest_C(1.0)
+    with pytest.raises(dwd.DwdError):
+        P.inspect("G")
+    capped = P.solve(1.0, 1.0, tol=1e-9, max_iter=3)
+    assert capped["status"] == 1 and capped["info"]["iters"] == 3
+    ok = P.solve(1.0, 1.0, tol=1e-6)
+    assert ok["info"]["converged"] == 1
+    P.close()
+    with pytest.raises(dwd.DwdError):
+        dwd.Problem(X, y, storage="bf16", solver="direct")
+    Xw, yw = synth.random_two_class(5200, 20, seed=48, dtype="f32")
+    with pytest.raises(dwd.DwdError):
+        dwd.Problem(Xw, yw, storage="f32", solver="direct")
+    with pytest.raises(dwd.DwdError):
+        dwd.serve([dict(X=X, y=y, t_arrival=0.0, params=dict(solver=1))])
