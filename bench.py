@@ -30,6 +30,8 @@ Beside it, on the same data and to the same tolerance, the line carries
             Section 4.1 choice of C on the device, then whole solves with the
             Section 4.5 class weights, pass and representer iterations
             (--no-weighted skips it);
+  direct    the direct (d+1)^2 branch on d=300 n=5e4 and d=54 n=581012
+            (--no-direct skips it);
   cpu_baseline  one whole solve of the FP64 oracle on the host cores.
 Prints one JSON line.
 """
@@ -306,6 +308,52 @@ def weighted_leg(dwd, torch, dev, steps):
     return out
 
 
+def direct_leg(dwd, torch, dev, steps):
+    """The direct (d+1)^2 branch (Section 3.3.1) on two d << n shapes of the
+    paper's UCI/LIBSVM kind (d=300, n=5e4; d=54, n=581012, beyond the SMW
+    factor's n <= 65536): whole solves with set-up, FP32 storage, q=1, C=1,
+    tol 1e-5.  An iteration reads X twice (two fused sweeps); `sweep_gbs`
+    counts the algorithmic bytes of both sweeps (X at d, not the padded
+    leading dimension, plus the n-vectors each sweep reads and writes) per
+    iteration over the whole iteration time, launches and small kernels
+    included."""
+    import numpy as np
+    import synth
+    out = {}
+    for d, n, seed in [(300, 50000, 61), (54, 581012, 62)]:
+        X, y = synth.random_two_class(d, n, seed=seed, mean=0.4, flip=0.1, pos_frac=0.3,
+                                      dtype="f32")
+        Xd = torch.from_numpy(X).to(dev)
+        del X
+        torch.cuda.synchronize()
+
+        def one():
+            P = dwd.Problem(Xd, y, storage="f32", solver="direct")
+            r = P.solve(1.0, 1.0, tol=1e-5, want_state=False)
+            P.close()
+            return r["info"]
+
+        one()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos = [one() for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        i = infos[-1]
+        us_it = i["solve_ms"] * 1e3 / max(1, i["iters"])
+        sweep_bytes = 2 * d * n * 4 + (7 + 8) * n * 8
+        out[f"d{d}_n{n}"] = {
+            "solves_per_s": steps / el, "ms_per_solve": el / steps * 1e3,
+            "setup_ms": float(np.median([x["setup_ms"] for x in infos])),
+            "iters": i["iters"], "us_per_iter": us_it,
+            "converged": all(x["converged"] == 1 for x in infos),
+            "kkt_check_max": max(x["kkt_check"] for x in infos),
+            "sweep_gbs": sweep_bytes / (us_it * 1e-6) / 1e9}
+        del Xd
+        torch.cuda.empty_cache()
+    return out
+
+
 def large_leg(dwd, torch, dev):
     """Mixed precision on one large problem: BF16 storage against FP32."""
     import synth
@@ -345,6 +393,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=64, help="0 to skip the serving leg")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-weighted", action="store_true")
+    ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration) and one solve")
     args = ap.parse_args()
@@ -458,6 +507,9 @@ def main():
     if not args.no_weighted:
         out["weighted"] = weighted_leg(dwd, torch, dev, args.steps)
         print("[bench] weighted done", file=sys.stderr, flush=True)
+    if not args.no_direct:
+        out["direct"] = direct_leg(dwd, torch, dev, args.steps)
+        print("[bench] direct done", file=sys.stderr, flush=True)
     if args.serve_requests > 0:
         del Xd
         torch.cuda.empty_cache()

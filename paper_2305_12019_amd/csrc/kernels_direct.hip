@@ -300,7 +300,8 @@ hipError_t launch_dir_gemv(const Consts& c, const DirPtrs& p, int mode, hipStrea
 //   MODE 0: sum_i x_i                                (set-up: Z~ y = that / Z_scale)
 //   MODE 1: sweep 1 of the iteration (see the file comment)
 //   MODE 2: sweep 2
-// Partials: part_d[b][v*ld + f] (v = 0, 1), part_n[b][0..NPD).
+// Partials: part_d[(v*ld + f) * nblk + b] (v = 0, 1; feature-major, so that
+// the reduction reads each feature's partials contiguously), part_n[b][0..NPD).
 // ---------------------------------------------------------------------------
 // (ordinary cached loads: in the regime of this branch X is often small
 // enough to stay in the last-level cache between the two sweeps)
@@ -459,7 +460,8 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
       }
   }
   // d-vector partials: the groups of the block summed in order
-  double* out = p.part_d + (size_t)blockIdx.x * 2 * ld;
+  double* out = p.part_d + blockIdx.x;
+  const size_t nb = (size_t)p.nblk;
   if constexpr (G == 1) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -468,13 +470,28 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
         const int64_t f = 4 * (int64_t)(lg + j * TPS);
         if (f < ld) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) out[v * ld + f + q] = acc[v][j][q];
+          for (int q = 0; q < 4; ++q) out[(v * ld + f + q) * nb] = acc[v][j][q];
         }
       }
   } else {
+    // the groups of a wave hold the same features at lane offsets that are
+    // multiples of TPS: a butterfly over those offsets, then the four waves
+    // added in order through LDS
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double a = acc[v][j][q];
+#pragma unroll
+          for (int off = TPS; off < 64; off <<= 1) a += __shfl_xor(a, off, 64);
+          acc[v][j][q] = a;
+        }
     __shared__ double buf[NV][TPS * NF * 4];
-    for (int gg = 0; gg < G; ++gg) {
-      if (g == gg) {
+    const int wid = threadIdx.x >> 6, lw = threadIdx.x & 63;
+    for (int ww = 0; ww < 4; ++ww) {
+      if (wid == ww && lw < TPS) {
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -482,13 +499,14 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int o = 4 * (lg + j * TPS) + q;
-              buf[v][o] = gg == 0 ? acc[v][j][q] : buf[v][o] + acc[v][j][q];
+              buf[v][o] = ww == 0 ? acc[v][j][q] : buf[v][o] + acc[v][j][q];
             }
       }
       __syncthreads();
     }
     for (int v = 0; v < NV; ++v)
-      for (int o = threadIdx.x; o < TPS * NF * 4 && o < ld; o += 256) out[v * ld + o] = buf[v][o];
+      for (int o = threadIdx.x; o < TPS * NF * 4 && o < ld; o += 256)
+        out[(v * ld + o) * nb] = buf[v][o];
   }
   // scalar partials: the group leaders summed in order
   if constexpr (MODE != 0) {
@@ -508,19 +526,26 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
   }
 }
 
-// threads per sample and feature quads per thread for a leading dimension
+// Threads per sample and feature quads per thread for a leading dimension:
+// the fewest threads per sample (more samples per wave, so fewer passes of
+// the scalar Step 1b-3 work) with at most four quads each, five at 64
+// threads; above 320 quads the whole block takes one sample.
 static void sweep_shape(int64_t ld, int* tps, int* nf) {
   const int64_t quads = ld / 4;
-  if (quads <= 32) {
-    *tps = 16;
-    *nf = (int)((quads + 15) / 16);
-  } else if (quads <= 256) {
-    *tps = 64;
-    *nf = (int)((quads + 63) / 64);
-  } else {
-    *tps = 256;
-    *nf = (int)((quads + 255) / 256);
+  for (int t = 4; t <= 64; t *= 2) {
+    if (quads <= 4 * t) {
+      *tps = t;
+      *nf = quads <= 2 * t ? 2 : 4;
+      return;
+    }
   }
+  if (quads <= 320) {
+    *tps = 64;
+    *nf = 5;
+    return;
+  }
+  *tps = 256;
+  *nf = (int)((quads + 255) / 256);
 }
 
 int dir_sweep_samples_per_block(int64_t ld, int n) {
@@ -543,8 +568,9 @@ static hipError_t sweep_t(const T* X, const Consts& c, const DirPtrs& p, hipStre
     hipLaunchKernelGGL((k_dir_sweep<T, TP, NFV, MODE>), grid, blk, 0, st, X, c, p);        \
     return hipGetLastError();                                                              \
   }
-  DWD_SWEEP(16, 1) DWD_SWEEP(16, 2)
-  DWD_SWEEP(64, 1) DWD_SWEEP(64, 2) DWD_SWEEP(64, 3) DWD_SWEEP(64, 4)
+  DWD_SWEEP(4, 2) DWD_SWEEP(4, 4) DWD_SWEEP(8, 2) DWD_SWEEP(8, 4)
+  DWD_SWEEP(16, 2) DWD_SWEEP(16, 4) DWD_SWEEP(32, 2) DWD_SWEEP(32, 4)
+  DWD_SWEEP(64, 2) DWD_SWEEP(64, 4) DWD_SWEEP(64, 5)
   DWD_SWEEP(256, 2) DWD_SWEEP(256, 3) DWD_SWEEP(256, 4) DWD_SWEEP(256, 5)
 #undef DWD_SWEEP
   return hipErrorInvalidValue;
@@ -565,32 +591,36 @@ hipError_t launch_dir_sweep(const void* X, int storage, const Consts& c, const D
 }
 
 // ---------------------------------------------------------------------------
-// Sum the sweep partials over blocks (fixed order) into zz[v0 + v] (v < nvec),
-// times `scale`; with nvec = 1 also the block partials of the squared norm
-// (the Step 1c residual).
+// Sum the sweep partials over blocks into zz[v0 + v] (v < nvec), times
+// `scale`: one wave per feature, lanes striding over the blocks, then a
+// butterfly (a fixed order).  With nvec = 1 also the block partials of the
+// squared norm (the Step 1c residual).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_dir_reduce(Consts c, DirPtrs p, int v0, int nvec,
                                                     double scale) {
   const int done = p.sc->done;
   const int64_t ld = c.ld;
   const int d = (int)c.d;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int v = (int)(t / d), f = (int)(t % d);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int t = blockIdx.x * 4 + wid;
+  const int v = t / d, f = t % d;
   if (done) return;
   double s = 0.0;
   if (v < nvec) {
-    const double* src = p.part_d + (size_t)v * ld + f;
-    for (int b = 0; b < p.nblk; ++b) s += src[(size_t)b * 2 * ld];
-    s *= scale;
-    p.zz[(size_t)(v0 + v) * ld + f] = s;
+    const double* src = p.part_d + ((size_t)v * ld + f) * p.nblk;
+    for (int b = lane; b < p.nblk; b += 64) s += src[b];
+    s = wave_sum(s) * scale;
+    if (lane == 0) p.zz[(size_t)(v0 + v) * ld + f] = s;
   }
   if (nvec == 1) {
-    const double sq = block_sum<256>(v < nvec ? s * s : 0.0);
-    if (threadIdx.x == 0) p.part_r[blockIdx.x] = sq;
+    __shared__ double sq[4];
+    if (lane == 0) sq[wid] = v < nvec ? s * s : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) p.part_r[blockIdx.x] = (sq[0] + sq[1]) + (sq[2] + sq[3]);
   }
 }
 
-int dir_reduce_blocks(int d, int nvec) { return (nvec * d + 255) / 256; }
+int dir_reduce_blocks(int d, int nvec) { return (nvec * d + 3) / 4; }
 
 hipError_t launch_dir_reduce(const Consts& c, const DirPtrs& p, int v0, int nvec, double scale,
                              hipStream_t st) {
