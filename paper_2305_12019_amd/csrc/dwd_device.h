@@ -199,6 +199,16 @@ __device__ __forceinline__ void wave_row_dot2(const double* __restrict__ a,
 }
 
 
+// a^(q/(q+1)) for a > 0: sqrt for q = 1, cube roots for q = 2 and 0.5
+__device__ __forceinline__ double pow_qexp(double a, const Consts& c) {
+  switch (c.qkind) {
+    case 1: return sqrt(a);
+    case 2: return cbrt(a * a);
+    case 5: return cbrt(a);
+    default: return pow(a, c.qexp);
+  }
+}
+
 // Per-row terms of the Section 4.3 residuals and objectives, with the loss
 // weight v_i of the row's class and the penalty weight e_i: alpha - q v / r^(q+1)
 // (eta_C3), max(0, alpha - C e) (eta_D2), xi (C e - alpha) (eta_C2),
@@ -218,7 +228,7 @@ __device__ __forceinline__ void nspace_sums(const Consts& c, double rq, double r
   acc[5] = comp * comp;
   acc[6] = v / rq;
   acc[7] = ei * xi;
-  acc[8] = a1 > 0.0 ? vd * pow(a1, c.qexp) : 0.0;
+  acc[8] = a1 > 0.0 ? vd * pow_qexp(a1, c) : 0.0;
 }
 
 

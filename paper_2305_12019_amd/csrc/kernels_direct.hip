@@ -304,12 +304,13 @@ hipError_t launch_dir_gemv(const Consts& c, const DirPtrs& p, int mode, hipStrea
 // the reduction reads each feature's partials contiguously), part_n[b][0..NPD).
 // ---------------------------------------------------------------------------
 // (ordinary cached loads: in the regime of this branch X is often small
-// enough to stay in the last-level cache between the two sweeps)
+// enough to stay in the last-level cache between the two sweeps; values are
+// kept in their storage type and widened at use)
 template <typename T>
 struct Quad;
 template <>
 struct Quad<float> {
-  __device__ static void load(const float* p, double (&o)[4]) {
+  __device__ static void load(const float* p, float (&o)[4]) {
     const nt_f4 v = *reinterpret_cast<const nt_f4*>(p);
     o[0] = v[0];
     o[1] = v[1];
@@ -385,7 +386,7 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
   for (int ib = i0; ib < i1; ib += G) {
     const int i = ib + g;
     const bool live = i < i1;
-    double xv[NF][4];
+    T xv[NF][4];
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
       const int64_t f = 4 * (int64_t)(lg + j * TPS);
@@ -393,7 +394,7 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
         Quad<T>::load(X + (int64_t)i * ld + f, xv[j]);
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) xv[j][q] = 0.0;
+        for (int q = 0; q < 4; ++q) xv[j][q] = (T)0;
       }
     }
     double cf0 = 1.0, cf1 = 0.0;
@@ -403,12 +404,18 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
 #pragma unroll
         for (int j = 0; j < NF; ++j)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) dot = fma(xv[j][q], wv[j][q], dot);
+          for (int q = 0; q < 4; ++q) dot = fma((double)xv[j][q], wv[j][q], dot);
         dot = group_sum<TPS>(dot, lds_red);
       }
+      double yi = 0.0, al = 0.0;
       if (live) {
-        const double yi = p.y[i];
-        const double al = p.alpha[i];
+        yi = p.y[i];
+        al = p.alpha[i];
+      }
+      // A group that spans several waves (TPS = 256): every wave has read
+      // alpha_i before the group leader overwrites it in sweep 2.
+      if constexpr (MODE == 2 && TPS > 64) __syncthreads();
+      if (live) {
         if constexpr (MODE == 1) {
           const double z = yi * dot * c.inv_zs;
           const double r0 = p.r[i];
@@ -455,8 +462,8 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
     for (int j = 0; j < NF; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        acc[0][j][q] = fma(cf0, xv[j][q], acc[0][j][q]);
-        if constexpr (NV == 2) acc[1][j][q] = fma(cf1, xv[j][q], acc[1][j][q]);
+        acc[0][j][q] = fma(cf0, (double)xv[j][q], acc[0][j][q]);
+        if constexpr (NV == 2) acc[1][j][q] = fma(cf1, (double)xv[j][q], acc[1][j][q]);
       }
   }
   // d-vector partials: the groups of the block summed in order

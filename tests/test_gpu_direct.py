@@ -194,3 +194,18 @@ def test_direct_rejections_and_cap(dwd):
         dwd.Problem(Xw, yw, storage="f32", solver="direct")
     with pytest.raises(dwd.DwdError):
         dwd.serve([dict(X=X, y=y, t_arrival=0.0, params=dict(solver=1))])
+
+
+@pytest.mark.parametrize("d,n", [(54, 3000), (300, 2000), (4000, 6000), (5000, 3000)])
+def test_direct_repeats_are_bit_identical(dwd, d, n):
+    # The sweeps reduce in a fixed order, and a sample group that spans
+    # several waves reads alpha_i on every wave before its leader overwrites
+    # it: two runs give the same bits.
+    X, y = synth.random_two_class(d, n, seed=5 * d + n, mean=0.5, pos_frac=0.3, dtype="f32")
+    P = dwd.Problem(X, y, storage="f32", solver="direct")
+    for k in (3, 40):
+        a = P.solve(1.5, 1.0, tol=1e-300, max_iter=k)
+        b = P.solve(1.5, 1.0, tol=1e-300, max_iter=k)
+        for key in ("w", "alpha", "r", "xi", "u", "rho"):
+            assert np.array_equal(a[key], b[key]), (k, key)
+    P.close()
