@@ -374,6 +374,140 @@ class DirectFactor:
         return x[:-1], float(x[-1])
 
 
+def psqmr(apply_A, b, x0, apply_Minv, tol, max_steps):
+    """Preconditioned symmetric QMR (Freund and Nachtigal) for a symmetric
+    A and a symmetric positive definite preconditioner M: the Lanczos
+    recurrences of the preconditioned CG direction q_j, with the iterate
+    formed by the quasi-minimal-residual smoothing (theta_j, c_j, tau_j) of
+    the unpreconditioned residual norms.  Stops when the true residual
+    ||b - A x|| is at most ``tol``.  Returns (x, steps, converged)."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    r = b - apply_A(x)
+    if np.linalg.norm(r) <= tol:
+        return x, 0, True
+    tau = np.linalg.norm(r)
+    q = apply_Minv(r)
+    rho = float(r @ q)
+    theta = 0.0
+    dvec = np.zeros_like(x)
+    for j in range(1, max_steps + 1):
+        t = apply_A(q)
+        sig = float(q @ t)
+        if sig == 0.0 or rho == 0.0:
+            break
+        alpha = rho / sig
+        r = r - alpha * t
+        theta_prev = theta
+        theta = np.linalg.norm(r) / tau
+        c2 = 1.0 / (1.0 + theta * theta)
+        tau = tau * theta * math.sqrt(c2)
+        dvec = c2 * theta_prev * theta_prev * dvec + c2 * alpha * q
+        x = x + dvec
+        if np.linalg.norm(b - apply_A(x)) <= tol:
+            return x, j, True
+        u = apply_Minv(r)
+        rho_new = float(r @ u)
+        q = u + (rho_new / rho) * q
+        rho = rho_new
+    return x, max_steps, np.linalg.norm(b - apply_A(x)) <= tol
+
+
+def top_eigenpairs(apply_S, dim, ell, steps=None, seed=0):
+    """The ``ell`` largest eigenpairs of a symmetric positive semidefinite
+    operator by the Lanczos method with full reorthogonalisation (Section
+    3.3.3 asks for them for eq-T): ``steps`` Lanczos vectors (default
+    min(dim, 3 ell + 20)), Ritz pairs from the tridiagonal matrix."""
+    m = min(dim, steps if steps else 3 * ell + 20)
+    rng = np.random.default_rng(seed)
+    V = np.zeros((dim, m))
+    a = np.zeros(m)
+    b = np.zeros(m)
+    v = rng.standard_normal(dim)
+    v /= np.linalg.norm(v)
+    k = m
+    for j in range(m):
+        V[:, j] = v
+        w = apply_S(v)
+        a[j] = v @ w
+        w = w - V[:, :j + 1] @ (V[:, :j + 1].T @ w)
+        w = w - V[:, :j + 1] @ (V[:, :j + 1].T @ w)
+        if j + 1 < m:
+            b[j] = np.linalg.norm(w)
+            if b[j] <= 1e-14 * max(1.0, abs(a[j])):
+                k = j + 1
+                break
+            v = w / b[j]
+    Tm = np.diag(a[:k]) + np.diag(b[:k - 1], 1) + np.diag(b[:k - 1], -1)
+    lam, S = np.linalg.eigh(Tm)
+    order = np.argsort(lam)[::-1][:ell]
+    return lam[order], V[:, :k] @ S[:, order]
+
+
+class IterativeFactor:
+    """Section 3.3.3 (n and d both large).  Step 1a and 1c first solve
+    eq-linsys with T = 0 by PSQMR to the accuracy eq-linsys-tol (warm
+    started at the current [w; beta]); once a solve needs more than
+    ``psqmr_max`` steps, the proximal term T of eq-T is added for the rest
+    of the solve, built from the ``ell`` largest eigenpairs of Z~ Z~^T:
+        T = lam_ell I + sum_{i<ell} (lam_i - lam_ell) v_i v_i^T - Z~ Z~^T,
+    so that Z~ Z~^T + mu I + T has the closed-form inverse
+        (mu + lam_ell)^-1 I + sum_{i<ell} ((mu + lam_i)^-1 - (mu + lam_ell)^-1) v_i v_i^T
+    and the system is solved through the Schur complement on beta (eq-schur).
+    The PSQMR preconditioner is that T-modified matrix (its inverse is the
+    closed form above with the Schur complement)."""
+
+    def __init__(self, Zt, y, mu=1.0, ell=10, psqmr_max=50):
+        self.Zt = Zt
+        self.y = np.asarray(y, dtype=np.float64)
+        self.mu = float(mu)
+        d = Zt.shape[0]
+        self.ell = min(ell, d)
+        self.psqmr_max = psqmr_max
+        lam, V = top_eigenpairs(lambda v: Zt @ (Zt.T @ v), d, self.ell)
+        self.lam, self.V = lam, V
+        self.Zy = Zt @ self.y
+        self.yy = float(self.y @ self.y)
+        self.g = self.Mw_inv(self.Zy)
+        self.schur = self.yy - float(self.Zy @ self.g)
+        self.use_T = psqmr_max <= 0
+        self.steps = []
+
+    def Mw_inv(self, x):
+        """(Z~ Z~^T + mu I + T)^-1 x in closed form."""
+        lam_l = self.lam[-1]
+        out = x / (self.mu + lam_l)
+        Vh = self.V[:, :-1]
+        coef = 1.0 / (self.mu + self.lam[:-1]) - 1.0 / (self.mu + lam_l)
+        return out + Vh @ (coef * (Vh.T @ x))
+
+    def T_apply(self, w):
+        lam_l = self.lam[-1]
+        Vh = self.V[:, :-1]
+        return (lam_l * w + Vh @ ((self.lam[:-1] - lam_l) * (Vh.T @ w))
+                - self.Zt @ (self.Zt.T @ w))
+
+    def solve_T(self, hw, hb):
+        """[w; beta] of the T-modified system by eq-schur."""
+        beta = (hb - float(self.g @ hw)) / self.schur
+        return self.Mw_inv(hw) - beta * self.g, float(beta)
+
+    def _A(self, x):
+        top, bot = linsys_matrix_apply(self.Zt, self.y, self.mu, x[:-1], x[-1])
+        return np.concatenate([top, [bot]])
+
+    def _Minv(self, x):
+        w, b = self.solve_T(x[:-1], x[-1])
+        return np.concatenate([w, [b]])
+
+    def solve_psqmr(self, hw, hb, w0, b0, tol):
+        """T = 0: PSQMR from [w0; b0]; returns (w, beta, converged within
+        psqmr_max steps)."""
+        x, steps, ok = psqmr(self._A, np.concatenate([hw, [hb]]), np.concatenate([w0, [b0]]),
+                             self._Minv, tol, self.psqmr_max)
+        self.steps.append(steps)
+        return x[:-1], float(x[-1]), ok
+
+
 def select_solver(d, n):
     """The solver choice printed with the paper's pseudo-code: the SMW form
     when d > 5000, n < 0.2 d and n <= 2500; the iterative solver (PSQMR,
@@ -501,7 +635,8 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
           sigma0: Optional[float] = None, eps_c: Optional[float] = None,
           record: bool = False, start: Optional[Dict] = None,
           scale: bool = True, rho_residual: bool = True, sigma_every: int = 2,
-          weights=False, e=None, solver: str = "smw") -> Dict:
+          weights=False, e=None, solver: str = "smw", ell: int = 10,
+          psqmr_max: int = 50) -> Dict:
     """Run Algorithm 1 on eq-gen-scale and return the unscaled solution.
 
     ``X`` has shape (n, d) (row i = sample x_i), ``y`` is +-1.  Returns a dict
@@ -518,8 +653,11 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
     Section 4.5 (:func:`class_weights`) on the loss terms, or an array of n
     positive loss weights; ``e``: the positive penalty vector of eq-primal
     (n values; default 1).  ``solver``: "smw" (Section 3.3.2) or "direct"
-    (Section 3.3.1) for the eq-linsys solves; both give the same iterates in
-    exact arithmetic.
+    (Section 3.3.1) for the eq-linsys solves (both give the same iterates in
+    exact arithmetic), or "iterative" (Section 3.3.3: PSQMR to the accuracy
+    eq-linsys-tol, and the proximal T of eq-T from the ``ell`` largest
+    eigenpairs once a solve needs more than ``psqmr_max`` steps; 0 = T from
+    the start).
     """
     y = np.asarray(y, dtype=np.float64)
     if scale:
@@ -531,8 +669,11 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
         F = SMWFactor(Zt, y, mu)
     elif solver == "direct":
         F = DirectFactor(Zt, y, mu)
+    elif solver == "iterative":
+        F = IterativeFactor(Zt, y, mu, ell=ell, psqmr_max=psqmr_max)
     else:
         raise ValueError(f"unknown solver {solver}")
+    it_mode = solver == "iterative"
     R = zscale
     wt = loss_weights(y, q, weights)
     ev = np.ones(n) if e is None else np.asarray(e, np.float64)
@@ -564,7 +705,17 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
         eps_k = c_eps / (k + 1.0) ** 1.5
         # Step 1a
         hw, hb = linsys_rhs(Zt, y, mu, sigma, r, xi, u, alpha, rho)
-        wbar, bbar = F.solve(hw, hb)
+        Tw = None
+        if not it_mode:
+            wbar, bbar = F.solve(hw, hb)
+        else:
+            if not F.use_T:
+                wbar, bbar, ok = F.solve_psqmr(hw, hb, w, beta, eps_k)
+                if not ok:
+                    F.use_T = True
+            if F.use_T:
+                Tw = F.T_apply(w)          # the proximal term adds T w^k
+                wbar, bbar = F.solve_T(hw + Tw, hb)
         # Step 1b
         c = Zt.T @ wbar + y * bbar + xi - alpha / sigma
         r_new, steps = prox_weighted(c, sigma, q, wt, r, eps_k / math.sqrt(n))
@@ -572,9 +723,23 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
         # Step 1c
         hw1, hb1 = linsys_rhs(Zt, y, mu, sigma, r_new, xi, u, alpha, rho)
         Aw, Ab = linsys_matrix_apply(Zt, y, mu, wbar, bbar)
+        if Tw is not None:
+            # with T: A_T [w; beta] = A [w; beta] + [T w; 0], rhs + [T w^k; 0]
+            Aw = Aw + F.T_apply(wbar) - Tw
         res = math.sqrt(float(np.sum((hw1 - Aw) ** 2)) + (hb1 - Ab) ** 2)
         if res > 5.0 * eps_k:
-            w, beta = F.solve(hw1, hb1)
+            if not it_mode:
+                w, beta = F.solve(hw1, hb1)
+            elif Tw is not None:
+                w, beta = F.solve_T(hw1 + Tw, hb1)
+            else:
+                w1, b1, ok = F.solve_psqmr(hw1, hb1, wbar, bbar, 5.0 * eps_k)
+                if ok:
+                    w, beta = w1, b1
+                else:
+                    F.use_T = True
+                    Tw = F.T_apply(w)
+                    w, beta = F.solve_T(hw1 + Tw, hb1)
             n_double += 1
         else:
             w, beta = wbar, bbar
@@ -600,6 +765,8 @@ def solve(X, y, C, q, tol=1e-5, max_iter=2000, mu=1.0, tau=TAU_DEFAULT,
     return dict(w=w / zscale, u=u / zscale, beta=float(beta), r=r, xi=xi, alpha=alpha,
                 w_scaled=w, u_scaled=u, rho=rho, sigma=sigma, zscale=zscale,
                 iters=it, n_double=n_double, newton_max=newton_max, eta=e,
+                psqmr_steps=list(F.steps) if it_mode else None,
+                used_T=bool(F.use_T) if it_mode else None,
                 converged=converged, history=hist)
 
 
