@@ -55,8 +55,9 @@ typedef enum { DWD_DENSE = 0, DWD_CSR = 1 } dwd_layout;
  *                     n x n factor; n <= 65536; every mode and input format.
  *   DWD_SOLVER_DIRECT the whole (d+1) x (d+1) matrix of eq-linsys, formed
  *                     and inverted once (Section 3.3.1); d <= 5120, dense X,
- *                     FP32 or FP64 storage, n limited only by memory; single
- *                     solves (not dwd_solve_batch, dwd_serve, representer).
+ *                     FP32 or FP64 storage, n limited only by memory;
+ *                     dwd_solve and dwd_serve (not dwd_solve_batch or the
+ *                     representer iteration).
  *   DWD_SOLVER_AUTO   the paper's choice: direct when d <= 5000, else the SMW
  *                     form (the paper's iterative solver for d > 5000 with
  *                     n >= 0.2 d or n > 2500 is not built; the SMW form takes

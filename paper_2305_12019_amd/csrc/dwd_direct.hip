@@ -125,6 +125,19 @@ dwd_status setup_direct(Problem* P, hipStream_t st) {
   return DWD_OK;
 }
 
+hipError_t queue_direct_iteration(Problem* P, const Consts& c, hipStream_t st) {
+  const DirPtrs& dp = P->dp;
+  const double inv_zs = 1.0 / P->zscale;
+  hipError_t e;
+  if ((e = launch_dir_gemv(c, dp, 0, st)) != hipSuccess) return e;
+  if ((e = launch_dir_sweep(P->X_rec, P->st_rec, c, dp, 1, st)) != hipSuccess) return e;
+  if ((e = launch_dir_reduce(c, dp, 0, 1, inv_zs, st)) != hipSuccess) return e;
+  if ((e = launch_dir_gemv(c, dp, 1, st)) != hipSuccess) return e;
+  if ((e = launch_dir_sweep(P->X_rec, P->st_rec, c, dp, 2, st)) != hipSuccess) return e;
+  if ((e = launch_dir_reduce(c, dp, 1, 2, inv_zs, st)) != hipSuccess) return e;
+  return launch_dir_tail(c, dp, st);
+}
+
 dwd_status solve_direct(Problem* P, const dwd_params* p, double* w, dwd_info* info,
                         double* alpha, double* r, double* xi, double* u, double* rho) {
   dwd_status s;
@@ -138,18 +151,8 @@ dwd_status solve_direct(Problem* P, const dwd_params* p, double* w, dwd_info* in
   HIP_TRY_D(hipEventRecord(P->ev_a, st));
   const Consts c = make_consts(P, p);
   const DirPtrs& dp = P->dp;
-  const double inv_zs = 1.0 / P->zscale;
   HIP_TRY_D(launch_dir_init(c, dp, default_sigma0(p, P->n), st));
-  auto queue_iteration = [&]() -> hipError_t {
-    hipError_t e;
-    if ((e = launch_dir_gemv(c, dp, 0, st)) != hipSuccess) return e;
-    if ((e = launch_dir_sweep(P->X_rec, P->st_rec, c, dp, 1, st)) != hipSuccess) return e;
-    if ((e = launch_dir_reduce(c, dp, 0, 1, inv_zs, st)) != hipSuccess) return e;
-    if ((e = launch_dir_gemv(c, dp, 1, st)) != hipSuccess) return e;
-    if ((e = launch_dir_sweep(P->X_rec, P->st_rec, c, dp, 2, st)) != hipSuccess) return e;
-    if ((e = launch_dir_reduce(c, dp, 1, 2, inv_zs, st)) != hipSuccess) return e;
-    return launch_dir_tail(c, dp, st);
-  };
+  auto queue_iteration = [&]() -> hipError_t { return queue_direct_iteration(P, c, st); };
   // Chunks of check_every iterations; the stop flag of a chunk is read on
   // the host while the next chunk runs.
   const int chunk = std::max(1, p->check_every > 0 ? p->check_every : 8);
@@ -175,11 +178,11 @@ dwd_status solve_direct(Problem* P, const dwd_params* p, double* w, dwd_info* in
   const int64_t d = P->d;
   if (w) {
     HIP_TRY_D(hipMemcpy(w, dp.w, d * 8, hipMemcpyDeviceToHost));
-    for (int64_t k = 0; k < d; ++k) w[k] *= inv_zs;
+    for (int64_t k = 0; k < d; ++k) w[k] /= P->zscale;  // (as every other path unscales)
   }
   if (u) {
     HIP_TRY_D(hipMemcpy(u, dp.u, d * 8, hipMemcpyDeviceToHost));
-    for (int64_t k = 0; k < d; ++k) u[k] *= inv_zs;
+    for (int64_t k = 0; k < d; ++k) u[k] /= P->zscale;
   }
   if (rho) HIP_TRY_D(hipMemcpy(rho, dp.rho, d * 8, hipMemcpyDeviceToHost));
   if (alpha) HIP_TRY_D(hipMemcpy(alpha, dp.alpha, (size_t)P->n * 8, hipMemcpyDeviceToHost));

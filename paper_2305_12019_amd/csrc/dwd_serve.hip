@@ -75,6 +75,18 @@ void destroy_slot(Slot& s) {
 // Queue up to `chunk` iterations of the current phase and the flag copy.
 hipError_t queue_chunk(Slot& s, int chunk) {
   Problem* P = s.P;
+  if (P->solver == DWD_SOLVER_DIRECT) {
+    // direct branch: one phase; its residuals come from explicit passes
+    hipError_t e;
+    for (int j = 0; j < chunk && s.k_base + s.queued < s.prm.max_iter; ++j, ++s.queued)
+      if ((e = queue_direct_iteration(P, s.c, s.stream)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(s.hs, P->dp.sc, sizeof(Scal), hipMemcpyDeviceToHost, s.stream)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipEventRecord(s.ev, s.stream)) != hipSuccess) return e;
+    s.in_flight = true;
+    return hipSuccess;
+  }
   const bool lowp = (s.phase == MAIN && P->storage == DWD_BF16 && !s.c.representer);
   const Consts& c = lowp ? s.c_lowp : s.c;
   const void* X = lowp ? P->X_lowp : P->X_rec;
@@ -121,6 +133,10 @@ hipError_t advance(Slot& s, int chunk) {
   switch (s.phase) {
     case MAIN:
       if (s.queued > 0 && (hs.done || s.k_base + s.queued >= s.prm.max_iter)) {
+        if (s.P->solver == DWD_SOLVER_DIRECT) {
+          s.phase = DONE;
+          return hipSuccess;
+        }
         const bool bf16 = s.P->storage == DWD_BF16 && !s.c.representer;
         if (bf16) s.iters_lowp = hs.k;
         if (bf16 && s.prm.refine && hs.k < s.prm.max_iter) {
@@ -192,8 +208,9 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
   for (int i = 0; i < nreq; ++i) {
     dwd_status s = validate_params(&reqs[i].params, true);
     if (s == DWD_OK) s = validate_penalty(&reqs[i].params, reqs[i].X.n);
-    if (s == DWD_OK && reqs[i].params.solver == DWD_SOLVER_DIRECT)
-      s = fail(DWD_E_INVALID, "dwd_serve runs the SMW form (solver must be SMW or AUTO)");
+    if (s == DWD_OK && reqs[i].params.representer &&
+        resolve_solver(&reqs[i].params, &reqs[i].X) == DWD_SOLVER_DIRECT)
+      s = fail(DWD_E_INVALID, "the representer iteration needs the SMW set-up");
     if (s != DWD_OK) return s;
     memset(&out[i].info, 0, sizeof(dwd_info));
     out[i].status = DWD_E_BUSY;
@@ -221,7 +238,8 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
       r.info.solve_ms = (now_s(t0) - s.t_admit) * 1e3 - s.P->setup_ms;
       if (r.w) {
         std::vector<double> hw(s.P->d);
-        if (hipMemcpy(hw.data(), s.P->ip.w, s.P->d * 8, hipMemcpyDeviceToHost) == hipSuccess)
+        const double* wsrc = s.P->solver == DWD_SOLVER_DIRECT ? s.P->dp.w : s.P->ip.w;
+        if (hipMemcpy(hw.data(), wsrc, s.P->d * 8, hipMemcpyDeviceToHost) == hipSuccess)
           for (int64_t k = 0; k < s.P->d; ++k) r.w[k] = hw[k] / s.P->zscale;
         else
           status = DWD_E_DEVICE;
@@ -245,8 +263,10 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
       if (active >= max_slots) break;
       const int r = waiting.front();
       const dwd_request& q = reqs[r];
-      const int64_t fp = problem_footprint(q.X.d, (int)q.X.n, q.params.storage, q.X.layout,
-                                           q.X.nnz);
+      const bool direct = resolve_solver(&q.params, &q.X) == DWD_SOLVER_DIRECT;
+      const int64_t fp = direct ? direct_footprint(q.X.d, (int)q.X.n, q.params.storage)
+                                : problem_footprint(q.X.d, (int)q.X.n, q.params.storage,
+                                                    q.X.layout, q.X.nnz);
       if ((double)fp > budget) {  // can never fit
         out[r].status = DWD_E_BUSY;
         out[r].t_done = now_s(t0);
@@ -268,9 +288,7 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
           hipHostMalloc((void**)&s.hs, sizeof(Scal), 0) != hipSuccess) {
         st = DWD_E_DEVICE;
       } else {
-        dwd_params ps = q.params;
-        ps.solver = DWD_SOLVER_SMW;  // the serving loop steps SMW problems
-        st = setup_problem(&q.X, q.y, &ps, s.stream, &s.P);
+        st = setup_problem(&q.X, q.y, &q.params, s.stream, &s.P);
       }
       if (st != DWD_OK) {
         out[r].status = st;
@@ -284,8 +302,11 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
       s.c = make_consts(s.P, &s.prm);
       s.c_lowp = s.P->storage == DWD_BF16 ? lowp_consts(s.P, &s.prm) : s.c;
       memset(s.hs, 0, sizeof(Scal));
+      const double sigma0 = default_sigma0(&s.prm, s.P->n);
       if (s.P->set_penalty(s.prm.e) != hipSuccess ||
-          launch_init(s.c, s.P->ip, default_sigma0(&s.prm, s.P->n), s.stream) != hipSuccess ||
+          (s.P->solver == DWD_SOLVER_DIRECT
+               ? launch_dir_init(s.c, s.P->dp, sigma0, s.stream)
+               : launch_init(s.c, s.P->ip, sigma0, s.stream)) != hipSuccess ||
           queue_chunk(s, chunk) != hipSuccess) {
         out[r].status = DWD_E_DEVICE;
         fatal = DWD_E_DEVICE;

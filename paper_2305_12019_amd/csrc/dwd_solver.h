@@ -160,6 +160,8 @@ dwd_status setup_direct(Problem* P, hipStream_t st);
 dwd_status solve_direct(Problem* P, const dwd_params* p, double* w, dwd_info* info,
                         double* alpha, double* r, double* xi, double* u, double* rho);
 int64_t direct_footprint(int64_t d, int n, int storage);
+// One iteration of the direct branch queued on st (seven launches).
+hipError_t queue_direct_iteration(Problem* P, const Consts& c, hipStream_t st);
 // The factor a set-up request resolves to (DWD_SOLVER_SMW or DWD_SOLVER_DIRECT).
 int resolve_solver(const dwd_params* p, const dwd_matrix* X);
 dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* info,

@@ -193,7 +193,7 @@ def test_direct_rejections_and_cap(dwd):
     with pytest.raises(dwd.DwdError):
         dwd.Problem(Xw, yw, storage="f32", solver="direct")
     with pytest.raises(dwd.DwdError):
-        dwd.serve([dict(X=X, y=y, t_arrival=0.0, params=dict(solver=1))])
+        dwd.serve([dict(X=X, y=y, t_arrival=0.0, params=dict(solver=1, representer=1))])
 
 
 @pytest.mark.parametrize("d,n", [(54, 3000), (300, 2000), (4000, 6000), (5000, 3000)])

@@ -150,3 +150,37 @@ def test_serve_admission_by_memory_budget(dwd):
     big = dict(reqs[0])
     res = dwd.serve([big], hbm_budget_bytes=0.5 * fps[0])
     assert res[0]["status"] == -5  # DWD_E_BUSY: can never fit
+
+
+def test_serve_steps_direct_problems_beside_smw_problems(dwd):
+    # solver = AUTO: the paper's choice picks the direct (d+1)^2 factor for
+    # d <= 5000 (dense FP32) and the SMW form otherwise; each result equals the
+    # single solve with the same choice, alone and in the mix.
+    specs = [(300, 2000, 1.0, 1.0), (54, 5000, 2.0, 0.5), (8000, 150, 1.0, 1.0),
+             (2000, 900, 1.0, 3.0)]
+    reqs = []
+    for j, (d, n, q, C) in enumerate(specs):
+        X, y = synth.random_two_class(d, n, seed=700 + j, mean=0.5, dtype="f32")
+        reqs.append(dict(X=X, y=y, t_arrival=0.001 * j,
+                         params=dict(C=C, q=q, tol=1e-5, storage="f32", solver=2,
+                                     class_weights=j % 2)))
+    mix = dwd.serve(reqs, iters_per_round=8)
+    for j, (r, m) in enumerate(zip(reqs, mix)):
+        p = r["params"]
+        P = dwd.Problem(r["X"], r["y"], storage="f32", solver="auto")
+        want_direct = specs[j][0] <= 5000
+        assert P.inspect("solver")[0] == (1 if want_direct else 0)
+        single = P.solve(p["C"], p["q"], tol=p["tol"], class_weights=p["class_weights"],
+                         want_state=False)
+        P.close()
+        assert m["status"] == 0 and m["info"]["converged"] == 1, (j, m)
+        assert m["info"]["iters"] == single["info"]["iters"], j
+        assert np.array_equal(m["w"], single["w"]), j
+        assert m["info"]["kkt_check"] <= 1.5e-5, (j, m["info"])
+        # and against the oracle's branch of the same kind at the same tolerance
+        Xd = r["X"].astype(np.float64)
+        o = O.solve(Xd, r["y"], p["C"], p["q"], tol=p["tol"], max_iter=2000,
+                    solver="direct" if want_direct else "smw",
+                    weights=bool(p["class_weights"]))
+        assert abs(m["info"]["iters"] - o["iters"]) <= max(3, 0.1 * o["iters"]), j
+        assert np.linalg.norm(m["w"] - o["w"]) <= 1e-4 * np.linalg.norm(o["w"]), j
