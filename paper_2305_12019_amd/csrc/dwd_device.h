@@ -76,6 +76,11 @@ struct Vec<uint16_t> {
 // Step 1b: prox of theta_q by the Newton map of Section 3.2 (eq-varphi),
 // warm-started at r^k, with the bracket safeguard.
 // ---------------------------------------------------------------------------
+// General-q powers and the rarely taken bracket restart out of line: the
+// integer and q = 0.5 cases do not need them, and inlined they cost the fused
+// kernels many registers.
+__device__ __noinline__ double pow_general(double a, double b) { return pow(a, b); }
+
 __device__ __forceinline__ double pow_qp1(double s, const Consts& c) {  // s^(q+1)
   switch (c.qkind) {
     case 1: return s * s;
@@ -85,7 +90,7 @@ __device__ __forceinline__ double pow_qp1(double s, const Consts& c) {  // s^(q+
       return s2 * s2 * s;
     }
     case 5: return s * sqrt(s);
-    default: return pow(s, c.q + 1.0);
+    default: return pow_general(s, c.q + 1.0);
   }
 }
 
@@ -98,11 +103,11 @@ __device__ __forceinline__ double pow_q(double s, const Consts& c) {  // s^q
       return s2 * s2;
     }
     case 5: return sqrt(s);
-    default: return pow(s, c.q);
+    default: return pow_general(s, c.q);
   }
 }
 
-__device__ __forceinline__ double prox_lower(double a, double sigma, const Consts& c) {
+__device__ __noinline__ double prox_lower(double a, double sigma, const Consts& c) {
   const double s0 = pow(c.q / sigma, 1.0 / (c.q + 2.0));
   if (a >= 0.0) return fmax(a, s0);
   return pow(c.q / (sigma * (s0 - a)), 1.0 / (c.q + 1.0));
@@ -205,7 +210,7 @@ __device__ __forceinline__ double pow_qexp(double a, const Consts& c) {
     case 1: return sqrt(a);
     case 2: return cbrt(a * a);
     case 5: return cbrt(a);
-    default: return pow(a, c.qexp);
+    default: return pow_general(a, c.qexp);
   }
 }
 
