@@ -58,12 +58,26 @@ typedef enum { DWD_DENSE = 0, DWD_CSR = 1 } dwd_layout;
  *                     FP32 or FP64 storage, n limited only by memory;
  *                     dwd_solve and dwd_serve (not dwd_solve_batch or the
  *                     representer iteration).
+ *   DWD_SOLVER_ITERATIVE  n and d both large (Section 3.3.3): eq-linsys with
+ *                     the proximal term T of eq-T, built from the ell largest
+ *                     eigenpairs of Z~ Z~^T (Lanczos at set-up), solved in
+ *                     closed form through eq-schur; four passes over X per
+ *                     iteration, any n and d.  The paper first tries PSQMR
+ *                     with T = 0 and switches to this term after a solve of
+ *                     more than 50 steps; this library starts with the term
+ *                     (PSQMR is not built on the GPU).  Dense X, FP32 or
+ *                     FP64 storage, dwd_solve only.
  *   DWD_SOLVER_AUTO   the paper's choice: direct when d <= 5000, else the SMW
- *                     form (the paper's iterative solver for d > 5000 with
- *                     n >= 0.2 d or n > 2500 is not built; the SMW form takes
- *                     those cases while n <= 65536).  CSR input or BF16
- *                     storage resolve to SMW.                                */
-typedef enum { DWD_SOLVER_SMW = 0, DWD_SOLVER_DIRECT = 1, DWD_SOLVER_AUTO = 2 } dwd_solver;
+ *                     form while n <= 65536 (the paper's iterative case for
+ *                     d > 5000 with n >= 0.2 d or n > 2500 included), else
+ *                     the iterative branch.  CSR input or BF16 storage
+ *                     resolve to SMW.                                         */
+typedef enum {
+  DWD_SOLVER_SMW = 0,
+  DWD_SOLVER_DIRECT = 1,
+  DWD_SOLVER_AUTO = 2,
+  DWD_SOLVER_ITERATIVE = 3
+} dwd_solver;
 
 /* The data matrix X (d x n), Section 2 "X Matrix".
  * DWD_DENSE: values is d x n column-major with leading dimension d, i.e.
@@ -147,6 +161,8 @@ typedef struct {
                         v_i^(1/(q+1)) alpha_i^(q/(q+1))) carry the weight.
                         0 (default) = all weights 1.                         */
   int32_t solver;    /* dwd_solver, used by dwd_setup; default DWD_SOLVER_SMW  */
+  int32_t ell;       /* DWD_SOLVER_ITERATIVE: eigenpairs in eq-T, 2..32; 0 = 10
+                        (used by dwd_setup)                                    */
   const double* e;   /* host array of n positive finite penalty weights e_i of
                         eq-primal (the paper normalises ||e||_inf = 1), read
                         during the call; NULL (default) = e = 1.  C e replaces

@@ -412,18 +412,26 @@ def psqmr(apply_A, b, x0, apply_Minv, tol, max_steps):
     return x, max_steps, np.linalg.norm(b - apply_A(x)) <= tol
 
 
-def top_eigenpairs(apply_S, dim, ell, steps=None, seed=0):
+def lanczos_start(dim):
+    """Deterministic Lanczos start vector: entry i is the fractional part of
+    (i + 1) * 0.6180339887498949 (golden-ratio sequence) minus 0.5,
+    normalised."""
+    i = np.arange(1, dim + 1, dtype=np.float64)
+    v = np.mod(i * 0.6180339887498949, 1.0) - 0.5
+    return v / np.linalg.norm(v)
+
+
+def top_eigenpairs(apply_S, dim, ell, steps=None, v0=None):
     """The ``ell`` largest eigenpairs of a symmetric positive semidefinite
     operator by the Lanczos method with full reorthogonalisation (Section
     3.3.3 asks for them for eq-T): ``steps`` Lanczos vectors (default
-    min(dim, 3 ell + 20)), Ritz pairs from the tridiagonal matrix."""
-    m = min(dim, steps if steps else 3 * ell + 20)
-    rng = np.random.default_rng(seed)
+    min(dim, 64)) from ``v0`` (default :func:`lanczos_start`), Ritz pairs
+    from the tridiagonal matrix."""
+    m = min(dim, steps if steps else 64)
     V = np.zeros((dim, m))
     a = np.zeros(m)
     b = np.zeros(m)
-    v = rng.standard_normal(dim)
-    v /= np.linalg.norm(v)
+    v = lanczos_start(dim) if v0 is None else np.asarray(v0, np.float64) / np.linalg.norm(v0)
     k = m
     for j in range(m):
         V[:, j] = v

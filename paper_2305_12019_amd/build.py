@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdwd.so")
 SOURCES = ["dwd_api.hip", "kernels_setup.hip", "kernels_iter.hip", "kernels_batch.hip", "kernels_csr.hip",
-           "kernels_direct.hip", "dwd_batch.hip", "dwd_serve.hip", "dwd_direct.hip"]
+           "kernels_direct.hip", "kernels_iterative.hip", "dwd_batch.hip", "dwd_serve.hip",
+           "dwd_direct.hip", "dwd_iterative.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

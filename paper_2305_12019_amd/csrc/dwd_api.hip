@@ -78,8 +78,10 @@ dwd_status validate_params(const dwd_params* p, bool for_solve) {
   if (p->sigma_every < 1) return fail(DWD_E_INVALID, "sigma_every must be >= 1");
   if (p->class_weights != 0 && p->class_weights != 1)
     return fail(DWD_E_INVALID, "class_weights must be 0 or 1");
-  if (p->solver != DWD_SOLVER_SMW && p->solver != DWD_SOLVER_DIRECT && p->solver != DWD_SOLVER_AUTO)
-    return fail(DWD_E_INVALID, "solver must be DWD_SOLVER_SMW, _DIRECT or _AUTO");
+  if (p->solver < DWD_SOLVER_SMW || p->solver > DWD_SOLVER_ITERATIVE)
+    return fail(DWD_E_INVALID, "solver must be DWD_SOLVER_SMW, _DIRECT, _AUTO or _ITERATIVE");
+  if (p->ell < 0 || p->ell == 1 || p->ell > kItMaxEll)
+    return fail(DWD_E_INVALID, "ell must be 0 (default) or 2..32");
   return DWD_OK;
 }
 
@@ -150,10 +152,16 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   dwd_status s;
   if ((s = validate_matrix(X)) != DWD_OK) return s;
   if ((s = validate_params(p, false)) != DWD_OK) return s;
-  if (p->solver != DWD_SOLVER_SMW && p->solver != DWD_SOLVER_DIRECT && p->solver != DWD_SOLVER_AUTO)
-    return fail(DWD_E_INVALID, "solver must be DWD_SOLVER_SMW, _DIRECT or _AUTO");
+  if (p->solver < DWD_SOLVER_SMW || p->solver > DWD_SOLVER_ITERATIVE)
+    return fail(DWD_E_INVALID, "solver must be DWD_SOLVER_SMW, _DIRECT, _AUTO or _ITERATIVE");
+  if (p->ell < 0 || p->ell == 1 || p->ell > kItMaxEll)
+    return fail(DWD_E_INVALID, "ell must be 0 (default) or 2..32");
   const int solver = resolve_solver(p, X);
-  if (solver == DWD_SOLVER_DIRECT) {
+  if (solver == DWD_SOLVER_ITERATIVE) {
+    if (X->layout != DWD_DENSE) return fail(DWD_E_INVALID, "the iterative solver needs dense X");
+    if (p->storage == DWD_BF16)
+      return fail(DWD_E_INVALID, "the iterative solver needs FP32 or FP64 storage");
+  } else if (solver == DWD_SOLVER_DIRECT) {
     if (X->layout != DWD_DENSE) return fail(DWD_E_INVALID, "the direct solver needs dense X");
     if (p->storage == DWD_BF16)
       return fail(DWD_E_INVALID, "the direct solver needs FP32 or FP64 storage");
@@ -169,6 +177,7 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   P->n = (int)X->n;
   P->solver = solver;
   P->ld = solver == DWD_SOLVER_DIRECT ? direct_ld(X->d) : padded_ld(X->d);
+  const int ell_req = p->ell;
   P->storage = p->storage;
   P->mu = p->mu;
   P->layout = X->layout;
@@ -355,8 +364,12 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   if (!std::isfinite(frob2)) return cleanup(fail(DWD_E_INVALID, "X has non-finite entries"));
   if (!(frob2 > 0.0)) return cleanup(fail(DWD_E_INVALID, "X is all zero"));
   P->zscale = sqrt(sqrt(frob2));  // Z_scale = sqrt(||X||_F)
-  if (P->solver == DWD_SOLVER_DIRECT) {
-    if ((s = setup_direct(P, st)) != DWD_OK) return cleanup(s);
+  if (P->solver == DWD_SOLVER_DIRECT || P->solver == DWD_SOLVER_ITERATIVE) {
+    dwd_params pe = *p;
+    pe.ell = ell_req;
+    if ((s = P->solver == DWD_SOLVER_DIRECT ? setup_direct(P, st) : setup_iterative(P, &pe, st)) !=
+        DWD_OK)
+      return cleanup(s);
     if ((e = hipHostMalloc((void**)&P->h_flags, 4096, 0)) != hipSuccess)
       return cleanup(hip_fail(e, "hipHostMalloc"));
     if ((e = hipEventCreate(&P->ev_a)) != hipSuccess) return cleanup(hip_fail(e, "event"));
@@ -716,6 +729,8 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
   dwd_status s;
   if (!P) return fail(DWD_E_INVALID, "problem is NULL");
   if (P->solver == DWD_SOLVER_DIRECT) return solve_direct(P, p, w, info, alpha, r, xi, u, rho);
+  if (P->solver == DWD_SOLVER_ITERATIVE)
+    return solve_iterative(P, p, w, info, alpha, r, xi, u, rho);
   if ((s = validate_params(p, true)) != DWD_OK) return s;
   if ((s = validate_penalty(p, P->n)) != DWD_OK) return s;
   HIP_TRY(hipSetDevice(P->device));
@@ -998,9 +1013,11 @@ dwd_status dwd_inspect(dwd_problem H, const char* what, double* out, int64_t cou
   Problem* P = H->P;
   const std::string w(what);
   const int64_t nn = (int64_t)P->n * P->n;
-  if (w == "zscale" || w == "ymy" || w == "solver") {
+  if (w == "zscale" || w == "ymy" || w == "solver" || w == "ell") {
     if (count != 1) return fail(DWD_E_INVALID, "count must be 1");
-    out[0] = w == "zscale" ? P->zscale : (w == "ymy" ? P->ymy : (double)P->solver);
+    out[0] = w == "zscale" ? P->zscale
+                           : (w == "ymy" ? P->ymy
+                                         : (w == "solver" ? (double)P->solver : (double)P->ipt.ell));
     return DWD_OK;
   }
   const double* src = nullptr;
@@ -1010,6 +1027,7 @@ dwd_status dwd_inspect(dwd_problem H, const char* what, double* out, int64_t cou
   else if (w == "Minv" && !direct) { src = P->Minv; m = nn; }
   else if (w == "my" && !direct) { src = P->my; m = P->n; }
   else if (w == "Ainv" && direct) { src = P->Ainv; m = (P->d + 1) * (P->d + 1); }
+  else if (w == "lam" && P->solver == DWD_SOLVER_ITERATIVE) { src = P->ipt.lam; m = P->ipt.ell; }
   else return fail(DWD_E_INVALID, "unknown quantity for this problem's solver");
   if (count != m) return fail(DWD_E_INVALID, "wrong count");
   hipError_t e = hipSetDevice(P->device);
@@ -1021,8 +1039,10 @@ dwd_status dwd_inspect(dwd_problem H, const char* what, double* out, int64_t cou
 
 int64_t dwd_footprint(const dwd_matrix* X, const dwd_params* p) {
   if (!X || !p || X->d < 1 || X->n < 1) return 0;
-  if (resolve_solver(p, X) == DWD_SOLVER_DIRECT)
-    return direct_footprint(X->d, (int)X->n, p->storage);
+  const int sv = resolve_solver(p, X);
+  if (sv == DWD_SOLVER_DIRECT) return direct_footprint(X->d, (int)X->n, p->storage);
+  if (sv == DWD_SOLVER_ITERATIVE)
+    return iterative_footprint(X->d, (int)X->n, p->storage, p->ell > 0 ? p->ell : 10);
   return problem_footprint(X->d, (int)X->n, p->storage, X->layout, X->nnz);
 }
 

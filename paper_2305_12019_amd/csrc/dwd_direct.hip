@@ -22,9 +22,11 @@ int64_t direct_ld(int64_t d) { return (d + 15) / 16 * 16; }
 // The solver choice printed with the paper's pseudo-code, with the direct
 // factor only where this library builds it (dense X, FP32/FP64 storage).
 int resolve_solver(const dwd_params* p, const dwd_matrix* X) {
-  if (p->solver == DWD_SOLVER_DIRECT) return DWD_SOLVER_DIRECT;
+  if (p->solver == DWD_SOLVER_DIRECT || p->solver == DWD_SOLVER_ITERATIVE) return p->solver;
   if (p->solver != DWD_SOLVER_AUTO) return DWD_SOLVER_SMW;
-  if (X->d <= 5000 && X->layout == DWD_DENSE && p->storage != DWD_BF16) return DWD_SOLVER_DIRECT;
+  const bool dense = X->layout == DWD_DENSE && p->storage != DWD_BF16;
+  if (X->d <= 5000 && dense) return DWD_SOLVER_DIRECT;
+  if (X->n > 65536 && dense) return DWD_SOLVER_ITERATIVE;
   return DWD_SOLVER_SMW;
 }
 

@@ -211,6 +211,8 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
     if (s == DWD_OK && reqs[i].params.representer &&
         resolve_solver(&reqs[i].params, &reqs[i].X) == DWD_SOLVER_DIRECT)
       s = fail(DWD_E_INVALID, "the representer iteration needs the SMW set-up");
+    if (s == DWD_OK && resolve_solver(&reqs[i].params, &reqs[i].X) == DWD_SOLVER_ITERATIVE)
+      s = fail(DWD_E_INVALID, "dwd_serve does not run the iterative solver");
     if (s != DWD_OK) return s;
     memset(&out[i].info, 0, sizeof(dwd_info));
     out[i].status = DWD_E_BUSY;

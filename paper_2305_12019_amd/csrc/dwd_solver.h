@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "dwd_internal.h"
+#include "dwd_iterative.h"
 
 namespace dwd {
 
@@ -78,6 +79,7 @@ struct Problem {
   int solver = DWD_SOLVER_SMW;  // factor built at set-up (SMW or direct)
   double* Ainv = nullptr;      // direct: inverse of the (d+1)^2 eq-linsys matrix
   DirPtrs dp{};                // direct: iteration state
+  ItPtrs ipt{};                // iterative: iteration state
   double* y = nullptr;
   double* e = nullptr;         // penalty weights of eq-primal (n)
   bool e_ones = true;          // e currently holds all ones
@@ -162,6 +164,12 @@ dwd_status solve_direct(Problem* P, const dwd_params* p, double* w, dwd_info* in
 int64_t direct_footprint(int64_t d, int n, int storage);
 // One iteration of the direct branch queued on st (seven launches).
 hipError_t queue_direct_iteration(Problem* P, const Consts& c, hipStream_t st);
+// Iterative branch (dwd_iterative.hip).
+dwd_status setup_iterative(Problem* P, const dwd_params* p, hipStream_t st);
+dwd_status solve_iterative(Problem* P, const dwd_params* p, double* w, dwd_info* info,
+                           double* alpha, double* r, double* xi, double* u, double* rho);
+hipError_t queue_iterative_iteration(Problem* P, const Consts& c, hipStream_t st);
+int64_t iterative_footprint(int64_t d, int n, int storage, int ell);
 // The factor a set-up request resolves to (DWD_SOLVER_SMW or DWD_SOLVER_DIRECT).
 int resolve_solver(const dwd_params* p, const dwd_matrix* X);
 dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* info,

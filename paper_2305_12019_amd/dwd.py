@@ -24,7 +24,7 @@ DENSE, CSR = 0, 1
 STATUS = {0: "DWD_OK", 1: "DWD_NOT_CONVERGED", -1: "DWD_E_INVALID", -2: "DWD_E_NOMEM",
           -3: "DWD_E_DEVICE", -4: "DWD_E_NUMERIC", -5: "DWD_E_BUSY"}
 _STORAGE = {"f64": FP64, "fp64": FP64, "f32": FP32, "fp32": FP32, "bf16": BF16}
-_SOLVER = {"smw": 0, "direct": 1, "auto": 2}
+_SOLVER = {"smw": 0, "direct": 1, "auto": 2, "iterative": 3}
 
 
 class DwdError(RuntimeError):
@@ -47,7 +47,8 @@ class Params(C.Structure):
                 ("refine", C.c_int32), ("lowp_tol", C.c_double), ("profile", C.c_int32),
                 ("batch_fp32", C.c_int32), ("batch_tile", C.c_int32), ("graph", C.c_int32),
                 ("sigma_every", C.c_int32), ("representer", C.c_int32),
-                ("class_weights", C.c_int32), ("solver", C.c_int32), ("e", C.c_void_p)]
+                ("class_weights", C.c_int32), ("solver", C.c_int32), ("ell", C.c_int32),
+                ("e", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -231,7 +232,7 @@ class Problem:
     """A set-up problem (dwd_setup); free with close() or by garbage collection."""
 
     def __init__(self, X=None, y=None, storage="f32", mu: float = 1.0, csr=None, stream=None,
-                 solver="smw"):
+                 solver="smw", ell: int = 0):
         keep: List = []
         if csr is not None:
             indptr, indices, values, d = csr
@@ -242,7 +243,7 @@ class Problem:
         yy = np.ascontiguousarray(np.asarray(y, dtype=np.float64))
         if yy.shape != (self.n,):
             raise ValueError("y must have n entries")
-        p = params(storage=storage, mu=mu, solver=solver)
+        p = params(storage=storage, mu=mu, solver=solver, ell=ell)
         self._h = C.c_void_p()
         st = _current_stream() if stream is None else C.c_void_p(stream)
         _check(_lib.dwd_setup(C.byref(m), _dptr(yy), C.byref(p), st, C.byref(self._h)))
@@ -297,7 +298,12 @@ class Problem:
 
     def inspect(self, what: str) -> np.ndarray:
         """Copy a set-up quantity to the host (dwd_inspect)."""
-        size = {"zscale": 1, "ymy": 1, "solver": 1, "G": self.n * self.n,
+        if what == "lam":
+            m = int(self.inspect("ell")[0])
+            out = np.empty(m)
+            _check(_lib.dwd_inspect(self._h, b"lam", _dptr(out), m))
+            return out
+        size = {"zscale": 1, "ymy": 1, "solver": 1, "ell": 1, "G": self.n * self.n,
                 "Minv": self.n * self.n, "my": self.n,
                 "Ainv": (self.d + 1) * (self.d + 1)}[what]
         out = np.empty(size)
@@ -322,7 +328,8 @@ class Problem:
 
 def solve(X, y, C_: float = 1.0, q: float = 1.0, tol: float = 1e-5, storage="f32", **kw) -> Dict:
     """Set up and solve one problem; returns w (unscaled), beta, state and info."""
-    P = Problem(X, y, storage=storage, mu=kw.pop("mu", 1.0), solver=kw.pop("solver", "smw"))
+    P = Problem(X, y, storage=storage, mu=kw.pop("mu", 1.0), solver=kw.pop("solver", "smw"),
+                ell=kw.pop("ell", 0))
     try:
         return P.solve(C_, q, tol, **kw)
     finally:

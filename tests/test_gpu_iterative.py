@@ -1,0 +1,123 @@
+"""Parity of the iterative branch (Section 3.3.3: the proximal term of eq-T
+from the ell largest eigenpairs of Z~ Z~^T, solved in closed form through
+eq-schur) with the oracle's iterative branch when it uses T from the first
+iteration (psqmr_max = 0), through the C ABI."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dwd_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dwd():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_12019_amd import dwd as D
+    return D
+
+
+def _data(d, n, seed, storage="f32", log_scale=0.5):
+    return synth.random_two_class(d, n, seed=seed, mean=0.6, log_scale=log_scale,
+                                  dtype="f64" if storage == "f64" else "f32")
+
+
+@pytest.mark.parametrize("d,n,ell,storage", [(400, 300, 10, "f32"), (1500, 120, 6, "f64"),
+                                             (3000, 2100, 6, "f32"), (7000, 90, 12, "f32")])
+def test_eigenpairs_match_the_oracle_lanczos_and_a_dense_solver(dwd, d, n, ell, storage):
+    # (64 Lanczos steps resolve these top pairs; the flat spectrum of the
+    # d = 3000, n = 2100 data is spread by feature scales over 1.5 decades)
+    X, y = _data(d, n, seed=d + n, storage=storage, log_scale=1.5 if d == 3000 else 0.5)
+    P = dwd.Problem(X, y, storage=storage, solver="iterative", ell=ell)
+    assert P.inspect("solver")[0] == 3 and P.inspect("ell")[0] == ell
+    lam = P.inspect("lam")
+    P.close()
+    Zt, _ = O.scale_data(X, y)
+    lo, _ = O.top_eigenpairs(lambda v: Zt @ (Zt.T @ v), d, ell)
+    assert np.allclose(lam, lo, rtol=1e-9)
+    ev = np.linalg.eigvalsh(Zt.T @ Zt)[::-1][:ell]   # the same nonzero spectrum
+    assert np.allclose(lam, ev, rtol=1e-7)
+
+
+@pytest.mark.parametrize("d,n,storage", [(400, 300, "f32"), (900, 150, "f64")])
+def test_iterative_trajectory_follows_oracle(dwd, d, n, storage):
+    X, y = _data(d, n, seed=3 * d + n, storage=storage)
+    e = synth.penalty_vector(n, seed=n + 3)
+    C, q = 1.0, 1.0
+    P = dwd.Problem(X, y, storage=storage, solver="iterative", ell=8)
+    for k in (1, 2, 5, 20):
+        o = O.solve(X, y, C, q, tol=1e-300, max_iter=k, solver="iterative", ell=8, psqmr_max=0,
+                    weights=True, e=e)
+        g = P.solve(C, q, tol=1e-300, max_iter=k, class_weights=1, e=e)
+        assert g["info"]["iters"] == k
+        for key in ("alpha", "r", "xi"):
+            assert np.allclose(g[key], o[key], rtol=1e-8, atol=1e-11), (k, key)
+        for key in ("w", "u", "rho"):
+            assert np.allclose(g[key], o[key], rtol=1e-8,
+                               atol=1e-11 * max(1e-300, np.abs(o[key]).max())), (k, key)
+        assert abs(g["beta"] - o["beta"]) <= 1e-8 * max(1.0, abs(o["beta"])), k
+        assert g["info"]["n_double"] == o["n_double"], k
+    P.close()
+
+
+@pytest.mark.parametrize("d,n,q,C", [(400, 300, 1.0, 1.0), (800, 200, 2.0, 3.0),
+                                     (300, 1000, 0.5, 0.5)])
+def test_iterative_solves_match_oracle(dwd, d, n, q, C):
+    X, y = _data(d, n, seed=d + n, log_scale=0.5 if d != 800 else 1.0)
+    P = dwd.Problem(X, y, storage="f32", solver="iterative")
+    for tol in (1e-6, 1e-7):
+        ref = O.solve(X, y, C, q, tol=tol, max_iter=20000, solver="iterative", psqmr_max=0)
+        assert ref["converged"]
+        got = P.solve(C, q, tol=tol, max_iter=20000)
+        assert got["info"]["converged"] == 1, got["info"]
+        assert abs(got["info"]["iters"] - ref["iters"]) <= max(3, 0.1 * ref["iters"]), tol
+        w = got["w"] / max(1.0, np.linalg.norm(got["w"]))
+        wr = ref["w"] / max(1.0, np.linalg.norm(ref["w"]))
+        f = O.reduced_objective(X, y, w, got["beta"], C, q)
+        fr = O.reduced_objective(X, y, wr, ref["beta"], C, q)
+        assert abs(f - fr) <= 1e-6 * abs(fr), (tol, f, fr)
+        assert np.linalg.norm(got["w"] - ref["w"]) <= 1e-4 * np.linalg.norm(ref["w"])
+        k = O.kkt_of_solution(X, y, C, q, got)
+        assert max(k["P"], k["D"]) <= 2 * tol, k
+    # the same optimum as the exact SMW solves
+    smw = dwd.solve(X, y, C, q, tol=1e-7, solver="smw", max_iter=20000)
+    assert np.linalg.norm(got["w"] - smw["w"]) <= 1e-3 * np.linalg.norm(smw["w"])
+    P.close()
+
+
+def test_iterative_beyond_both_limits(dwd):
+    # d > 5120 and n > 65536: neither factor is built; AUTO picks this branch
+    d, n = 6000, 70000
+    X, y = synth.random_two_class(d, n, seed=91, mean=0.3, flip=0.05, dtype="f32")
+    P = dwd.Problem(X, y, storage="f32", solver="auto")
+    assert P.inspect("solver")[0] == 3
+    got = P.solve(1.0, 1.0, tol=1e-4, max_iter=5000)
+    P.close()
+    info = got["info"]
+    print("iterative d=6000 n=70000:", {k: info[k] for k in ("iters", "setup_ms", "solve_ms",
+                                                          "kkt_check", "eta_gap")})
+    assert info["converged"] == 1, info
+    Xd = X.astype(np.float64)
+    del X
+    k = O.kkt_of_solution(Xd, y, 1.0, 1.0, got)
+    assert max(k["P"], k["D"]) <= 1.5e-4, k
+
+
+def test_iterative_rejections(dwd):
+    X, y = _data(300, 100, seed=5)
+    with pytest.raises(dwd.DwdError):
+        dwd.Problem(X, y, storage="bf16", solver="iterative")
+    with pytest.raises(dwd.DwdError):
+        dwd.Problem(X, y, storage="f32", solver="iterative", ell=1)
+    P = dwd.Problem(X, y, storage="f32", solver="iterative")
+    with pytest.raises(dwd.DwdError):
+        P.solve_batch([dict(C=1.0, q=1.0)])
+    with pytest.raises(dwd.DwdError):
+        P.solve(1.0, 1.0, representer=1)
+    assert P.solve(1.0, 1.0, tol=1e-5)["info"]["converged"] == 1
+    P.close()
+    with pytest.raises(dwd.DwdError):
+        dwd.serve([dict(X=X, y=y, t_arrival=0.0, params=dict(solver=3))])
