@@ -34,8 +34,9 @@ struct ItPtrs {
   double *part_n;      // n-space partials, nbn x kItNpn (sweep 1)
   double *part_n2;     // n-space partials, nbn x kItNpn (sweep 2)
   double *part_d;      // d-space partials, nbd2 x 8
+  double *part3;       // Z~ [a0, a1, a2] sample-split partials, zsplits x 3 x ld
   Scal* sc;
-  int ell, nchunks, nbd, nbn, nbd2;
+  int ell, nchunks, nbd, nbn, nbd2, zsplits;
 };
 
 // Slots of ItPtrs::sca.
@@ -72,5 +73,9 @@ hipError_t launch_it_ritz(const Consts& c, const double* V, int m, const double*
                           double* Wm, hipStream_t st);
 hipError_t launch_it_gvec(const Consts& c, const ItPtrs& p, const double* Zy, hipStream_t st);
 hipError_t launch_it_copy(double* dst, const double* src, int64_t count, hipStream_t st);
+int it_zpass_splits(int64_t ld, int n);
+hipError_t launch_it_zpass(const void* X, int storage, const Consts& c, const ItPtrs& p,
+                           const double* a0, const double* a1, const double* a2, double* o0,
+                           double* o1, double* o2, const Scal* sc, hipStream_t st);
 
 }  // namespace dwd

@@ -35,6 +35,7 @@ int64_t iterative_footprint(int64_t d, int n, int storage, int ell) {
   b += (ld / kLdAlign) * 2 * (int64_t)n * 8;                 // Z~^T partials
   b += ((ld + kItDotsBlock - 1) / kItDotsBlock) * (kItMaxLanczos + 2) * 8;
   b += ((n + 255) / 256) * kItNpn * 16 + (ld / 256 + 1) * 64;
+  b += (int64_t)it_zpass_splits(ld, n) * 3 * ld * 8;        // sample-split pass partials
   return b;
 }
 
@@ -78,6 +79,8 @@ dwd_status setup_iterative(Problem* P, const dwd_params* p, hipStream_t st) {
   HIP_TRY_I(alloc(&q.part_n, (size_t)q.nbn * kItNpn));
   HIP_TRY_I(alloc(&q.part_n2, (size_t)q.nbn * kItNpn));
   HIP_TRY_I(alloc(&q.part_d, (size_t)q.nbd2 * 8));
+  q.zsplits = it_zpass_splits(ld, n);
+  HIP_TRY_I(alloc(&q.part3, (size_t)q.zsplits * 3 * ld));
   HIP_TRY_I(P->alloc((void**)&q.sc, 2 * sizeof(Scal)));  // [problem, skip flag]
   HIP_TRY_I(hipMemsetAsync(q.sc, 0, 2 * sizeof(Scal), st));
   q.y = P->y;
@@ -109,8 +112,8 @@ dwd_status setup_iterative(Problem* P, const dwd_params* p, hipStream_t st) {
     e = launch_gemvT(P->X_rec, P->st_rec, ld, n, vj, vj, q.partT, nullptr, st);
     if (e == hipSuccess) e = launch_it_reduceT(c, q, 3, st);
     if (e == hipSuccess)
-      e = launch_expand3(P->X_rec, P->st_rec, c, q.a0, q.a0, q.a0, P->y, W, q.scratch,
-                         q.scratch + ld, st);
+      e = launch_it_zpass(P->X_rec, P->st_rec, c, q, q.a0, q.a0, q.a0, W, q.scratch,
+                          q.scratch + ld, nullptr, st);
     if (e == hipSuccess) e = launch_it_dots(c, q, W, V, j + 1, ID_AUX, 0, st);
     if (e == hipSuccess) e = launch_it_copy(la + j, aux + j, 1, st);
     if (e == hipSuccess) e = launch_it_orth(c, W, V, j + 1, aux, st);
@@ -127,7 +130,7 @@ dwd_status setup_iterative(Problem* P, const dwd_params* p, hipStream_t st) {
   // Z~ y, g = (closed-form inverse) Z~ y, schur = y^T y - (Z~ y)^T g
   double* Zy = q.scratch;
   if (e == hipSuccess)
-    e = launch_expand3(P->X_rec, P->st_rec, c, P->y, P->y, P->y, P->y, Zy, q.h, q.wbar, st);
+    e = launch_it_zpass(P->X_rec, P->st_rec, c, q, P->y, P->y, P->y, Zy, q.h, q.wbar, nullptr, st);
   if (e == hipSuccess) e = launch_it_dots(c, q, Zy, q.Wm, ell - 1, ID_AUX, 0, st);
   if (e == hipSuccess) e = launch_it_gvec(c, q, Zy, st);
   if (e == hipSuccess) e = hipMemsetAsync(dv, 0, (size_t)ld * 11 * 8, st);
@@ -160,8 +163,8 @@ hipError_t queue_iterative_iteration(Problem* P, const Consts& c, hipStream_t st
     return e;
   if ((e = launch_it_reduceT(c, q, 1, st)) != hipSuccess) return e;
   // Step 1c: Z~ dr, the residual test and the re-solve
-  if ((e = launch_expand3(P->X_rec, P->st_rec, c, q.a0, q.a0, q.a0, q.y, q.zz, q.scratch,
-                          q.scratch + ld, st)) != hipSuccess)
+  if ((e = launch_it_zpass(P->X_rec, P->st_rec, c, q, q.a0, q.a0, q.a0, q.zz, q.scratch,
+                           q.scratch + ld, q.sc, st)) != hipSuccess)
     return e;
   if ((e = launch_it_dots(c, q, q.zz, q.Wm, L, ID_DR, 1, st)) != hipSuccess) return e;
   if ((e = launch_it_solve(c, q, 1, st)) != hipSuccess) return e;
@@ -171,8 +174,8 @@ hipError_t queue_iterative_iteration(Problem* P, const Consts& c, hipStream_t st
     return e;
   if ((e = launch_it_reduceT(c, q, 2, st)) != hipSuccess) return e;
   // Z~ [xi - r, alpha, Z~^T w]
-  if ((e = launch_expand3(P->X_rec, P->st_rec, c, q.a0, q.a1, q.a2, q.y, q.zz + ld,
-                          q.zz + 2 * ld, q.zz + 3 * ld, st)) != hipSuccess)
+  if ((e = launch_it_zpass(P->X_rec, P->st_rec, c, q, q.a0, q.a1, q.a2, q.zz + ld,
+                           q.zz + 2 * ld, q.zz + 3 * ld, q.sc, st)) != hipSuccess)
     return e;
   // Steps 2-3 in d-space, residuals, stopping and sigma rules
   if ((e = launch_it_dspace(c, q, 0, st)) != hipSuccess) return e;

@@ -7,8 +7,9 @@
 // g = (that inverse) Z~ y.  The eigenpairs come from Lanczos with full
 // reorthogonalisation on Z~ Z~^T (set-up).
 //
-// Products with Z use the SMW-layout passes (Z~^T v: k_gemvT partials,
-// reduced here; Z~ [a0, a1, a2]: the three-column k_expand).  d-vectors are
+// Products with Z use the SMW layout: Z~^T v by the k_gemvT partials,
+// reduced here; Z~ [a0, a1, a2] by a three-column pass split over samples as
+// well as rows (k_it_zpass, below: n is large in this branch).  d-vectors are
 // handled by grid-wide kernels over ld with block partials summed in a
 // fixed order; every kernel of an iteration returns at once once the
 // problem's stop flag is set.
@@ -618,6 +619,108 @@ hipError_t launch_it_gvec(const Consts& c, const ItPtrs& p, const double* Zy, hi
       hipSuccess)
     return e;
   hipLaunchKernelGGL(k_it_schur, dim3(1), dim3(64), 0, st, c, p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Z~ [a0, a1, a2] split over samples as well as rows (n is large here, so
+// row panels alone give too few blocks): block (panel, s) sums its share of
+// the samples into part3[(s*3 + q)*ld + row]; the second kernel adds the
+// shares in order.
+// ---------------------------------------------------------------------------
+constexpr int ZP_PANEL = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_it_zpass(const T* __restrict__ X, Consts c, ItPtrs p,
+                                                  const double* __restrict__ a0,
+                                                  const double* __restrict__ a1,
+                                                  const double* __restrict__ a2,
+                                                  const Scal* __restrict__ sc) {
+  if (sc && sc->done) return;
+  constexpr int V = Vec<T>::N;
+  constexpr int ROWS = 64 * V;
+  __shared__ double sv[3][ZP_PANEL];
+  __shared__ double red[4][3][ROWS];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t rbase = (int64_t)blockIdx.x * ROWS;
+  const T* xrow = X + rbase + lane * V;
+  const int S = gridDim.y;
+  const int per = (c.n + S - 1) / S;
+  const int s0 = blockIdx.y * per, s1 = min(c.n, s0 + per);
+  double acc[3][V];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc[j][e] = 0.0;
+  for (int pc = s0; pc < s1; pc += ZP_PANEL) {
+    const int pn = min(ZP_PANEL, s1 - pc);
+    for (int i = threadIdx.x; i < pn; i += 256) {
+      const double yz = p.y[pc + i] * c.inv_zs;
+      sv[0][i] = yz * a0[pc + i];
+      sv[1][i] = yz * a1[pc + i];
+      sv[2][i] = yz * a2[pc + i];
+    }
+    __syncthreads();
+    const int pw = (pn + 3) / 4;
+    const int j0 = wid * pw, j1 = min(pn, j0 + pw);
+    for (int j = j0; j < j1; ++j) {
+      double x[V];
+      Vec<T>::load(xrow + (int64_t)(pc + j) * c.ld, x);
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[q][e] = fma(x[e], sv[q][j], acc[q][e]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int e = 0; e < V; ++e) red[wid][q][lane * V + e] = acc[q][e];
+  __syncthreads();
+  for (int rr = threadIdx.x; rr < ROWS; rr += 256) {
+    const int64_t k = rbase + rr;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      p.part3[((size_t)blockIdx.y * 3 + q) * c.ld + k] =
+          (red[0][q][rr] + red[1][q][rr]) + (red[2][q][rr] + red[3][q][rr]);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_it_zreduce(Consts c, ItPtrs p, int S, double* o0,
+                                                    double* o1, double* o2,
+                                                    const Scal* __restrict__ sc) {
+  if (sc && sc->done) return;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int q = blockIdx.y;
+  if (k >= c.ld) return;
+  double s = 0.0;
+  for (int t = 0; t < S; ++t) s += p.part3[((size_t)t * 3 + q) * c.ld + k];
+  (q == 0 ? o0 : (q == 1 ? o1 : o2))[k] = s;
+}
+
+int it_zpass_splits(int64_t ld, int n) {
+  const int panels = (int)(ld / 256);
+  int S = (2048 + panels - 1) / panels;
+  S = std::min(S, std::max(1, (n + 255) / 256));
+  return std::max(1, std::min(S, 256));
+}
+
+hipError_t launch_it_zpass(const void* X, int storage, const Consts& c, const ItPtrs& p,
+                           const double* a0, const double* a1, const double* a2, double* o0,
+                           double* o1, double* o2, const Scal* sc, hipStream_t st) {
+  const int S = p.zsplits;
+  const int rows = storage == DWD_FP64 ? 128 : 256;
+  if (storage == DWD_FP64)
+    hipLaunchKernelGGL(k_it_zpass<double>, dim3((unsigned)(c.ld / rows), S), dim3(256), 0, st,
+                       (const double*)X, c, p, a0, a1, a2, sc);
+  else if (storage == DWD_FP32)
+    hipLaunchKernelGGL(k_it_zpass<float>, dim3((unsigned)(c.ld / rows), S), dim3(256), 0, st,
+                       (const float*)X, c, p, a0, a1, a2, sc);
+  else
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_it_zreduce, dim3((unsigned)((c.ld + 255) / 256), 3), dim3(256), 0, st, c,
+                     p, S, o0, o1, o2, sc);
   return hipGetLastError();
 }
 
