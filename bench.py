@@ -32,6 +32,8 @@ Beside it, on the same data and to the same tolerance, the line carries
             (--no-weighted skips it);
   direct    the direct (d+1)^2 branch on d=300 n=5e4 and d=54 n=581012
             (--no-direct skips it);
+  iterative the iterative branch (proximal eq-T) on d=6000 n=70000 and
+            d=20000 n=1e5 (--no-iterative skips it);
   cpu_baseline  one whole solve of the FP64 oracle on the host cores.
 Prints one JSON line.
 """
@@ -354,6 +356,39 @@ def direct_leg(dwd, torch, dev, steps):
     return out
 
 
+def iterative_leg(dwd, torch, dev):
+    """The iterative branch (Section 3.3.3: proximal term of eq-T, closed-form
+    solves) where neither factor is built: d=6000 n=70000 and d=20000 n=1e5,
+    FP32 storage, q=1, C=1, tol 1e-5, one whole solve each (set-up with the
+    Lanczos eigenpairs included).  `pass_gbs` counts the algorithmic bytes of
+    X of every pass (four per iteration, three when Step 1c keeps wbar) over
+    the iteration time."""
+    import synth
+    out = {}
+    for d, n in [(6000, 70000), (20000, 100000)]:
+        X, y = synth.random_two_class(d, n, seed=63, mean=0.3, flip=0.05, dtype="f32")
+        Xd = torch.from_numpy(X).to(dev)
+        del X
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P = dwd.Problem(Xd, y, storage="f32", solver="iterative")
+        ts = time.perf_counter() - t
+        r = P.solve(1.0, 1.0, tol=1e-5, want_state=False, max_iter=20000)
+        P.close()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        i = r["info"]
+        passes = 4 * i["iters"] - (i["iters"] - i["n_double"])
+        out[f"d{d}_n{n}"] = {
+            "solve_s": el, "setup_s": ts, "iters": i["iters"], "n_double": i["n_double"],
+            "ms_per_iter": i["solve_ms"] / max(1, i["iters"]), "converged": i["converged"],
+            "kkt_check": i["kkt_check"],
+            "pass_gbs": passes * d * n * 4 / (i["solve_ms"] * 1e-3) / 1e9}
+        del Xd
+        torch.cuda.empty_cache()
+    return out
+
+
 def large_leg(dwd, torch, dev):
     """Mixed precision on one large problem: BF16 storage against FP32."""
     import synth
@@ -394,6 +429,7 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-weighted", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
+    ap.add_argument("--no-iterative", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration) and one solve")
     args = ap.parse_args()
@@ -510,6 +546,9 @@ def main():
     if not args.no_direct:
         out["direct"] = direct_leg(dwd, torch, dev, args.steps)
         print("[bench] direct done", file=sys.stderr, flush=True)
+    if not args.no_iterative:
+        out["iterative"] = iterative_leg(dwd, torch, dev)
+        print("[bench] iterative done", file=sys.stderr, flush=True)
     if args.serve_requests > 0:
         del Xd
         torch.cuda.empty_cache()
