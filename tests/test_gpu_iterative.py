@@ -121,3 +121,23 @@ def test_iterative_rejections(dwd):
     P.close()
     with pytest.raises(dwd.DwdError):
         dwd.serve([dict(X=X, y=y, t_arrival=0.0, params=dict(solver=3))])
+    # CSR input: the iterative branch needs dense X
+    req = synth.Request(0, 0.0, d=3000, n=140, q=1.0, C=1.0, layout="csr", storage="f32",
+                        seed=42)
+    ip, ix, val, yc = synth.request_csr_data(req, density=5e-3)
+    with pytest.raises(dwd.DwdError):
+        dwd.Problem(csr=(ip, ix, val, 3000), y=yc, storage="f32", solver="iterative")
+
+
+@pytest.mark.parametrize("d,n", [(400, 300), (6000, 9000)])
+def test_iterative_repeats_are_bit_identical(dwd, d, n):
+    # The Z~ passes add their row-panel and sample shares in a fixed order:
+    # two runs of the same solve give the same bits.
+    X, y = _data(d, n, seed=7 * d + n)
+    P = dwd.Problem(X, y, storage="f32", solver="iterative")
+    for k in (3, 30):
+        a = P.solve(1.5, 1.0, tol=1e-300, max_iter=k)
+        b = P.solve(1.5, 1.0, tol=1e-300, max_iter=k)
+        for key in ("w", "alpha", "r", "xi", "u", "rho"):
+            assert np.array_equal(a[key], b[key]), (k, key)
+    P.close()
