@@ -261,6 +261,15 @@ __device__ __forceinline__ Step2Plan step2_plan_finish(const Consts& c, const do
 }
 
 
+// The plan's outcome and gamma for the tail kernel, written once per launch
+// by the kernel that sizes Step 2 (every block of it computes the same plan).
+__device__ __forceinline__ void publish_plan(const IterPtrs& p, const Step2Plan& pl) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    p.sc->redo = pl.redo;
+    p.sc->gamma = pl.gamma;
+  }
+}
+
 // Residuals of Section 4.3 from the reduced sums r[], computed in registers.
 __device__ __forceinline__ void finish_etas(const Consts& c, const double* r, double* e) {
   const double den = c.opC;

@@ -59,7 +59,7 @@ struct Scal {
   double sigma;
   double beta;
   double beta_bar;
-  double gamma;        // Step 2 ball scaling min(1, R/||g||)
+  double gamma;        // Step 2 ball scaling min(1, R/||g||) of this iteration
   double ytdr;         // y^T (r^{k+1} - r^k)
   double beta1;        // beta of the Step 1c re-solve
   double u2;           // ||u||^2 of the current u
@@ -71,7 +71,7 @@ struct Scal {
   int32_t doubled;     // this iteration redid Step 1c
   int32_t status;      // 0 ok, else a dwd_status error code
   int32_t frozen_iter; // batch: iteration at which the problem stopped
-  int32_t redo;        // batch: Step 1c outcome of this iteration (plan kernel)
+  int32_t redo;        // Step 1c outcome of this iteration (from the kernel that sizes Step 2)
   int32_t pad_;
   double red[R_COUNT];
   double eta[E_COUNT];

@@ -131,6 +131,7 @@ __global__ void __launch_bounds__(CSR_T) k_csr_pass(const int64_t* __restrict__ 
                                                     Consts c, IterPtrs p) {
   if (p.sc->done) return;
   const Step2Plan pl = step2_plan<CSR_T>(c, p);
+  publish_plan(p, pl);
   const double* ss = pl.redo ? p.s1 : p.s;
   const double* sa = pl.redo ? p.al1 : p.al0;
   const double sigma = p.sc->sigma;

@@ -512,6 +512,7 @@ k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
   }
   block_sum_k<NT, 6>(a);  // also orders the staging writes before their reads
   const Step2Plan pl = step2_plan_finish(c, a, k_it, u2);
+  publish_plan(p, pl);
   const int os = pl.redo ? PANEL : 0;
   double as[V], aa[V];
 #pragma unroll
@@ -640,6 +641,7 @@ __global__ void __launch_bounds__(256) k_rep_step(Consts c, IterPtrs p) {
   const int done = sc->done;  // tested after the plan's loads (see k_step1ab)
   const Step2Plan pl = step2_plan<256>(c, p);
   if (done) return;
+  publish_plan(p, pl);
   const int o = pl.redo;
   const double* al = o ? p.al1 : p.al0;
   const double* so = o ? p.s1 : p.s;
@@ -818,71 +820,112 @@ hipError_t launch_expand(const void* X, int storage, const Consts& c, const Iter
 // ---------------------------------------------------------------------------
 constexpr int NT1 = 512;
 
-// The d-space partials come from the pass (part_g, nblk_d blocks) and gamma
-// from the same plan the pass used.
-__global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d) {
+// Threads of the tail block, and rows per thread whose state it requests
+// before its reductions.
+constexpr int NTT = 1024;
+constexpr int TAIL_PRE = 2;
+// The tail's sums take one slot per group of TAIL_GROUP lanes: slots 0..8
+// and 9..17 the nine n-space sums of outcome 0 and 1 (Step 1c partials),
+// 18..23 the pass partials, 24 the most Newton steps (a maximum).  Lane g of
+// a group adds blocks g, g + TAIL_GROUP, ... in order, TAIL_UNROLL loads in
+// flight; the group then reduces over its lanes by a fixed tree.
+constexpr int TAIL_GROUP = 32;
+constexpr int TAIL_UNROLL = 16;
+constexpr int TAIL_SLOTS = 2 * 9 + NP2 + 1;
+static_assert(TAIL_SLOTS * TAIL_GROUP <= NTT, "every tail slot needs a lane group");
+
+// Sum (or maximum, for the Newton steps) of src[b * stride] over b = g,
+// g + TAIL_GROUP, ... < nb, in that order.
+template <bool MAX>
+__device__ __forceinline__ double tail_lane_sum(const double* __restrict__ src, int stride, int nb,
+                                                int g) {
+  double v = 0.0;
+  for (int b0 = g; b0 < nb; b0 += TAIL_GROUP * TAIL_UNROLL) {
+    double t[TAIL_UNROLL];
+#pragma unroll
+    for (int u = 0; u < TAIL_UNROLL; ++u) {
+      const int b = b0 + u * TAIL_GROUP;
+      t[u] = b < nb ? src[(size_t)b * stride] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < TAIL_UNROLL; ++u) v = MAX ? fmax(v, t[u]) : v + t[u];
+  }
+  return v;
+}
+
+// The outcome and gamma come from the kernel that sized Step 2 (sc->redo,
+// sc->gamma).  Every load the tail needs before its scalar work is requested
+// in one round: both outcomes' sums, the pass partials, and both outcomes of
+// this thread's first TAIL_PRE rows; the outcome is picked afterwards.
+__global__ void __launch_bounds__(NTT) k_tail(Consts c, IterPtrs p, int nblk_d) {
   Scal* sc = p.sc;
   if (sc->done) return;
   __shared__ double s_sigma;
+  __shared__ double s_sum[TAIL_SLOTS];
   const int nb = ngemv_blocks(c.n);
   // every device scalar this kernel needs, loaded at once
   const int k0 = sc->k;
-  const double u2 = sc->u2;
   const double sigma = sc->sigma;
   const double beta_bar = sc->beta_bar;
   const double beta_1 = sc->beta1;
   const int nd = sc->n_double;
   const int nm = sc->newton_max;
-  // The plan sums decide the outcome; then that outcome's nine n-space sums,
-  // the d-space sums and the largest Newton step count.
-  double pa[6];
-  plan_sums<NT1>(p, nb, pa);
-  const Step2Plan pl = step2_plan_finish(c, pa, k0, u2);
-  const int o = pl.redo;
-  constexpr int K = 9 + NP2;
-  double acc[K];
+  const int o = sc->redo;
+  const double gamma = sc->gamma;
+  // state of the first rows: rn, xi0, xi1, al0, al1, v, v1, s1, y, Prho
+  double pre[TAIL_PRE][10];
 #pragma unroll
-  for (int j = 0; j < K; ++j) acc[j] = 0.0;
-  double nmax = 0.0;
-  const double* pd_src = p.part_g;
-  for (int b = threadIdx.x; b < nb; b += NT1) {
-#pragma unroll
-    for (int j = 0; j < 9; ++j) acc[j] += p.part_c[(size_t)b * NPC + 1 + o * NPO + j];
-    nmax = fmax(nmax, p.part_it[b]);
+  for (int r = 0; r < TAIL_PRE; ++r) {
+    const int i = threadIdx.x + r * NTT;
+    const bool in = i < c.n;
+    pre[r][0] = in ? p.rn[i] : 0.0;
+    pre[r][1] = in ? p.xi0[i] : 0.0;
+    pre[r][2] = in ? p.xi1[i] : 0.0;
+    pre[r][3] = in ? p.al0[i] : 0.0;
+    pre[r][4] = in ? p.al1[i] : 0.0;
+    pre[r][5] = in ? p.v[i] : 0.0;
+    pre[r][6] = in ? p.v1[i] : 0.0;
+    pre[r][7] = in ? p.s1[i] : 0.0;
+    pre[r][8] = in ? p.y[i] : 0.0;
+    pre[r][9] = in ? p.Prho[i] : 0.0;
   }
-  for (int b = threadIdx.x; b < nblk_d; b += NT1)
-#pragma unroll
-    for (int j = 0; j < NP2; ++j) acc[9 + j] += pd_src[(size_t)b * NP2 + j];
-  block_sum_k<NT1, K>(acc);
   {
-    __shared__ double smax[NT1 / 64];
+    const int slot = threadIdx.x / TAIL_GROUP, g = threadIdx.x % TAIL_GROUP;
+    const bool is_max = slot == TAIL_SLOTS - 1;
+    double v = 0.0;
+    if (slot < 18)
+      v = tail_lane_sum<false>(p.part_c + 1 + (slot / 9) * NPO + slot % 9, NPC, nb, g);
+    else if (slot < 18 + NP2)
+      v = tail_lane_sum<false>(p.part_g + (slot - 18), NP2, nblk_d, g);
+    else if (is_max)
+      v = tail_lane_sum<true>(p.part_it, 1, nb, g);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) nmax = fmax(nmax, __shfl_xor(nmax, off, 64));
-    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = nmax;
-    __syncthreads();
-    double m = smax[0];
-    for (int w = 1; w < NT1 / 64; ++w) m = fmax(m, smax[w]);
-    nmax = m;
+    for (int off = TAIL_GROUP / 2; off > 0; off >>= 1) {
+      const double w = __shfl_xor(v, off, 64);
+      v = is_max ? fmax(v, w) : v + w;
+    }
+    if (g == 0 && slot < TAIL_SLOTS) s_sum[slot] = v;
   }
-
-  const double gamma = pl.gamma;
+  __syncthreads();
   const double beta = o ? beta_1 : beta_bar;
   if (threadIdx.x == 0) {
-    const double m = nmax;
+    const double m = s_sum[TAIL_SLOTS - 1];
+    const double* so = s_sum + o * 9;
+    const double* sd = s_sum + 18;
     double red[R_COUNT];
-    for (int j = 0; j < 9; ++j) red[R_PRES2 + j] = acc[j];
-    red[R_WU2] = acc[9];
-    red[R_W2] = acc[10];
-    red[R_DRES2] = acc[11];
-    red[R_ZA2] = acc[12];
+    for (int j = 0; j < 9; ++j) red[R_PRES2 + j] = so[j];
+    red[R_WU2] = sd[0];
+    red[R_W2] = sd[1];
+    red[R_DRES2] = sd[2];
+    red[R_ZA2] = sd[3];
     red[R_G2] = 0.0;
-    red[R_RHO2] = acc[13];
+    red[R_RHO2] = sd[4];
     double e[E_COUNT];
     e[E_PCHK] = e[E_DCHK] = 0.0;
     finish_etas(c, red, e);
     for (int j = 0; j < R_COUNT; ++j) sc->red[j] = red[j];
     for (int j = 0; j < E_COUNT; ++j) sc->eta[j] = e[j];
-    sc->u2 = acc[14];
+    sc->u2 = sd[5];
     sc->gamma = gamma;
     sc->beta = beta;
     sc->doubled = o;
@@ -905,24 +948,17 @@ __global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d) 
   const double sig1 = s_sigma;
   const double gr = 1.0 / (sigma * c.sqmu);
   const double rs = c.tau * sigma * c.sqmu;
-  const double* xs = o ? p.xi1 : p.xi0;
-  const double* as = o ? p.al1 : p.al0;
-  const double* ss = o ? p.s1 : p.s;
-  const double* vs = o ? p.v1 : p.v;
-  for (int i = threadIdx.x; i < c.n; i += NT1) {
-    const double rn = p.rn[i];
-    const double xi = xs[i];
-    const double al = as[i];
-    const double v = vs[i];
+  // commit the outcome and form the next iteration's t and x
+  auto commit = [&](int i, double rn, double xi, double al, double v, double s1, double yi,
+                    double pr) {
     p.r[i] = rn;
     p.xi[i] = xi;
     p.alpha[i] = al;
     if (o) {
-      p.s[i] = ss[i];
+      p.s[i] = s1;
       p.v[i] = v;
     }
-    const double ztw = v - beta * p.y[i];
-    const double pr = p.Prho[i];
+    const double ztw = v - beta * yi;
     const double pu = gamma * (ztw - gr * pr);
     const double prn = pr - rs * (ztw - pu);
     p.Pu[i] = pu;
@@ -930,11 +966,23 @@ __global__ void __launch_bounds__(NT1) k_tail(Consts c, IterPtrs p, int nblk_d) 
     const double t = xi - rn - al / sig1;
     p.t[i] = t;
     p.x[i] = t + (c.mu * pu + c.sqmu * prn / sig1) / c.mu;
+  };
+#pragma unroll
+  for (int r = 0; r < TAIL_PRE; ++r) {
+    const int i = threadIdx.x + r * NTT;
+    if (i < c.n)
+      commit(i, pre[r][0], o ? pre[r][2] : pre[r][1], o ? pre[r][4] : pre[r][3],
+             o ? pre[r][6] : pre[r][5], pre[r][7], pre[r][8], pre[r][9]);
   }
+  const double* xs = o ? p.xi1 : p.xi0;
+  const double* as = o ? p.al1 : p.al0;
+  const double* vs = o ? p.v1 : p.v;
+  for (int i = threadIdx.x + TAIL_PRE * NTT; i < c.n; i += NTT)
+    commit(i, p.rn[i], xs[i], as[i], vs[i], p.s1[i], p.y[i], p.Prho[i]);
 }
 
 hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, hipStream_t st) {
-  hipLaunchKernelGGL(k_tail, dim3(1), dim3(NT1), 0, st, c, p, nblk_d);
+  hipLaunchKernelGGL(k_tail, dim3(1), dim3(NTT), 0, st, c, p, nblk_d);
   return hipGetLastError();
 }
 
