@@ -511,7 +511,7 @@ def main():
                    "setup_ms": float(np.median([i["setup_ms"] for i in infos])),
                    "solve_ms": float(np.median([i["solve_ms"] for i in infos]))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "roofline": {"bound": "hbm", "kernel": "k_pass2<float,8> (Z~ [s, alpha] pass)",
+        "roofline": {"bound": "hbm", "kernel": "k_pass2<float,4> (Z~ [s, alpha] pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
