@@ -495,80 +495,95 @@ hipError_t launch_it_scale(const Consts& c, double* out, const double* in, const
 }
 
 // Eigenpairs of the m x m Lanczos tridiagonal (diagonal alpha, off-diagonal
-// sqrt(beta2)) by cyclic Jacobi rotations, one thread (a one-off set-up step
-// on a matrix of at most 64 x 64).  lam[0..ell) descending, S[j * ell + i] =
-// component j of the eigenvector of lam[i].  work: 2 m^2 doubles.
-__global__ void k_it_eig(const double* __restrict__ alpha, const double* __restrict__ beta2,
-                         int m, int ell, double* __restrict__ lam, double* __restrict__ S,
-                         double* __restrict__ work) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double* A = work;
-  double* Q = work + m * m;
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) {
-      A[i * m + j] = 0.0;
-      Q[i * m + j] = i == j ? 1.0 : 0.0;
-    }
-  for (int i = 0; i < m; ++i) A[i * m + i] = alpha[i];
-  for (int i = 0; i + 1 < m; ++i) {
-    const double b = sqrt(fmax(beta2[i], 0.0));
-    A[i * m + i + 1] = b;
-    A[(i + 1) * m + i] = b;
+// sqrt(beta2)) by cyclic Jacobi rotations on one wave, the matrix and the
+// rotations in LDS (m <= 64): lane k applies each rotation to row k of the
+// columns p, q, then to column k of the rows p, q, then to row k of the
+// accumulated rotations.  lam[0..ell) descending, S[j * ell + i] = component
+// j of the eigenvector of lam[i]; S[m * ell + i] holds the chosen index.
+__global__ void __launch_bounds__(64) k_it_eig(const double* __restrict__ alpha,
+                                               const double* __restrict__ beta2, int m, int ell,
+                                               double* __restrict__ lam, double* __restrict__ S) {
+  __shared__ double A[kItMaxLanczos][kItMaxLanczos + 1];
+  __shared__ double Q[kItMaxLanczos][kItMaxLanczos + 1];
+  const int k = threadIdx.x;
+  const bool on = k < m;
+  for (int j = 0; j < kItMaxLanczos; ++j) {
+    A[k][j] = 0.0;
+    Q[k][j] = k == j ? 1.0 : 0.0;
   }
+  if (on) {
+    A[k][k] = alpha[k];
+    if (k + 1 < m) A[k][k + 1] = sqrt(fmax(beta2[k], 0.0));
+    if (k > 0) A[k][k - 1] = sqrt(fmax(beta2[k - 1], 0.0));
+  }
+  __syncthreads();
   for (int sweep = 0; sweep < 64; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int i = 0; i < m; ++i) {
-      dia += A[i * m + i] * A[i * m + i];
-      for (int j = i + 1; j < m; ++j) off += A[i * m + j] * A[i * m + j];
+    if (on) {
+      dia = A[k][k] * A[k][k];
+      for (int j = k + 1; j < m; ++j) off += A[k][j] * A[k][j];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      dia += __shfl_xor(dia, o, 64);
     }
     if (off <= 1e-32 * dia) break;
     for (int p = 0; p < m - 1; ++p)
       for (int q = p + 1; q < m; ++q) {
-        const double apq = A[p * m + q];
-        if (fabs(apq) <= 1e-300) continue;
-        const double theta = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
+        const double apq = A[p][q];
+        if (fabs(apq) <= 1e-300) continue;  // uniform: every lane reads the same value
+        const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
         const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
         const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
-        for (int k = 0; k < m; ++k) {  // columns p, q
-          const double akp = A[k * m + p], akq = A[k * m + q];
-          A[k * m + p] = cs * akp - sn * akq;
-          A[k * m + q] = sn * akp + cs * akq;
+        __syncthreads();
+        if (on) {  // columns p, q of row k
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = cs * akp - sn * akq;
+          A[k][q] = sn * akp + cs * akq;
         }
-        for (int k = 0; k < m; ++k) {  // rows p, q
-          const double apk = A[p * m + k], aqk = A[q * m + k];
-          A[p * m + k] = cs * apk - sn * aqk;
-          A[q * m + k] = sn * apk + cs * aqk;
+        __syncthreads();
+        if (on) {  // rows p, q of column k
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = cs * apk - sn * aqk;
+          A[q][k] = sn * apk + cs * aqk;
+          const double qkp = Q[k][p], qkq = Q[k][q];
+          Q[k][p] = cs * qkp - sn * qkq;
+          Q[k][q] = sn * qkp + cs * qkq;
         }
-        for (int k = 0; k < m; ++k) {
-          const double qkp = Q[k * m + p], qkq = Q[k * m + q];
-          Q[k * m + p] = cs * qkp - sn * qkq;
-          Q[k * m + q] = sn * qkp + cs * qkq;
-        }
+        __syncthreads();
       }
   }
   // the ell largest, descending (selection by repeated maxima)
+  __shared__ int chosen[kItMaxEll];
   for (int i = 0; i < ell; ++i) {
-    int best = -1;
-    double bv = -DBL_MAX;
-    for (int j = 0; j < m; ++j) {
-      bool used = false;
-      for (int t = 0; t < i; ++t) used = used || (int)S[(size_t)m * ell + t] == j;
-      if (!used && A[j * m + j] > bv) {
-        bv = A[j * m + j];
-        best = j;
+    if (k == 0) {
+      int best = -1;
+      double bv = -DBL_MAX;
+      for (int j = 0; j < m; ++j) {
+        bool used = false;
+        for (int t = 0; t < i; ++t) used = used || chosen[t] == j;
+        if (!used && A[j][j] > bv) {
+          bv = A[j][j];
+          best = j;
+        }
       }
+      chosen[i] = best;
+      S[(size_t)m * ell + i] = (double)best;
+      lam[i] = bv;
     }
-    S[(size_t)m * ell + i] = (double)best;  // index scratch after S
-    lam[i] = bv;
-    for (int j = 0; j < m; ++j) S[(size_t)j * ell + i] = Q[j * m + best];
+    __syncthreads();
+    if (on) S[(size_t)k * ell + i] = Q[k][chosen[i]];
+    __syncthreads();
   }
 }
 
 hipError_t launch_it_eig(const double* alpha, const double* beta, int m, int ell, double* lam,
                          double* S, hipStream_t st) {
-  // S holds m * ell entries plus ell index slots; work follows them
-  double* work = S + (size_t)m * ell + ell;
-  hipLaunchKernelGGL(k_it_eig, dim3(1), dim3(64), 0, st, alpha, beta, m, ell, lam, S, work);
+  // S holds m * ell entries plus ell index slots
+  if (m < 1 || m > kItMaxLanczos || ell < 1 || ell > kItMaxEll || ell > m)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_it_eig, dim3(1), dim3(64), 0, st, alpha, beta, m, ell, lam, S);
   return hipGetLastError();
 }
 
