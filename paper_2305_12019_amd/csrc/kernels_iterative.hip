@@ -678,7 +678,23 @@ __global__ void __launch_bounds__(256) k_it_zpass(const T* __restrict__ X, Const
     __syncthreads();
     const int pw = (pn + 3) / 4;
     const int j0 = wid * pw, j1 = min(pn, j0 + pw);
-    for (int j = j0; j < j1; ++j) {
+    int j = j0;
+    // four columns in flight per lane, then their products in column order
+    for (; j + 4 <= j1; j += 4) {
+      typename Vec<T>::raw_t xr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xr[u] = Vec<T>::raw(xrow + (int64_t)(pc + j + u) * c.ld);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double x[V];
+        Vec<T>::cvt(xr[u], x);
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc[q][e] = fma(x[e], sv[q][j + u], acc[q][e]);
+      }
+    }
+    for (; j < j1; ++j) {
       double x[V];
       Vec<T>::load(xrow + (int64_t)(pc + j) * c.ld, x);
 #pragma unroll
