@@ -764,7 +764,23 @@ __global__ void __launch_bounds__(256) k_expand(const T* __restrict__ X, Consts 
     __syncthreads();
     const int per = (pn + 3) / 4;
     const int j0 = wid * per, j1 = min(pn, j0 + per);
-    for (int j = j0; j < j1; ++j) {
+    int j = j0;
+    // four columns in flight per lane, then their products in column order
+    for (; j + 4 <= j1; j += 4) {
+      typename Vec<T>::raw_t xr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xr[u] = Vec<T>::raw(xrow + (int64_t)(pc + j + u) * c.ld);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double x[V];
+        Vec<T>::cvt(xr[u], x);
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc[q][e] = fma(x[e], sv[q][j + u], acc[q][e]);
+      }
+    }
+    for (; j < j1; ++j) {
       double x[V];
       Vec<T>::load(xrow + (int64_t)(pc + j) * c.ld, x);
 #pragma unroll
@@ -1054,7 +1070,20 @@ __global__ void __launch_bounds__(256) k_dres(const T* __restrict__ X, Consts c,
     __syncthreads();
     const int per = (pn + 3) / 4;
     const int j0 = wid * per, j1 = min(pn, j0 + per);
-    for (int j = j0; j < j1; ++j) {
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+      typename Vec<T>::raw_t xr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xr[u] = Vec<T>::raw(xrow + (int64_t)(pc + j + u) * c.ld);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double x[V];
+        Vec<T>::cvt(xr[u], x);
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[e] = fma(x[e], sv[j + u], acc[e]);
+      }
+    }
+    for (; j < j1; ++j) {
       double x[V];
       Vec<T>::load(xrow + (int64_t)(pc + j) * c.ld, x);
 #pragma unroll
