@@ -106,6 +106,32 @@ def test_small_f64_trajectory_follows_oracle(dwd, small_ref):
         assert abs(g["info"]["sigma"] - o["sigma"]) <= 1e-12 * o["sigma"]
 
 
+def test_large_n_trajectory_follows_oracle(dwd):
+    # n = 6001 (ragged) takes the paths that small n never reaches: several
+    # 2048-sample panels in the pass, the pass's looped plan reduction, row
+    # dots over six 1024-wide chunks, and several load rounds per lane in the
+    # tail's sums.  Weighted, with a penalty vector, so both Step 1c outcomes
+    # and every n-space sum are exercised.
+    d, n = 2000, 6001
+    X, y = synth.random_two_class(d, n, seed=61, mean=0.4, pos_frac=0.3, dtype="f32")
+    e = synth.penalty_vector(n, seed=62)
+    C, q = 2.0, 1.0
+    P = dwd.Problem(X, y, storage="f32")
+    for k in (1, 3, 8):
+        o = O.solve(X, y, C, q, tol=1e-300, max_iter=k, weights=True, e=e)
+        g = P.solve(C, q, tol=1e-300, max_iter=k, class_weights=1, e=e)
+        assert g["info"]["iters"] == k
+        for key in ("alpha", "r", "xi"):
+            assert np.allclose(g[key], o[key], rtol=1e-9, atol=1e-12), (k, key)
+        for key in ("w", "u", "rho"):
+            assert np.allclose(g[key], o[key], rtol=1e-9,
+                               atol=1e-12 * max(1e-300, np.abs(o[key]).max())), (k, key)
+        assert abs(g["beta"] - o["beta"]) <= 1e-9 * max(1.0, abs(o["beta"])), k
+        assert abs(g["info"]["sigma"] - o["sigma"]) <= 1e-12 * o["sigma"]
+        assert g["info"]["n_double"] == o["n_double"], k
+    P.close()
+
+
 @pytest.mark.parametrize("q,C,d,n,storage", [
     (2.0, 3.0, 5000, 123, "f32"),
     (0.5, 0.2, 3000, 200, "f64"),
