@@ -412,12 +412,14 @@ struct MfmaB<double> {
   __device__ static __forceinline__ int row(int l, int v) { return 4 * v + (l >> 4); }
 };
 
-// Global loads of one K tile into registers: A is 256 rows x 16 columns of X
-// (2 four-element row segments per thread), B is 16 x 16 NB of SB.
+// Global loads of one K tile into registers: A is 256 rows x BT_K columns of
+// X (BT_K / 8 four-element row segments per thread), B is BT_K x 16 NB of SB.
+constexpr int BT_AH = BT_K * BT_M / 4 / BT_T;  // A row segments per thread
+static_assert(BT_AH * 4 * BT_T == BT_K * BT_M, "the A tile must split evenly over the block");
 template <typename TD, int NB>
 struct TileRegs {
-  static constexpr int NBL = (16 * 16 * NB + BT_T - 1) / BT_T;  // B elements per thread
-  TD a[2][4];
+  static constexpr int NBL = (BT_K * 16 * NB + BT_T - 1) / BT_T;  // B elements per thread
+  TD a[BT_AH][4];
   double b[NBL];
 };
 
@@ -427,8 +429,8 @@ __device__ __forceinline__ void tile_load(const TD* __restrict__ X, const double
                                           TileRegs<TD, NB>& R) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int e = tid + h * BT_T;        // 0..1023
+  for (int h = 0; h < BT_AH; ++h) {
+    const int e = tid + h * BT_T;        // 64 row segments per k
     const int kk = e >> 6, r4 = (e & 63) * 4;
     const int k = k0 + kk;
     if (k < n) {
@@ -454,11 +456,11 @@ __device__ __forceinline__ void tile_load(const TD* __restrict__ X, const double
   }
 #pragma unroll
   for (int h = 0; h < TileRegs<TD, NB>::NBL; ++h) {
-    // B: slot j = e / 16, kk = e % 16 (16 consecutive k of one slot)
+    // B: slot j = e / BT_K, kk = e % BT_K (BT_K consecutive k of one slot)
     const int e = tid + h * BT_T;
-    const int j = e >> 4, kb = e & 15;
+    const int j = e / BT_K, kb = e % BT_K;
     const int kq = k0 + kb;
-    R.b[h] = (e < 16 * 16 * NB && j < bact_tile && kq < n) ? SB[(size_t)j * n + kq] : 0.0;
+    R.b[h] = (e < BT_K * 16 * NB && j < bact_tile && kq < n) ? SB[(size_t)j * n + kq] : 0.0;
   }
 }
 
@@ -467,7 +469,7 @@ __device__ __forceinline__ void tile_store(const TileRegs<TD, NB>& R, T (*As)[BT
                                            T (*Bs)[16 * NB + 4]) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < BT_AH; ++h) {
     const int e = tid + h * BT_T;
     const int kk = e >> 6, r4 = (e & 63) * 4;
 #pragma unroll
@@ -476,7 +478,7 @@ __device__ __forceinline__ void tile_store(const TileRegs<TD, NB>& R, T (*As)[BT
 #pragma unroll
   for (int h = 0; h < TileRegs<TD, NB>::NBL; ++h) {
     const int e = tid + h * BT_T;
-    if (e < 16 * 16 * NB) Bs[e & 15][e >> 4] = (T)R.b[h];
+    if (e < BT_K * 16 * NB) Bs[e % BT_K][e / BT_K] = (T)R.b[h];
   }
 }
 
@@ -492,7 +494,7 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P,
   constexpr bool F64 = sizeof(T) == 8;
   __shared__ T As[BT_K][BT_M + 4];
   __shared__ T Bs[BT_K][BN + 4];
-  __shared__ double red[8][BN][NP2];
+  __shared__ double Tz[16][BT_M + 1];
   __shared__ int s_p[BN];
   __shared__ int s_live[BN];
   __shared__ double s_sig[BN], s_gam[BN], s_tau[BN];
@@ -579,9 +581,27 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P,
   }
   const double mu = P.cs[s_p[0] >= 0 ? s_p[0] : 0].mu;
   const double sqmu = sqrt(mu);
+  // Epilogue, one group of 16 problems at a time: the group's 256 x 16
+  // results are staged in LDS by (problem, row), then 32 consecutive lanes
+  // walk the rows of one problem, so the FP64 d-vector loads and stores of
+  // a wave cover two contiguous 256-byte runs; each problem's partials are
+  // summed by its 32 lanes in a fixed tree (the same for every tile width).
+  const int ej = tid >> 5, er = tid & 31;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int j = b * 16 + (lane & 15);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double zs;
+        if constexpr (F64)
+          zs = acc[a][b][v];
+        else
+          zs = acc64[a][b][v];
+        Tz[lane & 15][wid * 32 + a * 16 + MfmaB<T>::row(lane, v)] = zs;
+      }
+    __syncthreads();
+    const int j = b * 16 + ej;
     const int p = s_p[j];
     const bool live = s_live[j] != 0;
     double pw[NP2] = {0, 0, 0, 0, 0, 0};
@@ -589,49 +609,35 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P,
       const double sigma = s_sig[j], gamma = s_gam[j];
       const double br = sqmu / sigma, gr = 1.0 / (sigma * sqmu);
       const double rs = s_tau[j] * sigma * sqmu;
-      const size_t od = (size_t)p * P.ld;
+      const size_t od = (size_t)p * P.ld + m0;
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t k = m0 + wid * 32 + a * 16 + MfmaB<T>::row(lane, v);
-          double zs;
-          if constexpr (F64)
-            zs = acc[a][b][v];
-          else
-            zs = acc64[a][b][v];
-          const double rho = P.RHO[od + k];
-          const double bb = mu * P.U[od + k] + br * rho;
-          const double w = (bb - zs) / mu;
-          const double u = gamma * (w - gr * rho);
-          const double rn = rho - rs * (w - u);
-          P.W[od + k] = w;
-          P.U[od + k] = u;
-          P.RHO[od + k] = rn;
-          pw[0] += (w - u) * (w - u);
-          pw[1] += w * w;
-          pw[4] += rn * rn;
-          pw[5] += u * u;
-        }
+      for (int i = 0; i < BT_M / 32; ++i) {
+        const int r = er + 32 * i;
+        const double zs = Tz[ej][r];
+        const double rho = P.RHO[od + r];
+        const double bb = mu * P.U[od + r] + br * rho;
+        const double w = (bb - zs) / mu;
+        const double u = gamma * (w - gr * rho);
+        const double rn = rho - rs * (w - u);
+        P.W[od + r] = w;
+        P.U[od + r] = u;
+        P.RHO[od + r] = rn;
+        pw[0] += (w - u) * (w - u);
+        pw[1] += w * w;
+        pw[4] += rn * rn;
+        pw[5] += u * u;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < NP2; ++q) {
-      pw[q] += __shfl_xor(pw[q], 16, 64);
-      pw[q] += __shfl_xor(pw[q], 32, 64);
-    }
-    if (lane < 16) {
+    for (int q = 0; q < NP2; ++q)
 #pragma unroll
-      for (int q = 0; q < NP2; ++q) red[wid][j][q] = pw[q];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < BN * NP2; e += BT_T) {
-    const int j = e / NP2, q = e % NP2;
-    if (!s_live[j]) continue;
-    double v = 0.0;
+      for (int o = 16; o > 0; o >>= 1) pw[q] += __shfl_xor(pw[q], o, 64);
+    if (live && er == 0) {
 #pragma unroll
-    for (int w8 = 0; w8 < 8; ++w8) v += red[w8][j][q];
-    P.part_g[((size_t)s_p[j] * P.npb + blockIdx.x) * NP2 + q] = v;
+      for (int q = 0; q < NP2; ++q)
+        P.part_g[((size_t)p * P.npb + blockIdx.x) * NP2 + q] = pw[q];
+    }
+    __syncthreads();  // the next group reuses Tz
   }
 }
 
