@@ -381,13 +381,19 @@ __global__ void __launch_bounds__(256) k_plan_b(BatchPtrs P, const int* __restri
 // 2-3:  g = w - rho/(sigma sqrt(mu)), u = gamma g,
 // rho -= tau sigma sqrt(mu)(w - u), and per-problem block partials (NP2
 // layout of the single pass; the two Z~ alpha entries are 0 here: the batched
-// tail gets them in n-space).  Block tile: 256 rows x 16 NB slots, 8 waves,
+// tail gets them in n-space).  Block tile: 128 rows x 16 NB slots, 4 waves,
 // wave w owns rows 32w..32w+31; the next K tile is loaded into registers
-// while the current one is multiplied.  Every output element is the same
+// while the current one is multiplied.  (Three 128-row blocks fit on a CU,
+// so the 784 blocks of d=1e5 finish in about one round; 256-row blocks ran
+// one per CU in two uneven rounds and were 6% slower, 15% with FP64
+// products.)  Every output element is the same
 // sequence of MFMA steps over k whatever NB is, so the tile width (chosen by
 // the host's tuner) does not change any result.
 // ---------------------------------------------------------------------------
-constexpr int BT_M = 256, BT_K = 16, BT_T = 512;
+constexpr int BT_M = 128, BT_K = 16, BT_T = 256;
+static_assert(BT_M == 32 * (BT_T / 64), "each wave owns 32 rows of the tile");
+constexpr int BT_SEG = BT_M / 4;       // four-element row segments per k
+constexpr int BT_LPP = BT_T / 16;      // epilogue lanes per problem of a 16-problem group
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v_b __attribute__((ext_vector_type(4)));
@@ -430,8 +436,8 @@ __device__ __forceinline__ void tile_load(const TD* __restrict__ X, const double
   const int tid = threadIdx.x;
 #pragma unroll
   for (int h = 0; h < BT_AH; ++h) {
-    const int e = tid + h * BT_T;        // 64 row segments per k
-    const int kk = e >> 6, r4 = (e & 63) * 4;
+    const int e = tid + h * BT_T;
+    const int kk = e / BT_SEG, r4 = (e % BT_SEG) * 4;
     const int k = k0 + kk;
     if (k < n) {
       const TD* src = X + (int64_t)k * ld + m0 + r4;
@@ -471,7 +477,7 @@ __device__ __forceinline__ void tile_store(const TileRegs<TD, NB>& R, T (*As)[BT
 #pragma unroll
   for (int h = 0; h < BT_AH; ++h) {
     const int e = tid + h * BT_T;
-    const int kk = e >> 6, r4 = (e & 63) * 4;
+    const int kk = e / BT_SEG, r4 = (e % BT_SEG) * 4;
 #pragma unroll
     for (int q = 0; q < 4; ++q) As[kk][r4 + q] = (T)R.a[h][q];
   }
@@ -486,7 +492,7 @@ __device__ __forceinline__ void tile_store(const TileRegs<TD, NB>& R, T (*As)[BT
 // inner dimension; FP32 products (T = float) are summed per K tile and the
 // tile sums added in FP64.
 template <typename TD, typename T, int NB>
-__global__ void __launch_bounds__(BT_T) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 2 : 4)))
+__global__ void __launch_bounds__(BT_T) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 : 4)))
 k_pass_b(const TD* __restrict__ X, BatchPtrs P,
                                                  const int* __restrict__ idx, int bact) {
   typedef typename MfmaB<T>::acc_t acc_t;
@@ -581,12 +587,12 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P,
   }
   const double mu = P.cs[s_p[0] >= 0 ? s_p[0] : 0].mu;
   const double sqmu = sqrt(mu);
-  // Epilogue, one group of 16 problems at a time: the group's 256 x 16
-  // results are staged in LDS by (problem, row), then 32 consecutive lanes
-  // walk the rows of one problem, so the FP64 d-vector loads and stores of
-  // a wave cover two contiguous 256-byte runs; each problem's partials are
-  // summed by its 32 lanes in a fixed tree (the same for every tile width).
-  const int ej = tid >> 5, er = tid & 31;
+  // Epilogue, one group of 16 problems at a time: the group's BT_M x 16
+  // results are staged in LDS by (problem, row), then BT_LPP consecutive
+  // lanes walk the rows of one problem, so the FP64 d-vector loads and
+  // stores of a wave cover contiguous runs; each problem's partials are
+  // summed by its lanes in a fixed tree (the same for every tile width).
+  const int ej = tid / BT_LPP, er = tid % BT_LPP;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
 #pragma unroll
@@ -611,8 +617,8 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P,
       const double rs = s_tau[j] * sigma * sqmu;
       const size_t od = (size_t)p * P.ld + m0;
 #pragma unroll
-      for (int i = 0; i < BT_M / 32; ++i) {
-        const int r = er + 32 * i;
+      for (int i = 0; i < BT_M / BT_LPP; ++i) {
+        const int r = er + BT_LPP * i;
         const double zs = Tz[ej][r];
         const double rho = P.RHO[od + r];
         const double bb = mu * P.U[od + r] + br * rho;
@@ -631,7 +637,7 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P,
 #pragma unroll
     for (int q = 0; q < NP2; ++q)
 #pragma unroll
-      for (int o = 16; o > 0; o >>= 1) pw[q] += __shfl_xor(pw[q], o, 64);
+      for (int o = BT_LPP / 2; o > 0; o >>= 1) pw[q] += __shfl_xor(pw[q], o, 64);
     if (live && er == 0) {
 #pragma unroll
       for (int q = 0; q < NP2; ++q)
