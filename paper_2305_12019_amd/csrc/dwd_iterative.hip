@@ -96,11 +96,11 @@ dwd_status setup_iterative(Problem* P, const dwd_params* p, hipStream_t st) {
   // Lanczos on Z~ Z~^T (m steps, full reorthogonalisation twice per step)
   double *V = nullptr, *lan = nullptr;
   HIP_TRY_I(hipMalloc((void**)&V, (size_t)m * ld * 8));
-  const size_t lan_count = 2 * (size_t)m + (size_t)m * ell + ell + 2 * (size_t)m * m;
+  const size_t lan_count = 2 * (size_t)m + (size_t)m * ell + ell;
   hipError_t e = hipMalloc((void**)&lan, lan_count * 8);
   double* la = lan;          // alpha_j
   double* lb = lan + m;      // beta_j^2
-  double* S = lan + 2 * m;   // m x ell, ell index slots, eig work
+  double* S = lan + 2 * m;   // m x ell eigenvector components, ell index slots
   double* W = q.h;           // work d-vector
   double* aux = q.dots + 3 * (kItMaxLanczos + 2);
   if (e == hipSuccess) e = hipMemsetAsync(lan, 0, lan_count * 8, st);
