@@ -128,3 +128,14 @@ def test_footprint_scales_with_the_problem(D):
     c = D.footprint(200_000, 1000, "f32")
     assert 4e8 < a < 8e8 and b > a and c > a
     assert D.footprint(0, 10) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # The solver runs on one GPU: bench.py --gpus N > 1 exits with a message
+    # before it touches a device.
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in r.stdout + r.stderr
