@@ -61,8 +61,9 @@ typedef enum { DWD_DENSE = 0, DWD_CSR = 1 } dwd_layout;
  *   DWD_SOLVER_ITERATIVE  n and d both large (Section 3.3.3): eq-linsys with
  *                     the proximal term T of eq-T, built from the ell largest
  *                     eigenpairs of Z~ Z~^T (Lanczos at set-up), solved in
- *                     closed form through eq-schur; four passes over X per
- *                     iteration, any n and d.  The paper first tries PSQMR
+ *                     closed form through eq-schur; three passes over X per
+ *                     iteration (four when Step 1c solves again), any n
+ *                     and d.  The paper first tries PSQMR
  *                     with T = 0 and switches to this term after a solve of
  *                     more than 50 steps; this library starts with the term
  *                     (PSQMR is not built on the GPU).  Dense X, FP32 or
