@@ -488,6 +488,10 @@ def main():
     bpl = pass_bytes(d, ld, n, 4)
     achieved = bpl / (avg_us * 1e-6) / 1e9
     iters = int(np.median([i["iters"] for i in infos]))
+    # whole-iteration rate: the X bytes of the one pass per iteration over the
+    # average time of an iteration of the solve loop (all kernels included)
+    it_us = float(np.median([i["solve_ms"] / max(1, i["iters"]) for i in infos])) * 1e3
+    it_gbs = d * n * 4 / (it_us * 1e-6) / 1e9
     copy_gbs = copy_bandwidth(torch, dev)
     traffic = recorded_traffic(bpl)
     out = {
@@ -517,6 +521,8 @@ def main():
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
                      "traffic_ratio": traffic["ratio_to_algorithmic"] if traffic else None,
                      "avg_launch_us": avg_us, "launches": launches,
+                     "iteration_us": it_us, "iteration_gbs": it_gbs,
+                     "iteration_frac": it_gbs / HBM_PEAK_GBS,
                      "bytes_per_launch": bpl,
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
     }
