@@ -93,6 +93,21 @@ def test_small_f64_solve_matches_oracle(dwd, small_ref):
     assert np.all(got["xi"] >= 0) and np.all(got["r"] > 0)
 
 
+def test_small_f64_solve_matches_stored_solution(dwd):
+    # The stored tight oracle solution (tests/golden/small_f64_solution.json,
+    # written by tests/golden/make_golden.py from the oracle alone).
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "small_f64_solution.json")) as f:
+        g = json.load(f)
+    wl = synth.SMALL_F64
+    X, y = synth.two_class(wl.data)
+    got = dwd.solve(X, y, wl.C, wl.q, tol=1e-8, storage="f64", max_iter=20000)
+    assert got["info"]["converged"] == 1
+    _compare(X, y, wl.C, wl.q, got, dict(w=np.array(g["w"]), beta=g["beta"]))
+
+
 def test_small_f64_trajectory_follows_oracle(dwd, small_ref):
     # A fixed number of iterations from the same start: the iterates agree.
     X, y, wl, ref, same = small_ref
