@@ -434,8 +434,9 @@ def main():
                     help="run only a 1 GiB device copy (counter calibration) and one solve")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this "
-              "build (see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print("bench.py: this solver runs on one GPU; runs on several GPUs are not "
+              "supported (the path would shard by rows of Z, one all-reduce of the pass "
+              "partials per iteration)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

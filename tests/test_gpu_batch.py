@@ -48,7 +48,7 @@ def test_batch_matches_oracle_and_single_solves(dwd, storage):
         assert b["converged"] == 1
         assert abs(a["iters"] - b["iters"]) <= max(2, 0.05 * a["iters"]), (j, a["iters"], b["iters"])
         assert np.linalg.norm(alone["w"] - res7["W"][j]) <= 1e-4 * np.linalg.norm(alone["w"])
-    # FP32 MFMA pass (opt-in, tol >= 1e-6): judged by its FP64 check and the objective.
+    # FP32 MFMA pass (opt-in, tol >= 1e-6): checked by its FP64 check and the objective.
     res5 = P.solve_batch([dict(C=C, q=q, tol=1e-5, batch_fp32=1) for C, q in grid])
     for j, (C, q) in enumerate(grid):
         info = res5["info"][j]
