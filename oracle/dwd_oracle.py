@@ -39,8 +39,9 @@ that a caller may change):
   root, because the derivative of the prox objective is increasing and
   concave); at most 50 steps; a step below 4 ulp also stops.
 * the dual objective takes alpha^(q/(q+1)) on max(alpha, 0).
-* sigma is updated after every iteration's stopping test; no update when
-  eta_P or eta_D is below 1e-300.
+* the sigma rule runs after the stopping test of every second iteration
+  (``sigma_every = 2``; the paper gives no cadence, 1 = every iteration);
+  no update when eta_P or eta_D is below 1e-300.
 * eta_D also carries eta_D3 = ||Z~ alpha + D rho|| / (1 + C), the dual
   feasibility of the multipliers: the infimum of the Lagrangian of eq-gen
   over w is finite only when Z~ alpha + D rho = 0.  The paper's eta_D1 and
@@ -562,31 +563,31 @@ def kkt_residuals(Zt, zscale, y, C, q, mu, r, w, beta, xi, u, alpha, rho=None,
         Ztw = Zt.T @ w
     den = 1.0 + C
     ce = C * (np.ones(len(r)) if e is None else np.asarray(e, np.float64))
-    e = {}
-    e["P1"] = np.linalg.norm(Ztw + beta * y + xi - r) / den
-    e["P2"] = math.sqrt(mu) * np.linalg.norm(w - u) / den
-    e["P3"] = max(np.linalg.norm(w) - zscale, 0.0) / den
-    e["D1"] = np.linalg.norm(np.minimum(0.0, alpha)) / den
-    e["D2"] = np.linalg.norm(np.maximum(0.0, alpha - ce)) / den
-    e["C1"] = abs(float(y @ alpha)) / den
-    e["C2"] = abs(float(xi @ (ce - alpha))) / den
+    eta = {}
+    eta["P1"] = np.linalg.norm(Ztw + beta * y + xi - r) / den
+    eta["P2"] = math.sqrt(mu) * np.linalg.norm(w - u) / den
+    eta["P3"] = max(np.linalg.norm(w) - zscale, 0.0) / den
+    eta["D1"] = np.linalg.norm(np.minimum(0.0, alpha)) / den
+    eta["D2"] = np.linalg.norm(np.maximum(0.0, alpha - ce)) / den
+    eta["C1"] = abs(float(y @ alpha)) / den
+    eta["C2"] = abs(float(xi @ (ce - alpha))) / den
     wt = np.ones_like(r) if wt is None else np.asarray(wt, np.float64)
     s = q * wt / r ** (q + 1.0)
-    e["C3"] = float(np.sum((alpha - s) ** 2)) / den
+    eta["C3"] = float(np.sum((alpha - s) ** 2)) / den
     Zalpha = Zt @ alpha
     if rho is not None:
-        e["D3"] = np.linalg.norm(Zalpha + math.sqrt(mu) * rho) / den
+        eta["D3"] = np.linalg.norm(Zalpha + math.sqrt(mu) * rho) / den
     primobj = float(np.sum(wt * r ** (-q)) + np.sum(ce * xi))
     dualobj = float(kappa(q) * np.sum(wt ** (1.0 / (q + 1.0))
                                       * np.maximum(alpha, 0.0) ** (q / (q + 1.0)))
                     - zscale * np.linalg.norm(Zalpha))
-    e["primobj"] = primobj
-    e["dualobj"] = dualobj
-    e["gap"] = abs(primobj - dualobj) / (1.0 + abs(primobj) + abs(dualobj))
-    e["P"] = max(e["P1"], e["P2"], e["P3"])
-    e["D"] = max(e["D1"], e["D2"], e["D3"] if (rho_residual and "D3" in e) else 0.0)
-    e["C"] = max(e["C1"], e["C2"], e["C3"])
-    return e
+    eta["primobj"] = primobj
+    eta["dualobj"] = dualobj
+    eta["gap"] = abs(primobj - dualobj) / (1.0 + abs(primobj) + abs(dualobj))
+    eta["P"] = max(eta["P1"], eta["P2"], eta["P3"])
+    eta["D"] = max(eta["D1"], eta["D2"], eta["D3"] if (rho_residual and "D3" in eta) else 0.0)
+    eta["C"] = max(eta["C1"], eta["C2"], eta["C3"])
+    return eta
 
 
 def stop_test(e, tol):

@@ -467,16 +467,6 @@ def test_planted_sign_error_in_rhs_is_caught(monkeypatch):
     assert (not conv) or err > 1e-7
 
 
-def test_planted_dropped_beta_term_in_step2_is_caught(monkeypatch):
-    orig = O.step2
-
-    def bad(w, beta, r, alpha, rho, Ztw, y, C, sigma, mu, radius, e=1.0):
-        return orig(w, 0.0, r, alpha, rho, Ztw, y, C, sigma, mu, radius, e)
-
-    conv, err = _solution_error(monkeypatch, "step2", bad)
-    assert (not conv) or err > 1e-7
-
-
 def test_planted_wrong_kappa_is_caught(tight_small):
     X, y, C, q, sol = tight_small
     # a kappa off by 1% would leave a visible duality gap at the true optimum
