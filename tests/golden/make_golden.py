@@ -1,6 +1,8 @@
 """Write the stored expected values in tests/golden/ from the oracle alone.
 
 Run from the repository root:  python tests/golden/make_golden.py
+(and  python tests/golden/make_golden.py hdlss  for the d = 1e5 solution,
+which takes minutes).
 
 The paper prints no worked example with numbers (its result tables need the
 UCI/LIBSVM data sets), so every stored value here is the oracle's, computed
@@ -71,7 +73,45 @@ def small_solution():
                                                       ref["beta"], wl.C, wl.q))})
 
 
+def _probe_directions(d, count=16, seed=20230519):
+    """Fixed seeded unit directions on which a long w is pinned compactly."""
+    V = np.random.default_rng(seed).standard_normal((count, d))
+    return V / np.linalg.norm(V, axis=1)[:, None]
+
+
+def hdlss_solution():
+    # Algorithm 1 on the d = 1e5, n = 1e3 HDLSS workload (FP32 data of record,
+    # computed in FP64) to a tight tolerance.  w has 1e5 entries, so the file
+    # keeps its norm, its first 32 entries and its projections on 16 seeded
+    # unit directions beside beta, the reduced objective and the multipliers
+    # alpha (n values, from which w = Z alpha / ||Z alpha|| and a dual bound
+    # follow without the oracle).
+    wl = synth.HDLSS_F32
+    X, y = synth.two_class(wl.data)
+    Xd = X.astype(np.float64)
+    ref = O.solve(Xd, y, wl.C, wl.q, tol=1e-9, max_iter=50000)
+    w = np.asarray(ref["w"], np.float64)
+    V = _probe_directions(w.size)
+    _write("hdlss_f32_solution.json", {
+        "passage": "Algorithm 1 (SMW branch) with Sections 4.2-4.4",
+        "call": "oracle.dwd_oracle.solve(X, y, C, q, tol=1e-9, max_iter=50000)",
+        "inputs": {"workload": wl.name, "d": wl.data.d, "n": wl.data.n, "seed": wl.data.seed,
+                   "mean": wl.data.mean, "flip": wl.data.flip, "C": wl.C, "q": wl.q},
+        "probe_directions": "tests/golden/make_golden.py _probe_directions(d, 16, 20230519)",
+        "converged": bool(ref["converged"]), "iters": int(ref["iters"]),
+        "beta": float(ref["beta"]), "w_norm": float(np.linalg.norm(w)),
+        "w_head": [float(v) for v in w[:32]],
+        "w_proj": [float(v) for v in V @ w],
+        "alpha": [float(v) for v in ref["alpha"]],
+        "reduced_objective": float(O.reduced_objective(Xd, y, w / max(1.0, np.linalg.norm(w)),
+                                                      ref["beta"], wl.C, wl.q))})
+
+
 if __name__ == "__main__":
+    if "hdlss" in sys.argv[1:]:
+        # (minutes of CPU time: written only on request)
+        hdlss_solution()
+        sys.exit(0)
     kappa_values()
     prox_q1_values()
     small_solution()
