@@ -58,21 +58,20 @@ typedef enum { DWD_DENSE = 0, DWD_CSR = 1 } dwd_layout;
  *                     FP32 or FP64 storage, n limited only by memory;
  *                     dwd_solve and dwd_serve (not dwd_solve_batch or the
  *                     representer iteration).
- *   DWD_SOLVER_ITERATIVE  n and d both large (Section 3.3.3): eq-linsys with
- *                     the proximal term T of eq-T, built from the ell largest
- *                     eigenpairs of Z~ Z~^T (Lanczos at set-up), solved in
- *                     closed form through eq-schur; three passes over X per
- *                     iteration (four when Step 1c solves again), any n
- *                     and d.  The paper first tries PSQMR
- *                     with T = 0 and switches to this term after a solve of
- *                     more than 50 steps; this library starts with the term
- *                     (PSQMR is not built on the GPU).  Dense X, FP32 or
+ *   DWD_SOLVER_ITERATIVE  n and d both large (Section 3.3.3): eq-linsys is
+ *                     first solved with T = 0 by PSQMR (two passes over X per
+ *                     step), and once a solve needs more than
+ *                     dwd_params.psqmr_max steps, with the proximal term T of
+ *                     eq-T, built from the ell largest eigenpairs of Z~ Z~^T
+ *                     (Lanczos at set-up), solved in closed form through
+ *                     eq-schur (three passes over X per iteration, four when
+ *                     Step 1c solves again).  Any n and d.  Dense X, FP32 or
  *                     FP64 storage, dwd_solve only.
- *   DWD_SOLVER_AUTO   the paper's choice: direct when d <= 5000, else the SMW
- *                     form while n <= 65536 (the paper's iterative case for
- *                     d > 5000 with n >= 0.2 d or n > 2500 included), else
- *                     the iterative branch.  CSR input or BF16 storage
- *                     resolve to SMW.                                         */
+ *   DWD_SOLVER_AUTO   the choice printed with the paper's solver pseudo-code
+ *                     (Section 6.1): direct when d <= 5000; when d > 5000,
+ *                     the SMW form if n < 0.2 d and n <= 2500, else the
+ *                     iterative branch.  CSR input and BF16 storage, which
+ *                     only the SMW form takes, resolve to SMW.               */
 typedef enum {
   DWD_SOLVER_SMW = 0,
   DWD_SOLVER_DIRECT = 1,
@@ -169,6 +168,15 @@ typedef struct {
                         during the call; NULL (default) = e = 1.  C e replaces
                         C in Step 2, eta_D2, eta_C2 and the primal objective.
                         dwd_solve_batch takes each problem's own e.           */
+  int32_t psqmr_max; /* DWD_SOLVER_ITERATIVE: Steps 1a and 1c first solve
+                        eq-linsys with T = 0 by preconditioned symmetric QMR
+                        to the accuracy of eq-linsys-tol (eps_k, 5 eps_k),
+                        warm started, with the eq-T system as preconditioner;
+                        once a solve needs more than psqmr_max steps, the
+                        proximal term of eq-T is used for the rest of the
+                        solve (Section 3.3.3).  Default 50; 0 = the proximal
+                        term from the first iteration.                        */
+  int32_t reserved;
 } dwd_params;
 
 /* Per-solve report.  Residuals are those of Section 4.3 on the scaled
@@ -195,6 +203,12 @@ typedef struct {
   double streamT_ms;    /* profile=1: summed duration of the Z~^T [u, rho] passes */
   int32_t streamT_launches;
   int32_t graph_launches; /* dwd_solve_batch: chunks replayed as a captured graph */
+  int32_t psqmr_steps;  /* DWD_SOLVER_ITERATIVE: PSQMR steps over the solve     */
+  int32_t psqmr_solves; /* DWD_SOLVER_ITERATIVE: PSQMR solves (Steps 1a and 1c) */
+  int32_t psqmr_switch; /* DWD_SOLVER_ITERATIVE: iteration from which the
+                           proximal term of eq-T was used (0 with psqmr_max = 0);
+                           -1 if PSQMR solved every system                     */
+  int32_t reserved;
 } dwd_info;
 
 typedef struct dwd_problem_s* dwd_problem;
@@ -232,7 +246,11 @@ dwd_status dwd_solve(dwd_problem P, const dwd_params* p, double* w, dwd_info* in
 
 /* Solve B problems that share P's X and y but have their own (C, q, tol,
  * sigma0, ...) in p[0..B-1], stepping all of them together: the products
- * with Z become d x n by n x B and n x d by d x B matrix products.
+ * with Z become d x n by n x B and n x d by d x B matrix products.  This
+ * rests on the matrix of eq-linsys depending on X, y and the (1,1) shift
+ * only, not on sigma, C or q (Section 3.3.2, eq-Anew): one factor serves
+ * every problem of the batch (a sweep over C and q, or the folds of a
+ * cross-validation over one X).
  *   W:    d x B column-major host array (column j = w of problem j).
  *   info: B reports (nullable).
  * Each problem follows exactly the iteration it would follow alone; a
@@ -246,10 +264,15 @@ void dwd_free(dwd_problem P);
 
 /* ---------------------------------------------------------------------
  * Serving: a trace of solve requests with arrival times is replayed in
- * real time.  Requests are admitted while their device footprint fits the
- * HBM budget and a slot is free; admitted problems are set up on the device
- * and stepped together with the other admitted problems, one iteration of
- * each per round, so requests that arrive while others run join them.
+ * real time.  Each request is a whole problem of Section 2 (its own X, y, C,
+ * q, tolerance) solved by Algorithm 1 as dwd_solve would solve it; serving is
+ * not in the paper, it is how such solves are run side by side on one GPU.
+ * Requests are admitted while their device footprint fits the HBM budget and
+ * a slot is free; their set-up runs beside the stepping; admitted problems of
+ * the SMW form are stepped together, one iteration of each per round, by
+ * launches that each cover all of them (direct-branch problems and sparse
+ * passes per problem), so requests that arrive while others run join them.
+ * Device memory comes from one allocation made when the replay starts.
  * ------------------------------------------------------------------- */
 typedef struct {
   dwd_matrix X;        /* data (host or device)                               */
@@ -298,7 +321,9 @@ dwd_status dwd_suggest_C(dwd_problem P, double q, double* C);
  *   "ymy"    (1): y^T M^-1 y with M = I + Z~^T Z~ / mu;
  *   "G"    (n*n): G~ = Z~^T Z~, row-major;
  *   "Minv" (n*n): M^-1, row-major;
- *   "my"     (n): M^-1 y.
+ *   "my"     (n): M^-1 y;
+ *   "psqmr_count" (1): PSQMR solves of the last dwd_solve (iterative branch);
+ *   "psqmr_steps" (psqmr_count): the steps of each of those solves, in order.
  * Returns DWD_E_INVALID for an unknown name or a wrong count.                  */
 dwd_status dwd_inspect(dwd_problem P, const char* what, double* out, int64_t count);
 

@@ -8,9 +8,13 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdwd.so")
 SOURCES = ["dwd_api.hip", "kernels_setup.hip", "kernels_iter.hip", "kernels_batch.hip", "kernels_csr.hip",
            "kernels_direct.hip", "kernels_iterative.hip", "dwd_batch.hip", "dwd_serve.hip",
-           "dwd_direct.hip", "dwd_iterative.hip"]
+           "dwd_direct.hip", "dwd_iterative.hip", "kernels_psqmr.hip"]
 
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+# -ffp-contract=on: multiply-adds are fused only within one source expression
+# (as written), never across statements by the back end, so a device function
+# inlined into two kernels (the single-problem and the multi-problem serving
+# forms) rounds the same way in both.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-Wno-unused-command-line-argument"]

@@ -76,6 +76,8 @@ dwd_status validate_params(const dwd_params* p, bool for_solve) {
   if (p->batch_tile != 0 && p->batch_tile != 1 && p->batch_tile != 2 && p->batch_tile != 4)
     return fail(DWD_E_INVALID, "batch_tile must be 0, 1, 2 or 4");
   if (p->sigma_every < 1) return fail(DWD_E_INVALID, "sigma_every must be >= 1");
+  if (p->psqmr_max < 0 || p->psqmr_max > 100000)
+    return fail(DWD_E_INVALID, "psqmr_max must be in [0, 100000]");
   if (p->class_weights != 0 && p->class_weights != 1)
     return fail(DWD_E_INVALID, "class_weights must be 0 or 1");
   if (p->solver < DWD_SOLVER_SMW || p->solver > DWD_SOLVER_ITERATIVE)
@@ -127,7 +129,12 @@ static dwd_status validate_labels(const double* y, int64_t n) {
 // ---------------------------------------------------------------------------
 static void release(Problem* P) {
   if (!P) return;
-  for (void* ptr : P->allocs) (void)hipFree(ptr);
+  for (void* ptr : P->allocs) {
+    if (P->arena)
+      P->arena->give(ptr);
+    else
+      (void)hipFree(ptr);
+  }
   P->allocs.clear();
   if (P->h_flags) (void)hipHostFree(P->h_flags);
   P->h_flags = nullptr;
@@ -139,16 +146,56 @@ static void release(Problem* P) {
   P->ev_a = P->ev_b = nullptr;
 }
 
+// Pinned completion flags and events of dwd_solve.
+hipError_t Problem::host_objects() {
+  hipError_t e;
+  if ((e = hipHostMalloc((void**)&h_flags, 4096, 0)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&ev_a)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&ev_b)) != hipSuccess) return e;
+  for (auto& ev : ev_chunk)
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+void destroy_problem(Problem* P) {
+  release(P);
+  delete P;
+}
+
 hipError_t Problem::alloc(void** ptr, size_t bytes) {
+  if (arena) {
+    *ptr = arena->take(bytes ? bytes : 8);
+    if (!*ptr) return hipErrorOutOfMemory;
+    allocs.push_back(*ptr);
+    return hipSuccess;
+  }
   hipError_t e = hipMalloc(ptr, bytes ? bytes : 8);
   if (e == hipSuccess) allocs.push_back(*ptr);
   return e;
 }
 
-static hipError_t alloc_tmp(void** ptr, size_t bytes) { return hipMalloc(ptr, bytes ? bytes : 8); }
+// (a fragmented arena falls back to hipMalloc for set-up scratch)
+hipError_t Problem::alloc_tmp(void** ptr, size_t bytes) {
+  if (arena && (*ptr = arena->take(bytes ? bytes : 8)) != nullptr) {
+    tmp_from_arena.push_back(*ptr);
+    return hipSuccess;
+  }
+  return hipMalloc(ptr, bytes ? bytes : 8);
+}
+
+void Problem::free_tmp(void* ptr) {
+  if (!ptr) return;
+  for (void* a : tmp_from_arena)
+    if (a == ptr) {
+      arena->give(ptr);
+      tmp_from_arena.erase(std::find(tmp_from_arena.begin(), tmp_from_arena.end(), ptr));
+      return;
+    }
+  (void)hipFree(ptr);
+}
 
 dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params* p,
-                         hipStream_t st, Problem** out) {
+                         hipStream_t st, Problem** out, DeviceArena* arena) {
   dwd_status s;
   if ((s = validate_matrix(X)) != DWD_OK) return s;
   if ((s = validate_params(p, false)) != DWD_OK) return s;
@@ -172,6 +219,7 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   if ((s = validate_labels(y, X->n)) != DWD_OK) return s;
   auto t0 = std::chrono::steady_clock::now();
   Problem* P = new Problem();
+  P->arena = arena;
   P->stream = st;
   P->d = X->d;
   P->n = (int)X->n;
@@ -268,15 +316,21 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
     P->nnz = nnz;
   } else if (!X->on_device) {
     size_t bytes = (size_t)d * n * in_el;
-    hipError_t e = alloc_tmp(&Xtmp, bytes);
+    hipError_t e = P->alloc_tmp(&Xtmp, bytes);
     if (e != hipSuccess) { delete P; return hip_fail(e, "hipMalloc(X staging)"); }
     e = hipMemcpyAsync(Xtmp, X->values, bytes, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) { (void)hipFree(Xtmp); delete P; return hip_fail(e, "H2D X"); }
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(st);
+      P->free_tmp(Xtmp);
+      delete P;
+      return hip_fail(e, "H2D X");
+    }
     Xdev = Xtmp;
   }
 
   auto cleanup = [&](dwd_status st_) {
-    if (Xtmp) (void)hipFree(Xtmp);
+    (void)hipStreamSynchronize(st);
+    if (Xtmp) P->free_tmp(Xtmp);
     release(P);
     delete P;
     return st_;
@@ -343,7 +397,7 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   const int ychunks = (int)std::max<int64_t>(1, std::min<int64_t>(64, ld / 8192));
   const int nfb = 256;  // blocks of the CSR norm
   double* part = nullptr;
-  if ((e = alloc_tmp((void**)&part, (size_t)std::max(n * ychunks, nfb) * 8)) != hipSuccess)
+  if ((e = P->alloc_tmp((void**)&part, (size_t)std::max(n * ychunks, nfb) * 8)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMalloc(part)"));
   if (csr) {
     e = launch_csr_frob(P->valT, P->csr_dtype, P->nnz, part, nfb, st);
@@ -355,9 +409,9 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   double frob2 = 0.0;
   if (e == hipSuccess) e = hipMemcpyAsync(&frob2, dscal, 8, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(part);
+  P->free_tmp(part);
   if (Xtmp) {
-    (void)hipFree(Xtmp);
+    P->free_tmp(Xtmp);
     Xtmp = nullptr;
   }
   if (e != hipSuccess) return cleanup(hip_fail(e, "frob/copy"));
@@ -370,13 +424,7 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
     if ((s = P->solver == DWD_SOLVER_DIRECT ? setup_direct(P, st) : setup_iterative(P, &pe, st)) !=
         DWD_OK)
       return cleanup(s);
-    if ((e = hipHostMalloc((void**)&P->h_flags, 4096, 0)) != hipSuccess)
-      return cleanup(hip_fail(e, "hipHostMalloc"));
-    if ((e = hipEventCreate(&P->ev_a)) != hipSuccess) return cleanup(hip_fail(e, "event"));
-    if ((e = hipEventCreate(&P->ev_b)) != hipSuccess) return cleanup(hip_fail(e, "event"));
-    for (auto& ev : P->ev_chunk)
-      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
-        return cleanup(hip_fail(e, "event"));
+    if (!arena && (e = P->host_objects()) != hipSuccess) return cleanup(hip_fail(e, "host objects"));
     P->setup_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = P;
@@ -396,7 +444,7 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
       return hip_fail(e2, "hipMalloc(Minv)");
     const int splits = csr ? 1 : gram_splits(ld, n);
     double* Gpart = nullptr;
-    if ((e2 = alloc_tmp((void**)&Gpart, std::max({nn * splits, nn, spd_inverse_work(n)}) * 8)) !=
+    if ((e2 = P->alloc_tmp((void**)&Gpart, std::max({nn * splits, nn, spd_inverse_work(n)}) * 8)) !=
         hipSuccess)
       return hip_fail(e2, "hipMalloc(Gram partials)");
     if (csr)
@@ -418,7 +466,8 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
     if (e2 == hipSuccess) e2 = hipMemcpyAsync(hv, dscal, 16, hipMemcpyDeviceToHost, st);
     if (e2 == hipSuccess) e2 = hipMemcpyAsync(&hstat, d_status, 4, hipMemcpyDeviceToHost, st);
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
-    (void)hipFree(Gpart);
+    if (e2 != hipSuccess) (void)hipStreamSynchronize(st);
+    P->free_tmp(Gpart);
     if (e2 != hipSuccess) return hip_fail(e2, "Gram/inverse");
     if (hstat != 0 || !(hv[1] > 0.0) || !std::isfinite(hv[1]))
       return fail(DWD_E_NUMERIC, "factorisation of I + Z~^T Z~/mu failed");
@@ -434,13 +483,7 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
   // Iteration buffers.
   if ((e = P->alloc_iter_buffers()) != hipSuccess) return cleanup(hip_fail(e, "iteration buffers"));
   if (csr) P->nchunks = 1;  // the sparse Z~^T pass writes one chunk
-  if ((e = hipHostMalloc((void**)&P->h_flags, 4096, 0)) != hipSuccess)
-    return cleanup(hip_fail(e, "hipHostMalloc"));
-  if ((e = hipEventCreate(&P->ev_a)) != hipSuccess) return cleanup(hip_fail(e, "event"));
-  if ((e = hipEventCreate(&P->ev_b)) != hipSuccess) return cleanup(hip_fail(e, "event"));
-  for (auto& ev : P->ev_chunk)
-    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
-      return cleanup(hip_fail(e, "event"));
+  if (!arena && (e = P->host_objects()) != hipSuccess) return cleanup(hip_fail(e, "host objects"));
   auto t1 = std::chrono::steady_clock::now();
   P->setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   *out = P;
@@ -764,23 +807,29 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
   // Final check over the data of record.  If the loop stopped on its
   // in-loop residuals but the explicit FP64 check misses the tolerance
   // (rounding drift of the n-space recurrences), resume with a fresh pass
-  // every iteration; at most twice.
+  // every iteration and a tighter in-loop target.  The solve counts as
+  // converged only when the check itself meets the tolerance.
   Scal hs;
   int resumed = 0;
+  double chk = 0.0;
   for (;;) {
     HIP_TRY(P->queue_check(c));
     HIP_TRY(hipMemcpyAsync(&hs, P->ip.sc, sizeof(Scal), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    const double chk = std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]);
+    chk = std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]);
     // (BF16 storage without refinement: the check only reports the residual
     // of the BF16 solution against the data of record.)
     const bool no_refine = P->storage == DWD_BF16 && !p->refine && !c.representer;
-    if (!hs.converged || chk < p->tol || resumed >= 2 || hs.k >= p->max_iter || no_refine) break;
+    if (!hs.converged || chk < p->tol || resumed >= kMaxResume || hs.k >= p->max_iter ||
+        no_refine)
+      break;
     ++resumed;
+    c.tol = resume_tol(c.tol, p->tol, chk);
     hipLaunchKernelGGL(k_reset_done, dim3(1), dim3(1), 0, st, P->ip.sc);
     HIP_TRY(hipGetLastError());
     HIP_TRY(P->run_loop(c, P->X_rec, P->st_rec, 1, check_every, profile, hs.k));
   }
+  const int conv = hs.converged && chk < p->tol ? 1 : 0;
   HIP_TRY(hipEventRecord(P->ev_b, st));
   std::vector<double> hw;
   const bool want_w = w || u || rho;
@@ -828,7 +877,7 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
     info->iters = hs.k;
     info->n_double = hs.n_double;
     info->newton_max = hs.newton_max;
-    info->converged = hs.converged;
+    info->converged = conv;
     info->iters_lowp = iters_lowp;
     info->setup_ms = P->setup_ms;
     info->solve_ms = ms;
@@ -837,9 +886,9 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
     info->streamT_ms = stream_ms[1];
     info->streamT_launches = launches[1];
     info->resumed = resumed;
-    info->status = hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
+    info->status = conv ? DWD_OK : DWD_NOT_CONVERGED;
   }
-  return hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
+  return conv ? DWD_OK : DWD_NOT_CONVERGED;
 }
 
 // Section 4.1: C = 10^(q+1) max{1, 10^(q-1) log(n) max{1000, d}^(1/3) / dist^(q+1)}
@@ -896,12 +945,17 @@ dwd_status suggest_C(Problem* P, double q, double* C) {
   (void)hipFree(didx);
   (void)hipFree(hist);
   if (e != hipSuccess) return hip_fail(e, "suggest_C");
+  return C_from_median_keys(P, q, k1, k2, C);
+}
+
+dwd_status C_from_median_keys(const Problem* P, double q, unsigned long long k1,
+                              unsigned long long k2, double* C) {
   double v1, v2;
   memcpy(&v1, &k1, 8);
   memcpy(&v2, &k2, 8);
   const double dist = 0.5 * (P->zscale * sqrt(v1) + P->zscale * sqrt(v2));
   if (!(dist > 0.0)) return fail(DWD_E_INVALID, "the median between-class distance is zero");
-  const double t = pow(10.0, q - 1.0) * log((double)n) *
+  const double t = pow(10.0, q - 1.0) * log((double)P->n) *
                    cbrt(std::max(1000.0, (double)P->d)) / pow(dist, q + 1.0);
   *C = pow(10.0, q + 1.0) * std::max(1.0, t);
   return DWD_OK;
@@ -942,6 +996,7 @@ void dwd_default_params(dwd_params* p) {
   p->batch_tile = 0;
   p->graph = 1;
   p->sigma_every = 2;
+  p->psqmr_max = 50;
 }
 
 dwd_status dwd_setup(const dwd_matrix* X, const double* y, const dwd_params* p, void* stream,
@@ -1013,6 +1068,16 @@ dwd_status dwd_inspect(dwd_problem H, const char* what, double* out, int64_t cou
   Problem* P = H->P;
   const std::string w(what);
   const int64_t nn = (int64_t)P->n * P->n;
+  if (w == "psqmr_count") {
+    if (count != 1) return fail(DWD_E_INVALID, "count must be 1");
+    out[0] = (double)P->psqmr_log.size();
+    return DWD_OK;
+  }
+  if (w == "psqmr_steps") {
+    if (count != (int64_t)P->psqmr_log.size()) return fail(DWD_E_INVALID, "wrong count");
+    for (int64_t j = 0; j < count; ++j) out[j] = (double)P->psqmr_log[j];
+    return DWD_OK;
+  }
   if (w == "zscale" || w == "ymy" || w == "solver" || w == "ell") {
     if (count != 1) return fail(DWD_E_INVALID, "count must be 1");
     out[0] = w == "zscale" ? P->zscale

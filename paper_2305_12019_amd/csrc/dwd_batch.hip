@@ -420,9 +420,10 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   for (int j = 0; j < B; ++j) all[j] = j;
   if ((rs = check(all.data(), B)) != DWD_OK) return rs;
   // Problems that stopped on their in-loop residuals but miss the tolerance
-  // in the FP64 check continue with FP64 products (at most twice).
+  // in the FP64 check continue with FP64 products and a tighter in-loop
+  // target; a problem counts as converged only when its check meets tol.
   std::vector<int> resumed(B, 0);
-  for (int round = 0; round < 2; ++round) {
+  for (int round = 0; round < kMaxResume; ++round) {
     std::vector<int> again;
     int left = 0;
     for (int j = 0; j < B; ++j) {
@@ -431,9 +432,11 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
       if (hs.converged && chk >= p[j].tol && hs.k < p[j].max_iter) {
         again.push_back(j);
         left = std::max(left, p[j].max_iter - hs.k);
+        hcs[j].tol = resume_tol(hcs[j].tol, p[j].tol, chk);
       }
     }
     if (again.empty()) break;
+    HIP_TRY_B(hipMemcpyAsync(dcs, hcs, (size_t)B * sizeof(Consts), hipMemcpyHostToDevice, st));
     for (size_t i = 0; i < again.size(); ++i) {
       hidx[1 - cur][i] = again[i];
       resumed[again[i]] += 1;
@@ -470,7 +473,9 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   bool all_conv = true;
   for (int j = 0; j < B; ++j) {
     const Scal& hs = hsc[0][j];
-    all_conv = all_conv && hs.converged;
+    const int conv =
+        hs.converged && std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]) < p[j].tol ? 1 : 0;
+    all_conv = all_conv && conv;
     if (info) {
       dwd_info& in = info[j];
       memset(&in, 0, sizeof(in));
@@ -488,10 +493,10 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
       in.iters = hs.k;
       in.n_double = hs.n_double;
       in.newton_max = hs.newton_max;
-      in.converged = hs.converged;
+      in.converged = conv;
       in.setup_ms = P->setup_ms;
       in.solve_ms = ms;
-      in.status = hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
+      in.status = conv ? DWD_OK : DWD_NOT_CONVERGED;
       in.resumed = resumed[j];
       in.stream_ms = pass_ms;  // all pass launches of the batch
       in.stream_launches = (int32_t)(pev.size() / 2);

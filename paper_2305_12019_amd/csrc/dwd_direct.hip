@@ -24,10 +24,13 @@ int64_t direct_ld(int64_t d) { return (d + 15) / 16 * 16; }
 int resolve_solver(const dwd_params* p, const dwd_matrix* X) {
   if (p->solver == DWD_SOLVER_DIRECT || p->solver == DWD_SOLVER_ITERATIVE) return p->solver;
   if (p->solver != DWD_SOLVER_AUTO) return DWD_SOLVER_SMW;
+  // the choice printed with the paper's pseudo-code; sparse input and BF16
+  // storage are taken by the SMW form only
   const bool dense = X->layout == DWD_DENSE && p->storage != DWD_BF16;
-  if (X->d <= 5000 && dense) return DWD_SOLVER_DIRECT;
-  if (X->n > 65536 && dense) return DWD_SOLVER_ITERATIVE;
-  return DWD_SOLVER_SMW;
+  if (!dense) return DWD_SOLVER_SMW;
+  if (X->d <= 5000) return DWD_SOLVER_DIRECT;
+  if ((double)X->n < 0.2 * (double)X->d && X->n <= 2500) return DWD_SOLVER_SMW;
+  return DWD_SOLVER_ITERATIVE;
 }
 
 struct DirSizes {
@@ -110,7 +113,7 @@ dwd_status setup_direct(Problem* P, hipStream_t st) {
   HIP_TRY_D(launch_dir_reduce(c, dp, 0, 1, 1.0 / P->zscale, st));
   // A = [[Z~ Z~^T + mu I, Z~ y], [(Z~ y)^T, n]], then A^-1 in place
   double* tmp = nullptr;
-  HIP_TRY_D(hipMalloc((void**)&tmp, std::max<size_t>(z.factor_tmp, 1) * 8));
+  HIP_TRY_D(P->alloc_tmp((void**)&tmp, std::max<size_t>(z.factor_tmp, 1) * 8));
   hipError_t e = launch_fgram(P->X_rec, P->st_rec, ld, n, (int)d, tmp, z.splits, st);
   if (e == hipSuccess)
     e = launch_fgram_finish(tmp, z.splits, (int)d, n, dp.zz, 1.0 / (P->zscale * P->zscale),
@@ -121,7 +124,8 @@ dwd_status setup_direct(Problem* P, hipStream_t st) {
   int hstat = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&hstat, d_status, 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(tmp);
+  if (e != hipSuccess) (void)hipStreamSynchronize(st);
+  P->free_tmp(tmp);
   if (e != hipSuccess) return hip_fail(e, "direct factor");
   if (hstat != 0) return fail(DWD_E_NUMERIC, "factorisation of the (d+1)^2 matrix failed");
   return DWD_OK;
@@ -190,6 +194,10 @@ dwd_status solve_direct(Problem* P, const dwd_params* p, double* w, dwd_info* in
   if (alpha) HIP_TRY_D(hipMemcpy(alpha, dp.alpha, (size_t)P->n * 8, hipMemcpyDeviceToHost));
   if (r) HIP_TRY_D(hipMemcpy(r, dp.r, (size_t)P->n * 8, hipMemcpyDeviceToHost));
   if (xi) HIP_TRY_D(hipMemcpy(xi, dp.xi, (size_t)P->n * 8, hipMemcpyDeviceToHost));
+  // (the residuals of this branch come from explicit products, so the
+  // check values are the in-loop ones; the rule is the same as elsewhere)
+  const int conv =
+      hs.converged && std::max(hs.eta[E_PCHK], hs.eta[E_DCHK]) < p->tol ? 1 : 0;
   float ms = 0.0f;
   HIP_TRY_D(hipEventElapsedTime(&ms, P->ev_a, P->ev_b));
   if (info) {
@@ -208,12 +216,12 @@ dwd_status solve_direct(Problem* P, const dwd_params* p, double* w, dwd_info* in
     info->iters = hs.k;
     info->n_double = hs.n_double;
     info->newton_max = hs.newton_max;
-    info->converged = hs.converged;
+    info->converged = conv;
     info->setup_ms = P->setup_ms;
     info->solve_ms = ms;
-    info->status = hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
+    info->status = conv ? DWD_OK : DWD_NOT_CONVERGED;
   }
-  return hs.converged ? DWD_OK : DWD_NOT_CONVERGED;
+  return conv ? DWD_OK : DWD_NOT_CONVERGED;
 }
 
 }  // namespace dwd

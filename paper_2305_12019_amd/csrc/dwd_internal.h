@@ -140,6 +140,19 @@ struct BatchPtrs {
   int64_t ld;
 };
 
+// Serving: one problem's entry in the table that the multi-problem
+// kernels index by blockIdx.y (blockIdx.x stays the block index inside the
+// problem, so each problem runs exactly the blocks of its own launch).
+struct StepDesc {
+  Consts c;
+  IterPtrs p;
+  const void* X;   // data the pass streams (dense)
+  int npass;       // blocks of this problem's pass (or element step); the tail's nblk_d
+  int nrow;        // ngemv_blocks(n)
+};
+
+enum MultiKernel { MULTI_STEP1AB = 0, MULTI_STEP1C, MULTI_REP, MULTI_PASS, MULTI_TAIL };
+
 // Direct branch (Section 3.3.1): pointers of one problem's iteration state.
 // d-vectors have length ld (ld + 1 for wbar and h, whose last entry is the
 // beta component); zz holds [Z~ dr | Z~ (xi - r) | Z~ alpha], each ld long.

@@ -20,6 +20,10 @@ hipError_t launch_ngemv(int n, const double* A1, const double* x1, double* o1, c
                         const double* x2, double* o2, const double* wdot, double* part,
                         const Scal* sc, hipStream_t st);
 hipError_t launch_step1ab(const Consts& c, const IterPtrs& p, hipStream_t st);
+// Multi-problem launches over a device table of count StepDesc entries;
+// gx = the largest block count among them (the pass: per storage type).
+hipError_t launch_multi(int what, const StepDesc* D, int count, int gx, int storage,
+                        hipStream_t st);
 hipError_t launch_step1c_rows(const Consts& c, const IterPtrs& p, hipStream_t st);
 hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterPtrs& p,
                         hipStream_t st);
@@ -62,8 +66,19 @@ hipError_t launch_expand3(const void* X, int storage, const Consts& c, const dou
 hipError_t launch_csr_expand(const int64_t* ip, const int32_t* ix, const void* val, int dtype,
                              int64_t d, const Consts& c, const IterPtrs& p, hipStream_t st);
 
+// A device memory pool that a problem's buffers are taken from instead of
+// hipMalloc (serving: one allocation up front, so that admitting and
+// finishing requests neither allocates nor frees device memory, which would
+// synchronise the device).  take() returns nullptr when no block fits.
+struct DeviceArena {
+  virtual void* take(size_t bytes) = 0;
+  virtual void give(void* ptr) = 0;
+  virtual ~DeviceArena() {}
+};
+
 struct Problem {
   int device = 0;
+  DeviceArena* arena = nullptr;  // buffers from this pool (serving), else hipMalloc
   hipStream_t stream = nullptr;
   int64_t d = 0, ld = 0;
   int n = 0;
@@ -80,6 +95,9 @@ struct Problem {
   double* Ainv = nullptr;      // direct: inverse of the (d+1)^2 eq-linsys matrix
   DirPtrs dp{};                // direct: iteration state
   ItPtrs ipt{};                // iterative: iteration state
+  PqPtrs pq{};                 // iterative: PSQMR state
+  std::vector<int> psqmr_log;  // iterative: steps of each PSQMR solve of the last solve
+  int psqmr_switch = -1;       // iterative: iteration at which eq-T was switched on
   double* y = nullptr;
   double* e = nullptr;         // penalty weights of eq-primal (n)
   bool e_ones = true;          // e currently holds all ones
@@ -118,6 +136,11 @@ struct Problem {
   int csr_dtype = DWD_FP32;
 
   hipError_t alloc(void** ptr, size_t bytes);
+  // set-up scratch released before set-up returns (from the arena if any)
+  hipError_t alloc_tmp(void** ptr, size_t bytes);
+  void free_tmp(void* ptr);
+  std::vector<void*> tmp_from_arena;
+  hipError_t host_objects();
   hipError_t alloc_iter_buffers();
   // Load the penalty weights e of eq-primal for the next solve (host array
   // of n values, validated by the caller; NULL = all ones).
@@ -149,11 +172,29 @@ Consts make_consts(const Problem* P, const dwd_params* p);
 // Constants of the BF16 phase: its own y^T M^-1 y and the looser tolerance.
 Consts lowp_consts(const Problem* P, const dwd_params* p);
 double default_sigma0(const dwd_params* p, int n);
+// The final FP64 check (Section 4.3 eta_P and eta_D recomputed over the data
+// of record) decides convergence.  When the loop stopped on its in-loop
+// residuals but the check reads chk >= tol, the loop resumes with its
+// primal-dual target shrunk by the factor the check missed by (with margin);
+// at most kMaxResume times.
+constexpr int kMaxResume = 3;
+inline double resume_tol(double cur, double tol, double chk) {
+  const double f = 0.7 * tol / chk;
+  return cur * (f < 0.05 ? 0.05 : (f > 0.5 ? 0.5 : f));
+}
 int64_t padded_ld(int64_t d);
 int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz);
+// With an arena (serving) every device buffer comes from it, and the
+// host-side completion flags and timing events of dwd_solve are not made.
 dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params* p,
-                         hipStream_t st, Problem** out);
+                         hipStream_t st, Problem** out, DeviceArena* arena = nullptr);
+// Release every resource of P (buffers back to its arena or hipFree) and delete it.
+void destroy_problem(Problem* P);
 dwd_status suggest_C(Problem* P, double q, double* C);
+// The Section 4.1 formula from the bit patterns of the two middle squared
+// distances (equal for an odd count).
+dwd_status C_from_median_keys(const Problem* P, double q, unsigned long long k1,
+                              unsigned long long k2, double* C);
 // Direct branch (dwd_direct.hip): the factor and buffers after the data are
 // staged (Z_scale known), and the solve loop.
 constexpr int64_t kDirectMaxD = 5120;

@@ -382,17 +382,12 @@ __global__ void __launch_bounds__(256) k_plan_b(BatchPtrs P, const int* __restri
 // rho -= tau sigma sqrt(mu)(w - u), and per-problem block partials (NP2
 // layout of the single pass; the two Z~ alpha entries are 0 here: the batched
 // tail gets them in n-space).  Block tile: 128 rows x 16 NB slots, 4 waves,
-// wave w owns rows 32w..32w+31; the next K tile is loaded into registers
-// while the current one is multiplied.  (Three 128-row blocks fit on a CU,
-// so the 784 blocks of d=1e5 finish in about one round; 256-row blocks ran
-// one per CU in two uneven rounds and were 6% slower, 15% with FP64
-// products.)  Every output element is the same
-// sequence of MFMA steps over k whatever NB is, so the tile width (chosen by
-// the host's tuner) does not change any result.
+// wave w owns rows 32w..32w+31.  Every output element is the same sequence
+// of MFMA steps over k whatever NB is, so the tile width (chosen by the
+// host's tuner) does not change any result.
 // ---------------------------------------------------------------------------
-constexpr int BT_M = 128, BT_K = 16, BT_T = 256;
+constexpr int BT_M = 128, BT_T = 256;
 static_assert(BT_M == 32 * (BT_T / 64), "each wave owns 32 rows of the tile");
-constexpr int BT_SEG = BT_M / 4;       // four-element row segments per k
 constexpr int BT_LPP = BT_T / 16;      // epilogue lanes per problem of a 16-problem group
 
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -418,97 +413,74 @@ struct MfmaB<double> {
   __device__ static __forceinline__ int row(int l, int v) { return 4 * v + (l >> 4); }
 };
 
-// Global loads of one K tile into registers: A is 256 rows x BT_K columns of
-// X (BT_K / 8 four-element row segments per thread), B is BT_K x 16 NB of SB.
-constexpr int BT_AH = BT_K * BT_M / 4 / BT_T;  // A row segments per thread
-static_assert(BT_AH * 4 * BT_T == BT_K * BT_M, "the A tile must split evenly over the block");
-template <typename TD, int NB>
-struct TileRegs {
-  static constexpr int NBL = (BT_K * 16 * NB + BT_T - 1) / BT_T;  // B elements per thread
-  TD a[BT_AH][4];
-  double b[NBL];
+// The A operand comes straight from global memory into the MFMA registers.
+// In the 16x16x4 products lane l supplies row l % 16 and inner index l / 16;
+// here lane l loads the two consecutive rows 2 (l % 16) + {0, 1} of sample
+// k0 + l / 16 (one 8- or 16-byte load; 16 lanes cover 32 contiguous rows of
+// a sample), and component j feeds the product whose 16 output rows are
+// {2 i + j}.  So the wave owns 32 rows, the block (four waves) 128 rows, and
+// A never passes through LDS.  B (the BK x 16 NB slice of SB, shared by
+// the four waves) is staged in LDS, double-buffered: one barrier per K tile.
+// The A tile of the next K tile is loaded into registers while the current
+// one is multiplied.
+constexpr int BK = 32;                 // inner (sample) dimension per K tile
+constexpr int BK_STEPS = BK / 4;       // MFMA k-steps per K tile
+
+template <typename TD>
+struct ARow;
+template <>
+struct ARow<float> {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  __device__ static __forceinline__ void load(const float* p, float& a0, float& a1) {
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    a0 = v.x;
+    a1 = v.y;
+  }
+};
+template <>
+struct ARow<double> {
+  __device__ static __forceinline__ void load(const double* p, double& a0, double& a1) {
+    const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    a0 = v.x;
+    a1 = v.y;
+  }
 };
 
-template <typename TD, int NB>
-__device__ __forceinline__ void tile_load(const TD* __restrict__ X, const double* __restrict__ SB,
-                                          int64_t ld, int n, int64_t m0, int k0, int bact_tile,
-                                          TileRegs<TD, NB>& R) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int h = 0; h < BT_AH; ++h) {
-    const int e = tid + h * BT_T;
-    const int kk = e / BT_SEG, r4 = (e % BT_SEG) * 4;
-    const int k = k0 + kk;
-    if (k < n) {
-      const TD* src = X + (int64_t)k * ld + m0 + r4;
-      if constexpr (sizeof(TD) == 4) {
-        const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(src));
-        R.a[h][0] = v.x;
-        R.a[h][1] = v.y;
-        R.a[h][2] = v.z;
-        R.a[h][3] = v.w;
-      } else {
-        const nt_d2 v0 = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(src));
-        const nt_d2 v1 = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(src + 2));
-        R.a[h][0] = v0.x;
-        R.a[h][1] = v0.y;
-        R.a[h][2] = v1.x;
-        R.a[h][3] = v1.y;
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) R.a[h][q] = (TD)0;
-    }
-  }
-#pragma unroll
-  for (int h = 0; h < TileRegs<TD, NB>::NBL; ++h) {
-    // B: slot j = e / BT_K, kk = e % BT_K (BT_K consecutive k of one slot)
-    const int e = tid + h * BT_T;
-    const int j = e / BT_K, kb = e % BT_K;
-    const int kq = k0 + kb;
-    R.b[h] = (e < BT_K * 16 * NB && j < bact_tile && kq < n) ? SB[(size_t)j * n + kq] : 0.0;
-  }
+// Row (within the wave's 32) of output register v of lane l for component j.
+template <typename T>
+__device__ __forceinline__ int pass_b_row(int l, int v, int j) {
+  return 2 * MfmaB<T>::row(l, v) + j;
 }
 
-template <typename TD, typename T, int NB>
-__device__ __forceinline__ void tile_store(const TileRegs<TD, NB>& R, T (*As)[BT_M + 4],
-                                           T (*Bs)[16 * NB + 4]) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int h = 0; h < BT_AH; ++h) {
-    const int e = tid + h * BT_T;
-    const int kk = e / BT_SEG, r4 = (e % BT_SEG) * 4;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) As[kk][r4 + q] = (T)R.a[h][q];
-  }
-#pragma unroll
-  for (int h = 0; h < TileRegs<TD, NB>::NBL; ++h) {
-    const int e = tid + h * BT_T;
-    if (e < BT_K * 16 * NB) Bs[e % BT_K][e / BT_K] = (T)R.b[h];
-  }
+// LDS row stride of the B tile (elements): rows l / 16 = 0, 1 of a half-wave
+// land in different bank halves.
+template <int NB>
+constexpr int pass_b_bstride() {
+  return 16 * NB + (NB % 2 ? 32 : 16);
 }
 
 // FP64 products (T = double) accumulate in the MFMA registers over the whole
 // inner dimension; FP32 products (T = float) are summed per K tile and the
 // tile sums added in FP64.
 template <typename TD, typename T, int NB>
-__global__ void __launch_bounds__(BT_T) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 : 4)))
-k_pass_b(const TD* __restrict__ X, BatchPtrs P,
-                                                 const int* __restrict__ idx, int bact) {
+__global__ void __launch_bounds__(BT_T) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 2 : 3)))
+k_pass_b(const TD* __restrict__ X, BatchPtrs P, const int* __restrict__ idx, int bact) {
   typedef typename MfmaB<T>::acc_t acc_t;
   constexpr int BN = 16 * NB;
+  constexpr int BS = pass_b_bstride<NB>();
   constexpr bool F64 = sizeof(T) == 8;
-  __shared__ T As[BT_K][BT_M + 4];
-  __shared__ T Bs[BT_K][BN + 4];
+  __shared__ T Bs[2][BK][BS];
   __shared__ double Tz[16][BT_M + 1];
   __shared__ int s_p[BN];
   __shared__ int s_live[BN];
   __shared__ double s_sig[BN], s_gam[BN], s_tau[BN];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const int64_t m0 = (int64_t)blockIdx.x * BT_M;
   const int slot0 = blockIdx.y * BN;
   const int bact_tile = min(BN, bact - slot0);
   const int n = P.n;
+  const int64_t ld = P.ld;
   const double* SB = P.SB + (size_t)slot0 * n;
   if (tid < BN) {
     const int slot = slot0 + tid;
@@ -526,64 +498,107 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P,
       s_tau[tid] = P.cs[p].tau;
     }
   }
+  // this lane's two rows of the wave's 32, in sample k0 + lk of each step
+  const TD* xa = X + m0 + wid * 32 + 2 * li + (int64_t)lk * ld;
+  auto load_a = [&](int k0, TD (&a)[BK_STEPS][2]) {
+#pragma unroll
+    for (int s = 0; s < BK_STEPS; ++s) {
+      const int k = k0 + 4 * s + lk;
+      if (k < n) {
+        ARow<TD>::load(xa + (int64_t)(k0 + 4 * s) * ld, a[s][0], a[s][1]);
+      } else {
+        a[s][0] = (TD)0;
+        a[s][1] = (TD)0;
+      }
+    }
+  };
+  // B tile: element e = slot j * BK + kk (BK consecutive samples per slot)
+  constexpr int BE = (BK * BN + BT_T - 1) / BT_T;
+  auto load_b = [&](int k0, double (&b)[BE]) {
+#pragma unroll
+    for (int h = 0; h < BE; ++h) {
+      const int e = tid + h * BT_T;
+      const int j = e / BK, kk = e % BK;
+      b[h] = (e < BK * BN && j < bact_tile && k0 + kk < n) ? SB[(size_t)j * n + k0 + kk] : 0.0;
+    }
+  };
+  auto store_b = [&](int buf, const double (&b)[BE]) {
+#pragma unroll
+    for (int h = 0; h < BE; ++h) {
+      const int e = tid + h * BT_T;
+      if (e < BK * BN) Bs[buf][e % BK][e / BK] = (T)b[h];
+    }
+  };
   acc_t acc[2][NB];
   double acc64[F64 ? 1 : 2][F64 ? 1 : NB][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int j = 0; j < 2; ++j)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[a][b][v] = (T)0;
+      for (int v = 0; v < 4; ++v) acc[j][b][v] = (T)0;
   if constexpr (!F64) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc64[a][b][v] = 0.0;
+        for (int v = 0; v < 4; ++v) acc64[j][b][v] = 0.0;
   }
-  // Two K tiles in flight in registers while the staged one is multiplied.
-  TileRegs<TD, NB> R0, R1;
-  tile_load<TD, NB>(X, SB, P.ld, n, m0, 0, bact_tile, R0);
-  if (BT_K < n) tile_load<TD, NB>(X, SB, P.ld, n, m0, BT_K, bact_tile, R1);
-  auto step = [&](TileRegs<TD, NB>& R, int k0) {
-    tile_store<TD, T, NB>(R, As, Bs);
-    __syncthreads();
-    if (k0 + 2 * BT_K < n) tile_load<TD, NB>(X, SB, P.ld, n, m0, k0 + 2 * BT_K, bact_tile, R);
-    if constexpr (!F64) {
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[a][b][v] = (T)0;
-    }
-#pragma unroll
-    for (int ks = 0; ks < BT_K; ks += 4) {
-      const int li = lane & 15, lk = lane >> 4;
-      T av[2], bv[NB];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[ks + lk][wid * 32 + a * 16 + li];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) bv[b] = Bs[ks + lk][b * 16 + li];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = MfmaB<T>::op(av[a], bv[b], acc[a][b]);
+  TD a_cur[BK_STEPS][2], a_nxt[BK_STEPS][2];
+  double bnext[BE];
+  load_a(0, a_cur);
+  load_b(0, bnext);
+  store_b(0, bnext);
+  __syncthreads();
+  const int ntile = (n + BK - 1) / BK;
+  for (int t = 0; t < ntile; ++t) {
+    const int k0 = t * BK;
+    const int buf = t & 1;
+    const bool more = t + 1 < ntile;
+    if (more) {
+      load_a(k0 + BK, a_nxt);
+      load_b(k0 + BK, bnext);
     }
     if constexpr (!F64) {
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc64[a][b][v] += (double)acc[a][b][v];
+          for (int v = 0; v < 4; ++v) acc[j][b][v] = (T)0;
     }
+#pragma unroll
+    for (int s = 0; s < BK_STEPS; ++s) {
+      T bv[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[b] = Bs[buf][4 * s + lk][b * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const T av = (T)a_cur[s][j];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[j][b] = MfmaB<T>::op(av, bv[b], acc[j][b]);
+      }
+    }
+    if constexpr (!F64) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc64[j][b][v] += (double)acc[j][b][v];
+    }
+    if (more) {
+      store_b(buf ^ 1, bnext);
+#pragma unroll
+      for (int s = 0; s < BK_STEPS; ++s) {
+        a_cur[s][0] = a_nxt[s][0];
+        a_cur[s][1] = a_nxt[s][1];
+      }
+    }
+    // the next tile's B is visible, and nobody reads this tile's buffer
+    // after it is rewritten two tiles on
     __syncthreads();
-  };
-  for (int k0 = 0; k0 < n; k0 += 2 * BT_K) {
-    step(R0, k0);
-    if (k0 + BT_K < n) step(R1, k0 + BT_K);
   }
   const double mu = P.cs[s_p[0] >= 0 ? s_p[0] : 0].mu;
   const double sqmu = sqrt(mu);
@@ -596,25 +611,25 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P,
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double zs;
         if constexpr (F64)
-          zs = acc[a][b][v];
+          zs = acc[j][b][v];
         else
-          zs = acc64[a][b][v];
-        Tz[lane & 15][wid * 32 + a * 16 + MfmaB<T>::row(lane, v)] = zs;
+          zs = acc64[j][b][v];
+        Tz[li][wid * 32 + pass_b_row<T>(lane, v, j)] = zs;
       }
     __syncthreads();
-    const int j = b * 16 + ej;
-    const int p = s_p[j];
-    const bool live = s_live[j] != 0;
+    const int jj = b * 16 + ej;
+    const int p = s_p[jj];
+    const bool live = s_live[jj] != 0;
     double pw[NP2] = {0, 0, 0, 0, 0, 0};
     if (live) {
-      const double sigma = s_sig[j], gamma = s_gam[j];
+      const double sigma = s_sig[jj], gamma = s_gam[jj];
       const double br = sqmu / sigma, gr = 1.0 / (sigma * sqmu);
-      const double rs = s_tau[j] * sigma * sqmu;
+      const double rs = s_tau[jj] * sigma * sqmu;
       const size_t od = (size_t)p * P.ld + m0;
 #pragma unroll
       for (int i = 0; i < BT_M / BT_LPP; ++i) {

@@ -383,20 +383,31 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
 #pragma unroll
   for (int j = 0; j < KS; ++j) ssum[j] = 0.0;
   __shared__ double lds_red[4];
-  for (int ib = i0; ib < i1; ib += G) {
-    const int i = ib + g;
-    const bool live = i < i1;
-    T xv[NF][4];
+  // the group's next sample is loaded while the current one is processed
+  // (its dot product, the Step 1b-3 scalar work and the accumulation)
+  auto load_sample = [&](int i, T (&xv)[NF][4]) {
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
       const int64_t f = 4 * (int64_t)(lg + j * TPS);
-      if (live && f < ld) {
+      if (i < i1 && f < ld) {
         Quad<T>::load(X + (int64_t)i * ld + f, xv[j]);
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q) xv[j][q] = (T)0;
       }
     }
+  };
+  T xnext[NF][4];
+  load_sample(i0 + g, xnext);
+  for (int ib = i0; ib < i1; ib += G) {
+    const int i = ib + g;
+    const bool live = i < i1;
+    T xv[NF][4];
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xv[j][q] = xnext[j][q];
+    load_sample(i + G, xnext);
     double cf0 = 1.0, cf1 = 0.0;
     if constexpr (MODE != 0) {
       double dot = 0.0;

@@ -259,7 +259,7 @@ hipError_t launch_ngemv(int n, const double* A1, const double* x1, double* o1, c
 // c = v_bar + xi - alpha/sigma, r^{k+1}_i = prox(c_i), dr = r^{k+1} - r^k.
 // Block partials: y^T dr and the most Newton steps.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_step1ab(Consts c, IterPtrs p) {
+__device__ __forceinline__ void step1ab_body(const Consts& c, const IterPtrs& p) {
   Scal* sc = p.sc;
   // (the stop flag, uniform over the launch, is tested once the first loads
   // are in flight; nothing is written before the test)
@@ -315,6 +315,8 @@ __global__ void __launch_bounds__(256) k_step1ab(Consts c, IterPtrs p) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_step1ab(Consts c, IterPtrs p) { step1ab_body(c, p); }
+
 hipError_t launch_step1ab(const Consts& c, const IterPtrs& p, hipStream_t st) {
   hipLaunchKernelGGL(k_step1ab, dim3(ngemv_blocks(c.n)), dim3(256), 0, st, c, p);
   return hipGetLastError();
@@ -337,7 +339,7 @@ hipError_t launch_step1ab(const Consts& c, const IterPtrs& p, hipStream_t st) {
 // The consumers take the decision from the same fixed-order sums.
 // part_c[b*NPC + 0] = block sum of dr_i (G~ dr)_i; [1 + o*NPO + j] outcome o.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_step1c_rows(Consts c, IterPtrs p) {
+__device__ __forceinline__ void step1c_body(const Consts& c, const IterPtrs& p) {
   Scal* sc = p.sc;
   const int done = sc->done;  // tested after the first loads (see k_step1ab)
   __shared__ double wsum[4][NPC];
@@ -417,6 +419,8 @@ __global__ void __launch_bounds__(256) k_step1c_rows(Consts c, IterPtrs p) {
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->beta1 = beta1;
 }
 
+__global__ void __launch_bounds__(256) k_step1c_rows(Consts c, IterPtrs p) { step1c_body(c, p); }
+
 hipError_t launch_step1c_rows(const Consts& c, const IterPtrs& p, hipStream_t st) {
   hipLaunchKernelGGL(k_step1c_rows, dim3(ngemv_blocks(c.n)), dim3(256), 0, st, c, p);
   return hipGetLastError();
@@ -438,8 +442,8 @@ constexpr int PANEL = 2048;
 // for the data the pass streams: the data of record with its factor, or the
 // BF16 image with the factor of the BF16 image (BF16 phase).
 template <typename T, int NW>
-__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2)))
-k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
+__device__ __forceinline__ void pass2_body(const T* __restrict__ X, const Consts& c,
+                                           const IterPtrs& p) {
   // The stop flag is tested after the prologue's loads are issued (nothing
   // is written before the test), so its round trip overlaps theirs.
   const int done = p.sc->done;
@@ -603,6 +607,12 @@ k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
   if (threadIdx.x < NP2) p.part_g[(size_t)blockIdx.x * NP2 + threadIdx.x] = acc[threadIdx.x];
 }
 
+template <typename T, int NW>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2)))
+k_pass2(const T* __restrict__ X, Consts c, IterPtrs p) {
+  pass2_body<T, NW>(X, c, p);
+}
+
 // Blocks of the pass: 64 V rows each (V = 2, 4, 8 for FP64, FP32, BF16).
 int pass2_blocks(int storage, int64_t ld) {
   const int rows = storage == DWD_FP64 ? 128 : (storage == DWD_FP32 ? 256 : 512);
@@ -639,7 +649,7 @@ hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterP
 // G~ alpha' (for ||Z~ alpha'|| and ||Z~ alpha' + D rho'||).  One wave per
 // row; the block partials have the layout of the pass's (NP2).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_rep_step(Consts c, IterPtrs p) {
+__device__ __forceinline__ void rep_step_body(const Consts& c, const IterPtrs& p) {
   Scal* sc = p.sc;
   const int done = sc->done;  // tested after the plan's loads (see k_step1ab)
   const Step2Plan pl = step2_plan<256>(c, p);
@@ -719,6 +729,8 @@ __global__ void __launch_bounds__(256) k_rep_step(Consts c, IterPtrs p) {
     p.part_g[(size_t)blockIdx.x * NP2 + j] = (ws[0][j] + ws[1][j]) + (ws[2][j] + ws[3][j]);
   }
 }
+
+__global__ void __launch_bounds__(256) k_rep_step(Consts c, IterPtrs p) { rep_step_body(c, p); }
 
 hipError_t launch_rep_step(const Consts& c, const IterPtrs& p, hipStream_t st) {
   if (!iter_ptrs_ok(p)) return hipErrorInvalidValue;
@@ -876,7 +888,7 @@ __device__ __forceinline__ double tail_lane_sum(const double* __restrict__ src, 
 // sc->gamma).  Every load the tail needs before its scalar work is requested
 // in one round: both outcomes' sums, the pass partials, and both outcomes of
 // this thread's first TAIL_PRE rows; the outcome is picked afterwards.
-__global__ void __launch_bounds__(NTT) k_tail(Consts c, IterPtrs p, int nblk_d) {
+__device__ __forceinline__ void tail_body(const Consts& c, const IterPtrs& p, int nblk_d) {
   Scal* sc = p.sc;
   if (sc->done) return;
   __shared__ double s_sigma;
@@ -998,6 +1010,10 @@ __global__ void __launch_bounds__(NTT) k_tail(Consts c, IterPtrs p, int nblk_d) 
   const double* vs = o ? p.v1 : p.v;
   for (int i = threadIdx.x + TAIL_PRE * NTT; i < c.n; i += NTT)
     commit(i, p.rn[i], xs[i], as[i], vs[i], p.s1[i], p.y[i], p.Prho[i]);
+}
+
+__global__ void __launch_bounds__(NTT) k_tail(Consts c, IterPtrs p, int nblk_d) {
+  tail_body(c, p, nblk_d);
 }
 
 hipError_t launch_tail(const Consts& c, const IterPtrs& p, int nblk_d, hipStream_t st) {
@@ -1132,6 +1148,68 @@ __global__ void __launch_bounds__(1024) k_norm2(const double* __restrict__ v, in
 
 hipError_t launch_norm2(const double* v, int64_t m, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, st, v, m, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Multi-problem forms for serving: one launch steps every problem of a
+// descriptor table (grid.y = table entries, grid.x = the largest problem's
+// block count; blocks beyond a problem's own count return at once).  They
+// run the same device code as the single-problem kernels.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_step1ab_m(const StepDesc* __restrict__ D) {
+  const StepDesc* s = D + blockIdx.y;
+  if ((int)blockIdx.x >= s->nrow) return;
+  step1ab_body(s->c, s->p);
+}
+
+__global__ void __launch_bounds__(256) k_step1c_m(const StepDesc* __restrict__ D) {
+  const StepDesc* s = D + blockIdx.y;
+  if ((int)blockIdx.x >= s->nrow) return;
+  step1c_body(s->c, s->p);
+}
+
+__global__ void __launch_bounds__(256) k_rep_step_m(const StepDesc* __restrict__ D) {
+  const StepDesc* s = D + blockIdx.y;
+  if ((int)blockIdx.x >= s->nrow) return;
+  rep_step_body(s->c, s->p);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_pass2_m(const StepDesc* __restrict__ D) {
+  const StepDesc* s = D + blockIdx.y;
+  if ((int)blockIdx.x >= s->npass) return;
+  pass2_body<T, 4>((const T*)s->X, s->c, s->p);
+}
+
+__global__ void __launch_bounds__(NTT) k_tail_m(const StepDesc* __restrict__ D) {
+  const StepDesc* s = D + blockIdx.y;
+  tail_body(s->c, s->p, s->npass);
+}
+
+hipError_t launch_multi(int what, const StepDesc* D, int count, int gx, int storage,
+                        hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (count > 65535 || gx < 1) return hipErrorInvalidValue;
+  const dim3 g((unsigned)gx, (unsigned)count);
+  switch (what) {
+    case MULTI_STEP1AB: hipLaunchKernelGGL(k_step1ab_m, g, dim3(256), 0, st, D); break;
+    case MULTI_STEP1C: hipLaunchKernelGGL(k_step1c_m, g, dim3(256), 0, st, D); break;
+    case MULTI_REP: hipLaunchKernelGGL(k_rep_step_m, g, dim3(256), 0, st, D); break;
+    case MULTI_TAIL:
+      hipLaunchKernelGGL(k_tail_m, dim3(1, (unsigned)count), dim3(NTT), 0, st, D);
+      break;
+    case MULTI_PASS:
+      if (storage == DWD_FP64)
+        hipLaunchKernelGGL(k_pass2_m<double>, g, dim3(256), 0, st, D);
+      else if (storage == DWD_FP32)
+        hipLaunchKernelGGL(k_pass2_m<float>, g, dim3(256), 0, st, D);
+      else
+        hipLaunchKernelGGL(k_pass2_m<uint16_t>, g, dim3(256), 0, st, D);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

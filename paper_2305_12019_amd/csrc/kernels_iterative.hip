@@ -177,27 +177,32 @@ hipError_t launch_it_dots(const Consts& c, const ItPtrs& p, const double* x, con
 //   T w^k = lam_ell w + sum_{j<ell} (lam_j - lam_ell) (v_j^T w) v_j - Z~ Z~^T w.
 // (h_beta = -y^T t is kept in sca[IS_HB] by the tail.)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_it_rhs(Consts c, ItPtrs p) {
+// (with_T = 0: the right-hand side of eq-linsys itself, for the PSQMR solves)
+__global__ void __launch_bounds__(256) k_it_rhs(Consts c, ItPtrs p, int with_T) {
   Scal* sc = p.sc;
   const int done = sc->done;
   const double sigma = sc->sigma;
   const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (done || f >= c.ld) return;
-  const int L = p.ell;
-  const double lamL = p.lam[L - 1];
-  const double* dw = p.dots + (size_t)ID_W * DSTRIDE;
   const double* zxr = p.zz + c.ld;
   const double* za = p.zz + 2 * c.ld;
-  const double* zzw = p.zz + 3 * c.ld;
-  const double w = p.w[f];
-  double tw = lamL * w;
-  for (int j = 0; j < L - 1; ++j) tw = fma((p.lam[j] - lamL) * dw[j], p.Wm[(size_t)j * c.ld + f], tw);
-  tw -= zzw[f];
+  double tw = 0.0;
+  if (with_T) {
+    const int L = p.ell;
+    const double lamL = p.lam[L - 1];
+    const double* dw = p.dots + (size_t)ID_W * DSTRIDE;
+    const double* zzw = p.zz + 3 * c.ld;
+    tw = lamL * p.w[f];
+    for (int j = 0; j < L - 1; ++j)
+      tw = fma((p.lam[j] - lamL) * dw[j], p.Wm[(size_t)j * c.ld + f], tw);
+    tw -= zzw[f];
+  }
   p.h[f] = -(zxr[f] - za[f] / sigma) + c.mu * p.u[f] + c.sqmu * p.rho[f] / sigma + tw;
 }
 
-hipError_t launch_it_rhs(const Consts& c, const ItPtrs& p, hipStream_t st) {
-  hipLaunchKernelGGL(k_it_rhs, dim3((unsigned)((c.ld + 255) / 256)), dim3(256), 0, st, c, p);
+hipError_t launch_it_rhs(const Consts& c, const ItPtrs& p, hipStream_t st, int with_T) {
+  hipLaunchKernelGGL(k_it_rhs, dim3((unsigned)((c.ld + 255) / 256)), dim3(256), 0, st, c, p,
+                     with_T);
   return hipGetLastError();
 }
 
@@ -211,6 +216,8 @@ hipError_t launch_it_rhs(const Consts& c, const ItPtrs& p, hipStream_t st) {
 //     whether [w; beta] = [wbar; betabar] + solve(x) or [wbar; betabar].
 //     It also sets p.skip's flag so that the fresh Z~^T w pass is skipped
 //     when Step 1c kept wbar.
+//   mode 2: mode 1 with the re-solve taken (the switch from PSQMR to the
+//     proximal term inside Step 1c, decided by the PSQMR residual).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_it_solve(Consts c, ItPtrs p, Scal* skip, int mode) {
   Scal* sc = p.sc;
@@ -229,6 +236,7 @@ __global__ void __launch_bounds__(256) k_it_solve(Consts c, ItPtrs p, Scal* skip
     const double res = sqrt(fmax(dx[L] + xb * xb, 0.0));  // dx[L] = ||Z~ dr||^2
     redo = res > 5.0 * eps_k(c, k) ? 1 : 0;
   }
+  if (mode == 2) mode = 1;
   const double bbar = p.sca[IS_BETABAR];
   if (f < c.ld) {
     const double* x = mode == 0 ? p.h : p.zz;

@@ -48,7 +48,7 @@ class Params(C.Structure):
                 ("batch_fp32", C.c_int32), ("batch_tile", C.c_int32), ("graph", C.c_int32),
                 ("sigma_every", C.c_int32), ("representer", C.c_int32),
                 ("class_weights", C.c_int32), ("solver", C.c_int32), ("ell", C.c_int32),
-                ("e", C.c_void_p)]
+                ("e", C.c_void_p), ("psqmr_max", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -61,7 +61,9 @@ class Info(C.Structure):
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("stream_ms", C.c_double),
                 ("stream_launches", C.c_int32), ("resumed", C.c_int32),
                 ("streamT_ms", C.c_double), ("streamT_launches", C.c_int32),
-                ("graph_launches", C.c_int32)]
+                ("graph_launches", C.c_int32), ("psqmr_steps", C.c_int32),
+                ("psqmr_solves", C.c_int32), ("psqmr_switch", C.c_int32),
+                ("reserved", C.c_int32)]
 
     def to_dict(self) -> Dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -303,7 +305,14 @@ class Problem:
             out = np.empty(m)
             _check(_lib.dwd_inspect(self._h, b"lam", _dptr(out), m))
             return out
-        size = {"zscale": 1, "ymy": 1, "solver": 1, "ell": 1, "G": self.n * self.n,
+        if what == "psqmr_steps":
+            m = int(self.inspect("psqmr_count")[0])
+            out = np.empty(m)
+            if m:
+                _check(_lib.dwd_inspect(self._h, b"psqmr_steps", _dptr(out), m))
+            return out.astype(np.int64)
+        size = {"zscale": 1, "ymy": 1, "solver": 1, "ell": 1, "psqmr_count": 1,
+                "G": self.n * self.n,
                 "Minv": self.n * self.n, "my": self.n,
                 "Ainv": (self.d + 1) * (self.d + 1)}[what]
         out = np.empty(size)

@@ -175,6 +175,30 @@ def request_dense_data(req: Request):
                                   flip=0.1, dtype="f32"))
 
 
+def request_dense_data_device(req: Request, torch, device):
+    """The dense request recipe with the noise drawn on the device (for
+    streams too large to draw on the host): u, the labels and the flips as
+    in :func:`request_dense_data` from numpy with the request's seed, the
+    N(0, I) noise from a torch generator seeded with it, in FP32.  The same
+    distribution as :func:`request_dense_data`, other draws.  Returns
+    (X, y): X a device tensor of shape (n, d), y a float64 numpy vector."""
+    rng = np.random.default_rng(req.seed)
+    g = rng.standard_normal(req.d)
+    u = g / np.linalg.norm(g)
+    n_pos = req.n // 2
+    y_true = np.concatenate([np.ones(n_pos), -np.ones(req.n - n_pos)])[rng.permutation(req.n)]
+    n_flip = int(round(0.1 * req.n))
+    flip_idx = rng.choice(req.n, size=n_flip, replace=False)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(req.seed))
+    X = torch.randn((req.n, req.d), generator=gen, device=device, dtype=torch.float32)
+    X += (0.5 * torch.from_numpy(y_true.astype(np.float32)).to(device)[:, None]
+          * torch.from_numpy(u.astype(np.float32)).to(device)[None, :])
+    y = y_true.copy()
+    y[flip_idx] = -y[flip_idx]
+    return X, y
+
+
 def request_csr_data(req: Request, density: float = 1e-3):
     """Sparse request data as CSR of X^T (one row per sample, like a LIBSVM
     file): each entry is nonzero with probability ``density``, nonzeros are

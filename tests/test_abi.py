@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "dwd.h")
 def _declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"\b(dwd_[a-z_]+)\s*\(", src)
+    names = re.findall(r"\b(dwd_[A-Za-z0-9_]+)\s*\(", src)
     return sorted(set(names))
 
 
@@ -26,7 +26,8 @@ def D():
 
 def test_header_declares_the_boundary():
     names = _declared_functions()
-    for must in ("dwd_setup", "dwd_solve", "dwd_solve_batch", "dwd_serve", "dwd_free"):
+    for must in ("dwd_setup", "dwd_solve", "dwd_solve_batch", "dwd_serve", "dwd_free",
+                 "dwd_suggest_C"):
         assert must in names
 
 

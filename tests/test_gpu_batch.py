@@ -33,7 +33,7 @@ def test_batch_matches_oracle_and_single_solves(dwd, storage):
     for j, (C, q) in enumerate(grid):
         info = res["info"][j]
         assert info["converged"] == 1, (j, info)
-        assert info["kkt_check"] <= 2e-8, (j, info)
+        assert info["kkt_check"] < 1e-8, (j, info)
         ref = O.solve(X, y, C, q, tol=1e-9, max_iter=20000)
         w = res["W"][j]
         f, fr = _obj(X, y, w, info["beta"], C, q), _obj(X, y, ref["w"], ref["beta"], C, q)
@@ -52,7 +52,7 @@ def test_batch_matches_oracle_and_single_solves(dwd, storage):
     res5 = P.solve_batch([dict(C=C, q=q, tol=1e-5, batch_fp32=1) for C, q in grid])
     for j, (C, q) in enumerate(grid):
         info = res5["info"][j]
-        assert info["converged"] == 1 and info["kkt_check"] <= 1.5e-5, (j, info)
+        assert info["converged"] == 1 and info["kkt_check"] < 1e-5, (j, info)
         # as close to the optimum as the oracle stopped at the same tolerance
         ref = O.solve(X, y, C, q, tol=1e-9, max_iter=20000)
         same = O.solve(X, y, C, q, tol=1e-5, max_iter=2000)
@@ -81,10 +81,12 @@ def test_batch_freezes_finished_problems(dwd):
 def test_batch_sweep_full_size(dwd):
     """The 64-problem sweep at full size (d=2e5, n=1e3): with FP64 products and
     with the default FP32 products every problem converges and passes the
-    explicit FP64 check at the requested tolerance."""
+    explicit FP64 check at the requested tolerance; a sample is compared with
+    the FP64 oracle."""
     X, y = synth.two_class(synth.SWEEP_DATA)
     P = dwd.Problem(X, y, storage="f32")
     grid = synth.sweep_grid()
+    runs = {}
     for fp32 in (0, 1):
         res = P.solve_batch([dict(C=C, q=q, tol=1e-5, batch_fp32=fp32) for C, q in grid])
         infos = res["info"]
@@ -95,9 +97,36 @@ def test_batch_sweep_full_size(dwd):
                   infos[0]["solve_ms"], sum(i["resumed"] for i in infos)))
         for j, i in enumerate(infos):
             assert i["converged"] == 1, (fp32, j, i)
-            assert i["kkt_check"] <= 1.2e-5, (fp32, j, i)
+            assert i["kkt_check"] < 1e-5, (fp32, j, i)
         assert np.all(np.isfinite(res["W"]))
+        runs[fp32] = res
     P.close()
+    # A sample of two problems of the sweep (C ~ 0.22, q = 1 and C ~ 8.6,
+    # q = 2) against the FP64 oracle at the same tolerance: with FP64
+    # products the batch follows the oracle's trajectory (same iteration
+    # count, same w); with FP32 products it stops at another point within
+    # the tolerance, whose objective agrees to 2e-6 (each of the two points
+    # is within about 1e-6 of the optimum at this tolerance).
+    Xd = X.astype(np.float64)
+    for j in (21, 46):
+        C, q = grid[j]
+        o = O.solve(Xd, y, C, q, tol=1e-5, max_iter=2000)
+        assert o["converged"], j
+        fo = _obj(Xd, y, o["w"], o["beta"], C, q)
+        i0, w0 = runs[0]["info"][j], runs[0]["W"][j]
+        rel_w = np.linalg.norm(w0 - o["w"]) / np.linalg.norm(o["w"])
+        f0 = _obj(Xd, y, w0, i0["beta"], C, q)
+        f1 = _obj(Xd, y, runs[1]["W"][j], runs[1]["info"][j]["beta"], C, q)
+        print("sweep problem %d (C=%.4g q=%g): iters %d/%d (oracle) rel_w %.2e rel_obj fp64 %.2e "
+              "fp32 %.2e" % (j, C, q, i0["iters"], o["iters"], rel_w, abs(f0 - fo) / abs(fo),
+                             abs(f1 - fo) / abs(fo)))
+        assert abs(i0["iters"] - o["iters"]) <= 2, (j, i0["iters"], o["iters"])
+        if i0["iters"] == o["iters"]:  # the same stopping point
+            assert rel_w <= 1e-6, (j, rel_w)
+            assert abs(f0 - fo) <= 1e-9 * abs(fo), (j, f0, fo)
+        else:  # a neighbouring iterate of the same trajectory
+            assert abs(f0 - fo) <= 2e-6 * abs(fo), (j, f0, fo)
+        assert abs(f1 - fo) <= 2e-6 * abs(fo), (j, f1, fo)
 
 
 @pytest.mark.parametrize("fp32,tol", [(0, 1e-6), (1, 1e-5)])
@@ -120,7 +149,7 @@ def test_batch_tile_widths_and_graph_replay_are_bit_identical(dwd, fp32, tol):
     again = run(batch_tile=2, graph=1)
     ref = runs[(4, 0)]
     for i in ref["info"]:
-        assert i["converged"] == 1 and i["kkt_check"] <= 1.2 * tol, i
+        assert i["converged"] == 1 and i["kkt_check"] < tol, i
     assert ref["info"][0]["graph_launches"] == 0
     assert runs[(2, 1)]["info"][0]["graph_launches"] > 0
     for key, r in list(runs.items()) + [("again", again), ("tuned", run())]:
@@ -146,7 +175,7 @@ def test_batch_representer_matches_oracle_and_single_representer(dwd):
     assert res["info"][0]["graph_launches"] > 0 and eager["info"][0]["graph_launches"] == 0
     for j, (C, q) in enumerate(grid):
         info = res["info"][j]
-        assert info["converged"] == 1 and info["kkt_check"] <= 2e-8, (j, info)
+        assert info["converged"] == 1 and info["kkt_check"] < 1e-8, (j, info)
         ref = O.solve(X, y, C, q, tol=1e-9, max_iter=20000)
         f = _obj(X, y, res["W"][j], info["beta"], C, q)
         fr = _obj(X, y, ref["w"], ref["beta"], C, q)
@@ -170,5 +199,5 @@ def test_batch_representer_sweep_full_size(dwd):
         sum(i["converged"] for i in infos), max(i["iters"] for i in infos), infos[0]["solve_ms"],
         sum(i["resumed"] for i in infos)))
     for j, i in enumerate(infos):
-        assert i["converged"] == 1 and i["kkt_check"] <= 1.2e-5, (j, i)
+        assert i["converged"] == 1 and i["kkt_check"] < 1e-5, (j, i)
     P.close()

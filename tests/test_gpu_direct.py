@@ -86,7 +86,11 @@ def test_direct_solves_match_oracle(dwd, d, n, q, C, storage):
     # With d < n these problems have many margin violations and the ADMM tail
     # is slow (tens of thousands of iterations to 1e-9), so both sides stop at
     # 1e-7 and 1e-6 and are compared at the same stopping point; the
-    # objective is checked against a library solver where d is small.
+    # objective is checked against a library solver where d is small.  The
+    # iteration count is compared at 1e-6 only: near 1e-7 the sigma path
+    # depends on rounding order (a change of where multiply-adds are fused
+    # moved d = 10, n = 5000 from 1225 to 1391 iterations at the same
+    # solution), so the count there is not a parity quantity.
     X, y = synth.random_two_class(d, n, seed=d * 7 + n, mean=0.4, flip=0.1,
                                   dtype="f64" if storage == "f64" else "f32")
     P = dwd.Problem(X, y, storage=storage, solver="direct")
@@ -95,13 +99,14 @@ def test_direct_solves_match_oracle(dwd, d, n, q, C, storage):
         assert ref["converged"]
         got = P.solve(C, q, tol=tol, max_iter=20000)
         assert got["info"]["converged"] == 1, got["info"]
-        assert abs(got["info"]["iters"] - ref["iters"]) <= max(3, 0.1 * ref["iters"])
+        if tol >= 1e-6:
+            assert abs(got["info"]["iters"] - ref["iters"]) <= max(3, 0.1 * ref["iters"])
         fg, fr = _obj(X, y, C, q, got), _obj(X, y, C, q, ref)
         assert abs(fg - fr) <= 1e-6 * abs(fr), (tol, fg, fr)
         assert np.linalg.norm(got["w"] - ref["w"]) <= 1e-4 * np.linalg.norm(ref["w"]), tol
         k = O.kkt_of_solution(X, y, C, q, got)
         assert max(k["P"], k["D"]) <= 2 * tol, k
-        assert got["info"]["kkt_check"] <= 2 * tol
+        assert got["info"]["kkt_check"] < tol
     P.close()
     if d <= 130:
         import scipy.optimize as sopt
@@ -168,6 +173,18 @@ def test_auto_solver_choice(dwd):
     X, y = synth.random_two_class(100, 50, seed=43, dtype="f32")
     P = dwd.Problem(X, y, storage="bf16", solver="auto")
     assert P.inspect("solver")[0] == 0            # BF16 storage: SMW
+    P.close()
+    X, y = synth.random_two_class(6000, 1300, seed=44, dtype="f32")
+    P = dwd.Problem(X, y, storage="f32", solver="auto")
+    assert P.inspect("solver")[0] == 3            # d > 5000, n >= 0.2 d: iterative
+    P.close()
+    X, y = synth.random_two_class(20000, 2600, seed=45, dtype="f32")
+    P = dwd.Problem(X, y, storage="f32", solver="auto")
+    assert P.inspect("solver")[0] == 3            # d > 5000, n > 2500: iterative
+    P.close()
+    X, y = synth.random_two_class(20000, 2500, seed=46, dtype="f32")
+    P = dwd.Problem(X, y, storage="bf16", solver="auto")
+    assert P.inspect("solver")[0] == 0            # (BF16 storage: SMW)
     P.close()
 
 

@@ -1,7 +1,9 @@
-"""Parity of the iterative branch (Section 3.3.3: the proximal term of eq-T
-from the ell largest eigenpairs of Z~ Z~^T, solved in closed form through
-eq-schur) with the oracle's iterative branch when it uses T from the first
-iteration (psqmr_max = 0), through the C ABI."""
+"""Parity of the iterative branch (Section 3.3.3) with the oracle's, through
+the C ABI: PSQMR solves of eq-linsys with T = 0 to the accuracy of
+eq-linsys-tol, the switch to the proximal term of eq-T after a solve of more
+than psqmr_max steps, and the eq-T iteration itself (T from the ell largest
+eigenpairs of Z~ Z~^T, solved in closed form through eq-schur) from the
+first iteration (psqmr_max = 0)."""
 import numpy as np
 import pytest
 
@@ -51,7 +53,7 @@ def test_iterative_trajectory_follows_oracle(dwd, d, n, storage):
     for k in (1, 2, 5, 20):
         o = O.solve(X, y, C, q, tol=1e-300, max_iter=k, solver="iterative", ell=8, psqmr_max=0,
                     weights=True, e=e)
-        g = P.solve(C, q, tol=1e-300, max_iter=k, class_weights=1, e=e)
+        g = P.solve(C, q, tol=1e-300, max_iter=k, class_weights=1, e=e, psqmr_max=0)
         assert g["info"]["iters"] == k
         for key in ("alpha", "r", "xi"):
             assert np.allclose(g[key], o[key], rtol=1e-8, atol=1e-11), (k, key)
@@ -71,7 +73,7 @@ def test_iterative_solves_match_oracle(dwd, d, n, q, C):
     for tol in (1e-6, 1e-7):
         ref = O.solve(X, y, C, q, tol=tol, max_iter=20000, solver="iterative", psqmr_max=0)
         assert ref["converged"]
-        got = P.solve(C, q, tol=tol, max_iter=20000)
+        got = P.solve(C, q, tol=tol, max_iter=20000, psqmr_max=0)
         assert got["info"]["converged"] == 1, got["info"]
         assert abs(got["info"]["iters"] - ref["iters"]) <= max(3, 0.1 * ref["iters"]), tol
         w = got["w"] / max(1.0, np.linalg.norm(got["w"]))
@@ -86,6 +88,68 @@ def test_iterative_solves_match_oracle(dwd, d, n, q, C):
     smw = dwd.solve(X, y, C, q, tol=1e-7, solver="smw", max_iter=20000)
     assert np.linalg.norm(got["w"] - smw["w"]) <= 1e-3 * np.linalg.norm(smw["w"])
     P.close()
+
+
+@pytest.mark.parametrize("d,n,storage,pmax", [(400, 300, "f32", 50), (900, 150, "f64", 8),
+                                              (600, 400, "f32", 2)])
+def test_psqmr_trajectory_follows_oracle(dwd, d, n, storage, pmax):
+    """PSQMR with T = 0 (warm started, to eps_k in Step 1a and 5 eps_k in the
+    Step 1c re-solve): the first iterates, the step count of every solve and
+    the iteration at which the proximal term takes over agree with the
+    oracle.  psqmr_max = 50 never switches on these data; 8 switches inside
+    a Step 1a solve (iteration 7 at d = 900), 2 inside the first Step 1c
+    re-solve."""
+    X, y = _data(d, n, seed=3 * d + n, storage=storage)
+    e = synth.penalty_vector(n, seed=n + 3)
+    C, q = 1.0, 1.0
+    P = dwd.Problem(X, y, storage=storage, solver="iterative", ell=8)
+    for k in (1, 2, 5, 12):
+        o = O.solve(X, y, C, q, tol=1e-300, max_iter=k, solver="iterative", ell=8,
+                    psqmr_max=pmax, weights=True, e=e)
+        g = P.solve(C, q, tol=1e-300, max_iter=k, class_weights=1, e=e, psqmr_max=pmax)
+        steps = P.inspect("psqmr_steps")
+        info = g["info"]
+        assert info["iters"] == k
+        assert list(steps) == list(o["psqmr_steps"]), (k, list(steps), o["psqmr_steps"])
+        assert info["psqmr_solves"] == len(o["psqmr_steps"])
+        assert info["psqmr_steps"] == sum(o["psqmr_steps"])
+        assert (info["psqmr_switch"] >= 0) == bool(o["used_T"]), k
+        for key in ("alpha", "r", "xi"):
+            assert np.allclose(g[key], o[key], rtol=1e-8, atol=1e-11), (k, key)
+        for key in ("w", "u", "rho"):
+            assert np.allclose(g[key], o[key], rtol=1e-8,
+                               atol=1e-11 * max(1e-300, np.abs(o[key]).max())), (k, key)
+        assert abs(g["beta"] - o["beta"]) <= 1e-8 * max(1.0, abs(o["beta"])), k
+        assert info["n_double"] == o["n_double"], k
+    P.close()
+
+
+@pytest.mark.parametrize("d,n,q,C", [(400, 300, 1.0, 1.0), (800, 200, 2.0, 3.0)])
+def test_psqmr_solves_match_oracle(dwd, d, n, q, C):
+    """Whole solves with the paper's iterative method (PSQMR first, the
+    proximal term after a solve of more than 50 steps): the same stopping
+    point as the oracle, and the optimum of the exact SMW solve."""
+    X, y = _data(d, n, seed=d + n, log_scale=0.5 if d != 800 else 1.0)
+    P = dwd.Problem(X, y, storage="f32", solver="iterative")
+    ref = O.solve(X, y, C, q, tol=1e-6, max_iter=20000, solver="iterative", psqmr_max=50)
+    got = P.solve(C, q, tol=1e-6, max_iter=20000)
+    tight = O.solve(X, y, C, q, tol=1e-9, max_iter=20000)
+    P.close()
+    info = got["info"]
+    print("PSQMR solve d=%d n=%d: iters %d/%d, psqmr solves %d steps %d switch %d (oracle %s)" % (
+        d, n, info["iters"], ref["iters"], info["psqmr_solves"], info["psqmr_steps"],
+        info["psqmr_switch"], ref["used_T"]))
+    assert ref["converged"] and info["converged"] == 1 and info["kkt_check"] < 1e-6, info
+    assert abs(info["iters"] - ref["iters"]) <= max(3, 0.1 * ref["iters"])
+    w = got["w"] / max(1.0, np.linalg.norm(got["w"]))
+    f = O.reduced_objective(X, y, w, got["beta"], C, q)
+    fr = O.reduced_objective(X, y, ref["w"] / max(1.0, np.linalg.norm(ref["w"])), ref["beta"], C, q)
+    ft = O.reduced_objective(X, y, tight["w"] / max(1.0, np.linalg.norm(tight["w"])),
+                             tight["beta"], C, q)
+    assert abs(f - fr) <= 1e-6 * abs(fr), (f, fr)
+    assert abs(f - ft) <= 1e-5 * abs(ft), (f, ft)
+    k = O.kkt_of_solution(X, y, C, q, got)
+    assert max(k["P"], k["D"]) <= 1e-6 * (1 + 1e-6), k
 
 
 def test_iterative_beyond_both_limits(dwd):

@@ -85,8 +85,8 @@ def test_small_f64_solve_matches_oracle(dwd, small_ref):
     assert got["status"] == 0 and got["info"]["converged"] == 1
     _compare(X, y, wl.C, wl.q, got, ref)
     kkt, e = _recomputed_kkt(X, y, wl.C, wl.q, got)
-    assert kkt <= 1.5 * wl.tol, e
-    assert got["info"]["kkt_check"] <= 1.5 * wl.tol
+    assert kkt <= wl.tol * (1 + 1e-6), e
+    assert got["info"]["kkt_check"] < wl.tol
     # Same parameters, same tolerance: the iteration count follows the oracle's.
     assert abs(got["info"]["iters"] - same["iters"]) <= max(3, 0.1 * same["iters"])
     assert np.linalg.norm(got["w"]) <= 1 + 1e-5
@@ -181,6 +181,69 @@ def test_mu_and_exact_sgs_modes(dwd, small_ref):
         _compare(X, y, wl.C, wl.q, got, ref)
         if kw.get("eps_c") == 0.0:
             assert got["info"]["n_double"] >= got["info"]["iters"] - 1
+
+
+@pytest.mark.parametrize("kw", [dict(rho_residual=0), dict(sigma_every=1),
+                                dict(rho_residual=0, sigma_every=1)])
+def test_paper_literal_modes_follow_oracle(dwd, small_ref, kw):
+    """The printed two-term eta_D of Section 4.3 (rho_residual = 0) and the
+    sigma rule of Section 4.4 after every iteration (sigma_every = 1): the
+    first iterates agree with the oracle run in the same mode, a whole solve
+    stops where the oracle's does, and a tight solve reaches the optimum."""
+    X, y, wl, ref, _ = small_ref
+    okw = dict(rho_residual=bool(kw.get("rho_residual", 1)), sigma_every=kw.get("sigma_every", 2))
+    for k in (1, 2, 5, 20):
+        o = O.solve(X, y, wl.C, wl.q, tol=1e-300, max_iter=k, **okw)
+        g = dwd.solve(X, y, wl.C, wl.q, tol=1e-300, storage="f64", max_iter=k, **kw)
+        assert g["info"]["iters"] == k
+        for key in ("alpha", "r", "xi"):
+            assert np.allclose(g[key], o[key], rtol=1e-9, atol=1e-12), (k, key)
+        assert np.allclose(g["w"], o["w"], rtol=1e-9, atol=1e-12 * np.abs(o["w"]).max()), k
+        assert abs(g["info"]["sigma"] - o["sigma"]) <= 1e-12 * o["sigma"], k
+    same = O.solve(X, y, wl.C, wl.q, tol=wl.tol, max_iter=2000, **okw)
+    got = dwd.solve(X, y, wl.C, wl.q, tol=wl.tol, storage="f64", **kw)
+    assert got["status"] == 0 and got["info"]["converged"] == 1, got["info"]
+    assert got["info"]["kkt_check"] < wl.tol
+    assert abs(got["info"]["iters"] - same["iters"]) <= max(3, 0.1 * same["iters"]), \
+        (got["info"]["iters"], same["iters"])
+    tight = dwd.solve(X, y, wl.C, wl.q, tol=1e-8, storage="f64", max_iter=20000, **kw)
+    assert tight["info"]["converged"] == 1
+    _compare(X, y, wl.C, wl.q, tight, ref)
+
+
+def test_paper_literal_modes_ragged_f32(dwd):
+    """The literal modes on FP32 storage with a ragged shape (several tiles
+    and a tail): first iterates and a whole solve against the oracle in the
+    same mode.  On this case the printed two-term eta_D, which never measures
+    w-stationarity (||Z~ alpha + D rho||, eta_D3), lets the stopping rule
+    stop at tol 1e-8 about 0.5% above the optimal objective, with eta_D3
+    near 1e-3; the oracle stops at the same point.  With the D3 term (the
+    default) the same tolerance reaches the optimum."""
+    d, n, q, C = 5000, 123, 2.0, 3.0
+    X, y = synth.random_two_class(d, n, seed=7 * d + n, mean=0.6, dtype="f32")
+    P = dwd.Problem(X, y, storage="f32")
+    for k in (3, 8):
+        o = O.solve(X, y, C, q, tol=1e-300, max_iter=k, rho_residual=False, sigma_every=1)
+        g = P.solve(C, q, tol=1e-300, max_iter=k, rho_residual=0, sigma_every=1)
+        for key in ("alpha", "r", "xi"):
+            assert np.allclose(g[key], o[key], rtol=1e-9, atol=1e-12), (k, key)
+        assert abs(g["info"]["sigma"] - o["sigma"]) <= 1e-12 * o["sigma"], k
+    same = O.solve(X, y, C, q, tol=1e-8, max_iter=20000, rho_residual=False, sigma_every=1)
+    got = P.solve(C, q, tol=1e-8, max_iter=20000, rho_residual=0, sigma_every=1)
+    full = P.solve(C, q, tol=1e-8, max_iter=20000, sigma_every=1)
+    P.close()
+    assert got["info"]["converged"] == 1 and got["info"]["kkt_check"] < 1e-8, got["info"]
+    assert abs(got["info"]["iters"] - same["iters"]) <= max(3, 0.1 * same["iters"]), \
+        (got["info"]["iters"], same["iters"])
+    _compare(X, y, C, q, got, same)  # the same stopping point
+    ref = O.solve(X, y, C, q, tol=1e-9, max_iter=20000)
+    f_got, f_ref = _obj(X, y, got["w"], got["beta"], C, q), _obj(X, y, ref["w"], ref["beta"], C, q)
+    e = O.kkt_of_solution(X, y, C, q, got)
+    print("printed eta_D: rel. objective above the optimum %.3e, eta_D3 %.3e" % (
+        (f_got - f_ref) / f_ref, e["D3"]))
+    assert f_got - f_ref > 1e-3 * f_ref and e["D3"] > 1e-4
+    assert full["info"]["converged"] == 1
+    _compare(X, y, C, q, full, ref)
 
 
 def test_bf16_storage_with_fp32_refinement(dwd):
@@ -291,9 +354,9 @@ def test_hdlss_full_size_properties(dwd):
     info = got["info"]
     print("HDLSS solve:", {k: info[k] for k in ("iters", "n_double", "setup_ms", "solve_ms",
                                                   "kkt_check", "eta_gap")})
-    assert info["converged"] == 1
+    assert info["converged"] == 1 and info["kkt_check"] < wl.tol
     kkt, e = _recomputed_kkt(X, y, wl.C, wl.q, got)
-    assert kkt <= 1.5 * wl.tol, e
+    assert kkt <= wl.tol * (1 + 1e-6), e
     # Duality-gap certificate: the optimum lies between the dual value at a
     # feasible alpha and the primal value at the returned (w, beta).
     Xd = X.astype(np.float64)
@@ -310,6 +373,56 @@ def test_hdlss_full_size_properties(dwd):
     # r - xi = Z~^T w~ + beta y = y (x^T w + beta) for the unscaled w
     # (w~ = Z_scale w, Z~ = Z / Z_scale), up to the primal residual
     assert np.max(np.abs(m_gpu - m_ref)) <= 10 * wl.tol * (1 + wl.C)
+
+
+def test_hdlss_full_size_against_oracle(dwd):
+    """The HDLSS workload at full size (d = 1e5, n = 1e3, FP32 data) against
+    the FP64 oracle.  At the working tolerance 1e-5 the GPU follows the
+    oracle's own trajectory: the same iteration count and the same w and
+    beta.  At 1e-6 it reaches the optimum stored in tests/golden (written by
+    the oracle at 1e-9): w* = Z alpha* / ||Z alpha*||, objective within 1e-6,
+    w within 1e-4.  (At 1e-5 the oracle's own w is about 4e-4 from w*, so
+    the w bar is taken at 1e-6.)"""
+    import json
+    import os
+    wl = synth.HDLSS_F32
+    X, y = synth.two_class(wl.data)
+    Xd = X.astype(np.float64)
+    P = dwd.Problem(X, y, storage="f32")
+    got = P.solve(wl.C, wl.q, tol=wl.tol, want_state=False)
+    same = O.solve(Xd, y, wl.C, wl.q, tol=wl.tol, max_iter=2000)
+    gi = got["info"]
+    rel_w = np.linalg.norm(got["w"] - same["w"]) / np.linalg.norm(same["w"])
+    print("HDLSS vs oracle: iters %d/%d n_double %d/%d rel_w %.2e beta %.12g/%.12g" % (
+        gi["iters"], same["iters"], gi["n_double"], same["n_double"], rel_w, got["beta"],
+        same["beta"]))
+    assert gi["converged"] == 1 and gi["kkt_check"] < wl.tol, gi
+    assert same["converged"]
+    assert abs(gi["iters"] - same["iters"]) <= 2, (gi["iters"], same["iters"])
+    f_got, f_same = _obj(Xd, y, got["w"], got["beta"], wl.C, wl.q), \
+        _obj(Xd, y, same["w"], same["beta"], wl.C, wl.q)
+    if gi["iters"] == same["iters"]:  # the same stopping point
+        assert rel_w <= 1e-6, rel_w
+        assert abs(got["beta"] - same["beta"]) <= 1e-6 * max(1.0, abs(same["beta"]))
+        assert abs(f_got - f_same) <= 1e-9 * abs(f_same), (f_got, f_same)
+    else:  # a neighbouring iterate of the same trajectory
+        assert abs(f_got - f_same) <= 2e-6 * abs(f_same), (f_got, f_same)
+    # the optimum
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "hdlss_f32_solution.json")) as f:
+        g = json.load(f)
+    za = _z_alpha_by_rows(X, y, np.array(g["alpha"]))
+    w_star = za / np.linalg.norm(za)
+    tight = P.solve(wl.C, wl.q, tol=1e-6, want_state=False, max_iter=20000)
+    P.close()
+    assert tight["info"]["converged"] == 1 and tight["info"]["kkt_check"] < 1e-6
+    f_t = _obj(Xd, y, tight["w"], tight["beta"], wl.C, wl.q)
+    rel_obj = abs(f_t - g["reduced_objective"]) / abs(g["reduced_objective"])
+    rel_ws = np.linalg.norm(tight["w"] - w_star) / np.linalg.norm(w_star)
+    print("HDLSS tol 1e-6 vs stored optimum: rel_obj %.2e rel_w %.2e" % (rel_obj, rel_ws))
+    assert rel_obj <= 1e-6 and rel_ws <= 1e-4, (rel_obj, rel_ws)
+    # and the working-tolerance solve is within 1e-6 of the optimal objective
+    assert abs(f_got - g["reduced_objective"]) <= 1e-6 * abs(g["reduced_objective"])
 
 
 def _margins_by_rows(X, y, w, beta, rows=64):
@@ -330,12 +443,44 @@ def _z_alpha_by_rows(X, y, a, rows=64):
     return acc
 
 
+def _kkt_by_rows(X, y, C, got, mu=1.0, rows=64):
+    """The Section 4.3 residuals eta_P and eta_D (with the D3 term) of a
+    returned state, on the scaled problem, from X in row blocks in FP64: for
+    data too large to scale whole on the host.  With w~ = Z_scale w,
+    u~ = Z_scale u, Z~ = Z / Z_scale (Section 4.2):
+      P1 = ||Z^T w + beta y + xi - r||, P2 = sqrt(mu) Z_scale ||w - u||,
+      P3 = Z_scale max(||w|| - 1, 0), D1 = ||min(0, alpha)||,
+      D2 = ||max(0, alpha - C)||, D3 = ||Z alpha / Z_scale + sqrt(mu) rho||,
+    each over 1 + C."""
+    fro2 = 0.0
+    for r0 in range(0, X.shape[0], rows):
+        b = X[r0:r0 + rows].astype(np.float64)
+        fro2 += float(np.sum(b * b))
+    zs = fro2 ** 0.25
+    w, u, a = got["w"], got["u"], got["alpha"]
+    m = _margins_by_rows(X, y, w, got["beta"], rows)
+    den = 1.0 + C
+    p1 = np.linalg.norm(m + got["xi"] - got["r"]) / den
+    p2 = np.sqrt(mu) * zs * np.linalg.norm(w - u) / den
+    p3 = zs * max(np.linalg.norm(w) - 1.0, 0.0) / den
+    d1 = np.linalg.norm(np.minimum(0.0, a)) / den
+    d2 = np.linalg.norm(np.maximum(0.0, a - C)) / den
+    d3 = np.linalg.norm(_z_alpha_by_rows(X, y, a, rows) / zs + np.sqrt(mu) * got["rho"]) / den
+    return max(p1, p2, p3), max(d1, d2, d3)
+
+
 def test_large_bf16_full_size(dwd):
     """The large mixed-precision workload at full size (d=1e6, n=2000, q=2,
     C=1, BF16 storage of Z, FP64 factors, FP32 refinement): the FP64 check on
     the device, every sample's margin recomputed in FP64 on the host, a
     duality-gap certificate, and agreement with FP32 storage."""
     torch = pytest.importorskip("torch")
+    # the host helper reproduces the oracle's residuals on a small solved state
+    Xs, ys = synth.random_two_class(300, 40, seed=5, mean=0.6, dtype="f32")
+    so = O.solve(Xs, ys, 1.0, 2.0, tol=1e-4)
+    ek = O.kkt_of_solution(Xs, ys, 1.0, 2.0, so)
+    hp, hd = _kkt_by_rows(Xs, ys, 1.0, so)
+    assert abs(hp - ek["P"]) <= 1e-12 + 1e-9 * ek["P"] and abs(hd - ek["D"]) <= 1e-12 + 1e-9 * ek["D"]
     wl = synth.LARGE_BF16
     X, y = synth.two_class(wl.data)
     Xd = torch.from_numpy(X).to("cuda")
@@ -344,7 +489,14 @@ def test_large_bf16_full_size(dwd):
     print("large BF16 solve:", {k: info[k] for k in ("iters", "iters_lowp", "setup_ms",
                                                       "solve_ms", "kkt_check", "eta_gap")})
     assert info["converged"] == 1 and info["iters_lowp"] > 0
-    assert info["kkt_check"] <= 1.2 * wl.tol
+    assert info["kkt_check"] < wl.tol
+    # the residuals recomputed on the host in FP64 from the returned state
+    ep, ed = _kkt_by_rows(X, y, wl.C, got)
+    print("large BF16 host residuals: eta_P %.3e (device %.3e) eta_D %.3e (device %.3e)" % (
+        ep, info["eta_p_check"], ed, info["eta_d_check"]))
+    assert max(ep, ed) < wl.tol, (ep, ed)
+    assert abs(ep - info["eta_p_check"]) <= 1e-3 * wl.tol
+    assert abs(ed - info["eta_d_check"]) <= 1e-3 * wl.tol
     # r - xi = y (x^T w + beta) for every sample, up to the primal residual
     m = _margins_by_rows(X, y, got["w"], got["beta"])
     assert np.max(np.abs((got["r"] - got["xi"]) - m)) <= 10 * wl.tol * (1 + wl.C)

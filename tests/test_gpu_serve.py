@@ -102,7 +102,7 @@ def test_serve_result_is_the_same_alone_and_in_the_mix(dwd):
         assert m["status"] == 0 and alone["status"] == 0, (j, m["status"], alone["status"])
         assert m["info"]["iters"] == alone["info"]["iters"], j
         assert np.array_equal(m["w"], alone["w"]), j
-        assert m["info"]["kkt_check"] <= 1.5e-5, (j, m["info"])
+        assert m["info"]["kkt_check"] < 1e-5, (j, m["info"])
     # some requests shared the device
     iv = [(m["t_admit"], m["t_done"]) for m in mix]
     assert any(a2 < d1 and a1 < d2 for j, (a1, d1) in enumerate(iv) for (a2, d2) in iv[j + 1:])
@@ -176,7 +176,7 @@ def test_serve_steps_direct_problems_beside_smw_problems(dwd):
         assert m["status"] == 0 and m["info"]["converged"] == 1, (j, m)
         assert m["info"]["iters"] == single["info"]["iters"], j
         assert np.array_equal(m["w"], single["w"]), j
-        assert m["info"]["kkt_check"] <= 1.5e-5, (j, m["info"])
+        assert m["info"]["kkt_check"] < 1e-5, (j, m["info"])
         # and against the oracle's branch of the same kind at the same tolerance
         Xd = r["X"].astype(np.float64)
         o = O.solve(Xd, r["y"], p["C"], p["q"], tol=p["tol"], max_iter=2000,
@@ -184,3 +184,57 @@ def test_serve_steps_direct_problems_beside_smw_problems(dwd):
                     weights=bool(p["class_weights"]))
         assert abs(m["info"]["iters"] - o["iters"]) <= max(3, 0.1 * o["iters"]), j
         assert np.linalg.norm(m["w"] - o["w"]) <= 1e-4 * np.linalg.norm(o["w"]), j
+
+
+def test_serve_stream_sample_matches_oracle_and_plain_solves(dwd):
+    """A random sample of 50 requests of the seeded serving stream (the
+    requests among its first 600 with d n <= 2e6, so that the oracle solves
+    take seconds; dense FP32, dense BF16 and CSR as drawn), served together
+    with every request queued at t = 0.  Each result equals the plain
+    single solve bit for bit and agrees with the FP64 oracle run to the same
+    tolerance: FP32 and CSR requests stop where the oracle stops (same
+    iteration count within 10%, w within 1e-4), BF16 requests (whose first
+    phase iterates on the BF16 image) reach the same objective within
+    1e-5."""
+    stream = synth.request_stream(600, rate=1.0)
+    small = [r for r in stream if r.d * r.n <= 2e6]
+    pick = sorted(np.random.default_rng(12).choice(len(small), size=50, replace=False))
+    sample = [small[i] for i in pick]
+    reqs, dense = [], []
+    for r in sample:
+        if r.layout == "csr":
+            ip, ix, val, y = synth.request_csr_data(r)
+            reqs.append(dict(csr=(ip, ix, val, r.d), y=y))
+            dense.append(synth.csr_to_dense(ip, ix, val, r.d, np.float64))
+        else:
+            X, y = synth.request_dense_data(r)
+            reqs.append(dict(X=X, y=y))
+            dense.append(X.astype(np.float64))
+        reqs[-1]["params"] = dict(C=r.C, q=r.q, tol=1e-5, storage=r.storage)
+    out = dwd.serve(reqs, iters_per_round=8)
+    kinds = {}
+    for j, (r, rq, o, Xd) in enumerate(zip(sample, reqs, out, dense)):
+        kind = "csr" if r.layout == "csr" else r.storage
+        kinds[kind] = kinds.get(kind, 0) + 1
+        assert o["status"] == 0 and o["info"]["converged"] == 1, (j, o["info"])
+        assert o["info"]["kkt_check"] < 1e-5, (j, o["info"])
+        p = rq["params"]
+        if "csr" in rq:
+            P = dwd.Problem(csr=rq["csr"], y=rq["y"], storage=p["storage"])
+        else:
+            P = dwd.Problem(rq["X"], rq["y"], storage=p["storage"])
+        single = P.solve(p["C"], p["q"], tol=p["tol"], want_state=False)
+        P.close()
+        assert np.array_equal(single["w"], o["w"]), j
+        same = O.solve(Xd, rq["y"], p["C"], p["q"], tol=1e-5, max_iter=2000)
+        assert same["converged"], j
+        f = _obj(Xd, rq["y"], o["w"], o["beta"], p["C"], p["q"])
+        fo = _obj(Xd, rq["y"], same["w"], same["beta"], p["C"], p["q"])
+        if kind == "bf16":
+            assert abs(f - fo) <= 1e-5 * abs(fo), (j, f, fo)
+        else:
+            it, ito = o["info"]["iters"], same["iters"]
+            assert abs(it - ito) <= max(3, 0.1 * ito), (j, it, ito)
+            assert np.linalg.norm(o["w"] - same["w"]) <= 1e-4 * np.linalg.norm(same["w"]), j
+    print("served sample:", kinds)
+    assert len(kinds) == 3  # every kind of request is in the sample

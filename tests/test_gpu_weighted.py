@@ -84,7 +84,7 @@ def test_weighted_solves_match_oracle(dwd, q, C, d, n, storage, cw, use_e, rep):
     _compare(X, y, C, q, got, ref, wt, e)
     k = O.kkt_of_solution(X, y, C, q, got, weights=bool(cw), e=e)
     assert max(k["P"], k["D"]) <= 2e-8, k
-    assert got["info"]["kkt_check"] <= 2e-8
+    assert got["info"]["kkt_check"] < 1e-8
     # the reported objectives are the weighted ones
     assert abs(got["info"]["primal_obj"] - k["primobj"]) <= 1e-6 * abs(k["primobj"])
     assert abs(got["info"]["dual_obj"] - k["dualobj"]) <= 1e-6 * abs(k["dualobj"])
@@ -133,7 +133,7 @@ def test_weighted_batch_matches_oracle_and_single_solves(dwd):
     res = P.solve_batch([dict(g, tol=1e-8, max_iter=20000) for g in grid])
     for j, g in enumerate(grid):
         info = res["info"][j]
-        assert info["converged"] == 1 and info["kkt_check"] <= 2e-8, (j, info)
+        assert info["converged"] == 1 and info["kkt_check"] < 1e-8, (j, info)
         cw, e = bool(g.get("class_weights", 0)), g.get("e")
         ref = O.solve(X, y, g["C"], g["q"], tol=1e-9, max_iter=20000, weights=cw, e=e)
         got = dict(w=res["W"][j], beta=info["beta"])
