@@ -315,6 +315,20 @@ dwd_status dwd_serve(const dwd_request* reqs, int32_t nreq, const dwd_serve_opts
  * DWD_E_DEVICE.                                                                */
 dwd_status dwd_suggest_C(dwd_problem P, double q, double* C);
 
+/* Allocation-free form of dwd_suggest_C, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, errors and value (bit for bit) as
+ * dwd_suggest_C; the class split and the histogram of the radix selection
+ * live in a fixed static device work area of 263,424 bytes that each GPU the
+ * library runs on holds until the process ends, and the call performs no
+ * device or host allocation (only small reads into stack variables; the
+ * call synchronises P's stream).
+ *   Limit: n <= 65536 samples; a larger n returns DWD_E_INVALID.
+ *   Every call on one GPU shares that GPU's work area: calls that overlap in
+ *   time on one GPU (several threads, or several streams) race, and the
+ *   caller must serialise them.                                                */
+dwd_status dwd_suggest_C_noalloc(dwd_problem P, double q, double* C);
+
 /* Diagnostics: copy a set-up quantity of P to the host array out (count
  * doubles, must equal the quantity's size).  what is one of
  *   "zscale" (1): Z_scale = sqrt(||X||_F) of Section 4.2;

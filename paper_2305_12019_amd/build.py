@@ -8,7 +8,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdwd.so")
 SOURCES = ["dwd_api.hip", "kernels_setup.hip", "kernels_iter.hip", "kernels_batch.hip", "kernels_csr.hip",
            "kernels_direct.hip", "kernels_iterative.hip", "dwd_batch.hip", "dwd_serve.hip",
-           "dwd_direct.hip", "dwd_iterative.hip", "kernels_psqmr.hip"]
+           "dwd_direct.hip", "dwd_iterative.hip", "dwd_static.hip", "kernels_psqmr.hip"]
 
 # -ffp-contract=on: multiply-adds are fused only within one source expression
 # (as written), never across statements by the back end, so a device function

@@ -1063,6 +1063,15 @@ dwd_status dwd_suggest_C(dwd_problem H, double q, double* C) {
   }
 }
 
+dwd_status dwd_suggest_C_noalloc(dwd_problem H, double q, double* C) {
+  if (!H || !H->P || !C) return fail(DWD_E_INVALID, "NULL argument");
+  try {
+    return suggest_C_static(H->P, q, C);
+  } catch (...) {
+    return fail(DWD_E_DEVICE, "unexpected exception in dwd_suggest_C_noalloc");
+  }
+}
+
 dwd_status dwd_inspect(dwd_problem H, const char* what, double* out, int64_t count) {
   if (!H || !H->P || !what || !out) return fail(DWD_E_INVALID, "NULL argument");
   Problem* P = H->P;

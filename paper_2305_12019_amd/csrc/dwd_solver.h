@@ -195,6 +195,10 @@ dwd_status suggest_C(Problem* P, double q, double* C);
 // distances (equal for an odd count).
 dwd_status C_from_median_keys(const Problem* P, double q, unsigned long long k1,
                               unsigned long long k2, double* C);
+// suggest_C without any allocation: its work area is a static device array
+// (dwd_static.hip); n <= kStaticMaxN.
+constexpr int kStaticMaxN = 65536;
+dwd_status suggest_C_static(Problem* P, double q, double* C);
 // Direct branch (dwd_direct.hip): the factor and buffers after the data are
 // staged (Z_scale known), and the solve loop.
 constexpr int64_t kDirectMaxD = 5120;

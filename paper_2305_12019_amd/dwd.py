@@ -109,6 +109,8 @@ def _load():
     lib.dwd_footprint.restype = C.c_int64
     lib.dwd_suggest_C.argtypes = [C.c_void_p, C.c_double, dp]
     lib.dwd_suggest_C.restype = C.c_int
+    lib.dwd_suggest_C_noalloc.argtypes = [C.c_void_p, C.c_double, dp]
+    lib.dwd_suggest_C_noalloc.restype = C.c_int
     lib.dwd_inspect.argtypes = [C.c_void_p, C.c_char_p, dp, C.c_int64]
     lib.dwd_inspect.restype = C.c_int
     lib.dwd_status_str.argtypes = [C.c_int]
@@ -296,6 +298,13 @@ class Problem:
         """The Section 4.1 choice of C for exponent q (dwd_suggest_C)."""
         out = np.empty(1)
         _check(_lib.dwd_suggest_C(self._h, q, _dptr(out)))
+        return float(out[0])
+
+    def suggest_C_noalloc(self, q: float = 1.0) -> float:
+        """The same value from the allocation-free entry point
+        (dwd_suggest_C_noalloc)."""
+        out = np.empty(1)
+        _check(_lib.dwd_suggest_C_noalloc(self._h, q, _dptr(out)))
         return float(out[0])
 
     def inspect(self, what: str) -> np.ndarray:

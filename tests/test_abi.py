@@ -27,7 +27,7 @@ def D():
 def test_header_declares_the_boundary():
     names = _declared_functions()
     for must in ("dwd_setup", "dwd_solve", "dwd_solve_batch", "dwd_serve", "dwd_free",
-                 "dwd_suggest_C"):
+                 "dwd_suggest_C", "dwd_suggest_C_noalloc"):
         assert must in names
 
 
