@@ -254,8 +254,10 @@ dwd_status dwd_solve(dwd_problem P, const dwd_params* p, double* w, dwd_info* in
  *   W:    d x B column-major host array (column j = w of problem j).
  *   info: B reports (nullable).
  * Each problem follows exactly the iteration it would follow alone; a
- * converged problem is frozen.  Returns DWD_OK if all converged, else
- * DWD_NOT_CONVERGED, or an error.                                               */
+ * converged problem is frozen.  Needs a dense FP32 or FP64 set-up with the
+ * SMW solver and d <= 8388608 (the product addresses a K tile of X with
+ * 32-bit offsets), else DWD_E_INVALID.  Returns DWD_OK if all converged,
+ * else DWD_NOT_CONVERGED, or an error.                                          */
 dwd_status dwd_solve_batch(dwd_problem P, int32_t B, const dwd_params* p, double* W,
                            dwd_info* info);
 

@@ -26,6 +26,7 @@ hipError_t launch_resume_b(const BatchPtrs& P, const int* idx, int cnt, hipStrea
 hipError_t launch_anchor_b(const BatchPtrs& P, int p, const double* partT, int nchunks,
                            hipStream_t st);
 int batch_pass_row_blocks(int64_t ld);
+int batch_sb_rows(int n);
 
 namespace {
 
@@ -162,6 +163,7 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   if (P->layout != DWD_DENSE) return fail(DWD_E_INVALID, "dwd_solve_batch needs dense X");
   if (P->solver != DWD_SOLVER_SMW)
     return fail(DWD_E_INVALID, "dwd_solve_batch needs the SMW set-up");
+  if (P->ld > (int64_t)1 << 23) return fail(DWD_E_INVALID, "dwd_solve_batch needs d <= 8388608");
   HIP_TRY_B(hipSetDevice(P->device));
   const hipStream_t st = P->stream;
   const int n = P->n;
@@ -195,7 +197,16 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   bp.U = dv;
   bp.RHO = dv + (size_t)ld * B;
   bp.W = dv + 2 * (size_t)ld * B;
-  HIP_TRY_B(bb.dalloc((void**)&bp.SB, nB * 8));
+  bp.sbld = (B + 63) / 64 * 64;
+  {
+    const size_t sbn = (size_t)batch_sb_rows(n) * bp.sbld;
+    HIP_TRY_B(bb.dalloc((void**)&bp.SB, sbn * 8));
+    HIP_TRY_B(bb.dalloc((void**)&bp.SBf, sbn * 4));
+    // the zero rows past n stay zero; columns past the active slots are
+    // read by the product but their results are never used
+    HIP_TRY_B(hipMemsetAsync(bp.SB, 0, sbn * 8, st));
+    HIP_TRY_B(hipMemsetAsync(bp.SBf, 0, sbn * 4, st));
+  }
   {  // penalty weights of each problem (column j = p[j].e or ones)
     double* E = nullptr;
     HIP_TRY_B(bb.dalloc((void**)&E, nB * 8));

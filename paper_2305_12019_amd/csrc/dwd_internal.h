@@ -126,7 +126,12 @@ struct BatchPtrs {
   double *R, *XI, *AL, *PU, *PR, *T, *XX, *F, *S, *V, *DR, *RN, *S1, *V1, *XI0, *XI1, *AL0,
       *AL1, *HA;
   double *U, *RHO, *W;
-  double* SB;          // n x B: column slot = y .* s / Z_scale of the chosen outcome
+  // the pass's operand S, k-major (row k = sample k, row length sbld >= B,
+  // zero rows up to n rounded to 64): column slot = y .* s / Z_scale of the
+  // slot's chosen outcome, in FP64 (SB) or FP32 (SBf) for the product type
+  double* SB;
+  float* SBf;
+  int sbld;
   double *part_n1, *part_it, *part_c, *part_g, *part_ga;
   // representer mode: coefficients (u~ = Z~ AU, rho = Z~ ARHO, w~ = Z~ AW),
   // CV = alpha' + sqrt(mu) ARHO' (coefficients of Z~ alpha' + D rho') and the

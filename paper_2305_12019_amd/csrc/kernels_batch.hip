@@ -344,7 +344,8 @@ __global__ void __launch_bounds__(NM_T) k_s1c_mm(BatchPtrs P, const int* __restr
 // Per problem: the Step 1c decision and gamma = min(1, R/||g||) from the
 // block partials (fixed order), as step2_plan does for one problem.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_plan_b(BatchPtrs P, const int* __restrict__ idx) {
+__global__ void __launch_bounds__(256) k_plan_b(BatchPtrs P, const int* __restrict__ idx,
+                                                int f32) {
   const int pr = idx[blockIdx.x];
   Scal* sc = P.sc + pr;
   if (sc->done) return;
@@ -368,27 +369,47 @@ __global__ void __launch_bounds__(256) k_plan_b(BatchPtrs P, const int* __restri
     sc->gamma = pl.gamma;
   }
   if (P.rep) return;  // no pass in the representer iteration
-  // the pass's right-hand operand for this slot, dense and pre-scaled
+  // the pass's right-hand operand for this slot, dense and pre-scaled:
+  // column blockIdx.x of the k-major S, in the pass's product type
   const double* src = (pl.redo ? P.S1 : P.S) + (size_t)pr * P.n;
-  double* dst = P.SB + (size_t)blockIdx.x * P.n;
-  for (int i = threadIdx.x; i < P.n; i += 256) dst[i] = P.y[i] * c.inv_zs * src[i];
+  const size_t sl = P.sbld;
+  if (f32) {
+    float* dst = P.SBf + blockIdx.x;
+    for (int i = threadIdx.x; i < P.n; i += 256) dst[i * sl] = (float)(P.y[i] * c.inv_zs * src[i]);
+  } else {
+    double* dst = P.SB + blockIdx.x;
+    for (int i = threadIdx.x; i < P.n; i += 256) dst[i * sl] = P.y[i] * c.inv_zs * src[i];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // The pass over Z for all active problems: W = (Bm - Z~ S) / mu with the
-// dense, pre-scaled operand SB (column slot = y .* s_j / Z_scale of the
-// chosen Step 1c outcome), on MFMA 16x16x4 (f32 or f64), fused with Steps
-// 2-3:  g = w - rho/(sigma sqrt(mu)), u = gamma g,
+// dense, pre-scaled operand S (row k = sample k, column slot = y .* s / Z_scale
+// of the slot's chosen Step 1c outcome), on MFMA 16x16x4 (f32 or f64), fused
+// with Steps 2-3:  g = w - rho/(sigma sqrt(mu)), u = gamma g,
 // rho -= tau sigma sqrt(mu)(w - u), and per-problem block partials (NP2
 // layout of the single pass; the two Z~ alpha entries are 0 here: the batched
-// tail gets them in n-space).  Block tile: 128 rows x 16 NB slots, 4 waves,
-// wave w owns rows 32w..32w+31.  Every output element is the same sequence
-// of MFMA steps over k whatever NB is, so the tile width (chosen by the
-// host's tuner) does not change any result.
+// tail gets them in n-space).
+//
+// Block tile: 64 rows x 16 NB slots, 4 waves, wave w owns rows 16w..16w+15
+// and all 16 NB slots, so one block reads its rows of X once for all the
+// slots of the tile (with NB = 4, once for 64 problems).  64-row tiles keep
+// the work per CU within one tile of even at d = 1e5 (1568 tiles on 256
+// CUs); the A operand comes straight from global memory into the MFMA
+// registers (lane l: row l % 16, sample l / 16 of each 4-sample step), the
+// B tile (BK samples x 16 NB slots, shared by the four waves) goes through
+// LDS, double-buffered with one barrier per K tile, and both are loaded one
+// K tile ahead.  Column i of product b is slot NB i + b, so each lane reads
+// its NB B values of a step as one contiguous LDS vector.  Every output
+// element is the same sequence of MFMA steps over k whatever NB is, so the
+// tile width (chosen by the host's tuner) does not change any result.
+// FP32 products are summed in FP32 over 128 samples (four K tiles) and
+// those sums added in FP64; FP64 products accumulate in the MFMA registers
+// throughout.
 // ---------------------------------------------------------------------------
-constexpr int BT_M = 128, BT_T = 256;
-static_assert(BT_M == 32 * (BT_T / 64), "each wave owns 32 rows of the tile");
-constexpr int BT_LPP = BT_T / 16;      // epilogue lanes per problem of a 16-problem group
+constexpr int BT_M = 64, BT_T = 256;
+static_assert(BT_M == 16 * (BT_T / 64), "each wave owns 16 rows of the tile");
+constexpr int BT_SUM = 128;  // samples per FP32 partial sum of the FP32 products
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v_b __attribute__((ext_vector_type(4)));
@@ -413,75 +434,113 @@ struct MfmaB<double> {
   __device__ static __forceinline__ int row(int l, int v) { return 4 * v + (l >> 4); }
 };
 
-// The A operand comes straight from global memory into the MFMA registers.
-// In the 16x16x4 products lane l supplies row l % 16 and inner index l / 16;
-// here lane l loads the two consecutive rows 2 (l % 16) + {0, 1} of sample
-// k0 + l / 16 (one 8- or 16-byte load; 16 lanes cover 32 contiguous rows of
-// a sample), and component j feeds the product whose 16 output rows are
-// {2 i + j}.  So the wave owns 32 rows, the block (four waves) 128 rows, and
-// A never passes through LDS.  B (the BK x 16 NB slice of SB, shared by
-// the four waves) is staged in LDS, double-buffered: one barrier per K tile.
-// The A tile of the next K tile is loaded into registers while the current
-// one is multiplied.
-constexpr int BK = 32;                 // inner (sample) dimension per K tile
-constexpr int BK_STEPS = BK / 4;       // MFMA k-steps per K tile
-
-template <typename TD>
-struct ARow;
-template <>
-struct ARow<float> {
-  typedef float v2 __attribute__((ext_vector_type(2)));
-  __device__ static __forceinline__ void load(const float* p, float& a0, float& a1) {
-    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
-    a0 = v.x;
-    a1 = v.y;
-  }
-};
-template <>
-struct ARow<double> {
-  __device__ static __forceinline__ void load(const double* p, double& a0, double& a1) {
-    const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
-    a0 = v.x;
-    a1 = v.y;
-  }
-};
-
-// Row (within the wave's 32) of output register v of lane l for component j.
+// K tile depth (samples).
 template <typename T>
-__device__ __forceinline__ int pass_b_row(int l, int v, int j) {
-  return 2 * MfmaB<T>::row(l, v) + j;
+constexpr int pass_b_bk() {
+  return 32;
 }
+// Rows of the pre-scaled operand S (n padded with zero rows to whole K tiles
+// of either depth).
+int batch_sb_rows(int n) { return (n + 63) / 64 * 64; }
 
-// LDS row stride of the B tile (elements): rows l / 16 = 0, 1 of a half-wave
-// land in different bank halves.
-template <int NB>
+// LDS row of the B tile: the tile's 16 NB slots plus 16 bytes, so that the
+// four sample rows a half-wave reads start in different banks.
+template <typename T, int NB>
 constexpr int pass_b_bstride() {
-  return 16 * NB + (NB % 2 ? 32 : 16);
+  return 16 * NB + 16 / (int)sizeof(T);
+}
+// LDS row of the epilogue's (slot, row) staging: 64 rows plus one double (the
+// lanes of a write differ in slot).
+constexpr int BT_ZS = BT_M + 1;
+
+// The NB consecutive B values of a lane's step as one LDS vector read.
+template <typename T, int NB>
+__device__ __forceinline__ void b_frag(const T* s, T (&b)[NB]) {
+  if constexpr (NB == 1) {
+    b[0] = s[0];
+  } else if constexpr (sizeof(T) == 4 && NB == 2) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *reinterpret_cast<const v2*>(s);
+    b[0] = v.x;
+    b[1] = v.y;
+  } else if constexpr (sizeof(T) == 4 && NB == 4) {
+    const f4v v = *reinterpret_cast<const f4v*>(s);
+    b[0] = v.x;
+    b[1] = v.y;
+    b[2] = v.z;
+    b[3] = v.w;
+  } else {
+#pragma unroll
+    for (int h = 0; h < NB; h += 2) {
+      const nt_d2 v = *reinterpret_cast<const nt_d2*>(s + h);
+      b[h] = v.x;
+      b[h + 1] = v.y;
+    }
+  }
 }
 
-// FP64 products (T = double) accumulate in the MFMA registers over the whole
-// inner dimension; FP32 products (T = float) are summed per K tile and the
-// tile sums added in FP64.
+// 16-byte chunk of the B tile (4 floats or 2 doubles).
+template <typename T>
+struct BChunk;
+template <>
+struct BChunk<float> {
+  typedef f4v v_t;
+};
+template <>
+struct BChunk<double> {
+  typedef nt_d2 v_t;
+};
+
+// Raw buffer resource over [p, p + bytes) (gfx9 descriptor, no swizzle);
+// loads past the end return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+// (streamed once: non-temporal)
+template <typename TD>
+__device__ __forceinline__ TD buf_load_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(TD) == 4)
+    return __builtin_bit_cast(TD, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 2));
+  else
+    return __builtin_bit_cast(TD, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 2));
+}
+
 template <typename TD, typename T, int NB>
-__global__ void __launch_bounds__(BT_T) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 2 : 3)))
-k_pass_b(const TD* __restrict__ X, BatchPtrs P, const int* __restrict__ idx, int bact) {
+__global__ void __launch_bounds__(BT_T) __attribute__((amdgpu_waves_per_eu(sizeof(TD) == 8 && NB == 4 ? 3 : 4)))
+k_pass_b(const TD* __restrict__ X, BatchPtrs P, const T* __restrict__ SBk,
+         const int* __restrict__ idx, int bact, int ny) {
   typedef typename MfmaB<T>::acc_t acc_t;
+  typedef typename BChunk<T>::v_t chunk_t;
   constexpr int BN = 16 * NB;
-  constexpr int BS = pass_b_bstride<NB>();
+  constexpr int BK = pass_b_bk<T>();
+  constexpr int BK_STEPS = BK / 4;
+  constexpr int BS = pass_b_bstride<T, NB>();
   constexpr bool F64 = sizeof(T) == 8;
-  __shared__ T Bs[2][BK][BS];
-  __shared__ double Tz[16][BT_M + 1];
+  constexpr int VW = 16 / (int)sizeof(T);            // elements per 16-byte chunk
+  constexpr int CPR = BN / VW;                       // chunks per B tile row
+  constexpr int BCH = (BK * CPR + BT_T - 1) / BT_T;  // chunks per thread per tile
+  constexpr size_t BBYTES = sizeof(T) * 2 * BK * BS;
+  constexpr size_t ZBYTES = sizeof(double) * BN * BT_ZS;
+  __shared__ __align__(16) unsigned char smem[BBYTES > ZBYTES ? BBYTES : ZBYTES];
+  T(*Bs)[BK][BS] = reinterpret_cast<T(*)[BK][BS]>(smem);
+  double(*Tz)[BT_ZS] = reinterpret_cast<double(*)[BT_ZS]>(smem);
   __shared__ int s_p[BN];
   __shared__ int s_live[BN];
   __shared__ double s_sig[BN], s_gam[BN], s_tau[BN];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int64_t m0 = (int64_t)blockIdx.x * BT_M;
-  const int slot0 = blockIdx.y * BN;
+  // blocks of one XCD (linear id mod 8) take consecutive (row tile, slot
+  // tile) pairs, so the slot tiles of a row tile read its X rows from the
+  // same L2 at about the same time
+  const int L = blockIdx.x;
+  const int gi = L >> 3;
+  const int rt = (gi / ny) * 8 + (L & 7);
+  const int yt = gi % ny;
+  const int64_t m0 = (int64_t)rt * BT_M;
+  const int slot0 = yt * BN;
   const int bact_tile = min(BN, bact - slot0);
   const int n = P.n;
   const int64_t ld = P.ld;
-  const double* SB = P.SB + (size_t)slot0 * n;
   if (tid < BN) {
     const int slot = slot0 + tid;
     int p = -1, live = 0;
@@ -498,131 +557,150 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P, const int* __restrict__ idx, int
       s_tau[tid] = P.cs[p].tau;
     }
   }
-  // this lane's two rows of the wave's 32, in sample k0 + lk of each step
-  const TD* xa = X + m0 + wid * 32 + 2 * li + (int64_t)lk * ld;
-  auto load_a = [&](int k0, TD (&a)[BK_STEPS][2]) {
+  // A and B through buffer loads: a block-uniform base (per K tile) in the
+  // resource and the lane's 32-bit offset in a VGPR.  Lane (li, lk) reads
+  // row li of the wave's 16 in sample k0 + 4 s + lk of step s.  The A
+  // resource ends at the end of X, so in the last K tile the samples past n
+  // read as 0 (the hardware's range check; the S rows past n are 0 too).
+  const uint32_t aoff = ((uint32_t)(wid * 16 + li) + (uint32_t)lk * (uint32_t)ld) * sizeof(TD);
+  const uint32_t astep = 4u * (uint32_t)ld * sizeof(TD);
+  auto load_a = [&](int k0, TD (&a)[BK_STEPS]) {
+    const int64_t left = ((int64_t)(n - k0) * ld - m0) * (int64_t)sizeof(TD);
+    const uint32_t nrec = left > (int64_t)0xffffffffLL ? 0xffffffffu : (uint32_t)left;
+    const __amdgpu_buffer_rsrc_t r = buf_rsrc(X + m0 + (int64_t)k0 * ld, nrec);
 #pragma unroll
-    for (int s = 0; s < BK_STEPS; ++s) {
-      const int k = k0 + 4 * s + lk;
-      if (k < n) {
-        ARow<TD>::load(xa + (int64_t)(k0 + 4 * s) * ld, a[s][0], a[s][1]);
-      } else {
-        a[s][0] = (TD)0;
-        a[s][1] = (TD)0;
-      }
+    for (int s = 0; s < BK_STEPS; ++s) a[s] = buf_load_nt<TD>(r, aoff + s * astep, 0);
+  };
+  // B tile chunk c = tid + BT_T h: sample row c / CPR, slots VW (c % CPR) ..
+  const uint32_t sbld = (uint32_t)P.sbld;
+  const __amdgpu_buffer_rsrc_t rb = buf_rsrc(SBk + slot0, 0xffffffffu);
+  uint32_t boff[BCH];
+#pragma unroll
+  for (int h = 0; h < BCH; ++h) {
+    const uint32_t c = tid + h * BT_T;
+    boff[h] = ((c / CPR) * sbld + VW * (c % CPR)) * sizeof(T);
+  }
+  auto load_b = [&](int k0, chunk_t (&b)[BCH]) {
+    const uint32_t so = (uint32_t)k0 * sbld * sizeof(T);
+#pragma unroll
+    for (int h = 0; h < BCH; ++h)
+      if (BK * CPR % BT_T == 0 || tid + h * BT_T < BK * CPR)
+        b[h] = __builtin_bit_cast(chunk_t, __builtin_amdgcn_raw_buffer_load_b128(rb, boff[h], so, 0));
+  };
+  auto store_b = [&](int buf, const chunk_t (&b)[BCH]) {
+#pragma unroll
+    for (int h = 0; h < BCH; ++h) {
+      const int c = tid + h * BT_T;
+      if (BK * CPR % BT_T == 0 || c < BK * CPR)
+        *reinterpret_cast<chunk_t*>(&Bs[buf][c / CPR][VW * (c % CPR)]) = b[h];
     }
   };
-  // B tile: element e = slot j * BK + kk (BK consecutive samples per slot)
-  constexpr int BE = (BK * BN + BT_T - 1) / BT_T;
-  auto load_b = [&](int k0, double (&b)[BE]) {
+  acc_t acc[NB];
+  double acc64[F64 ? 1 : NB][4];
 #pragma unroll
-    for (int h = 0; h < BE; ++h) {
-      const int e = tid + h * BT_T;
-      const int j = e / BK, kk = e % BK;
-      b[h] = (e < BK * BN && j < bact_tile && k0 + kk < n) ? SB[(size_t)j * n + k0 + kk] : 0.0;
-    }
-  };
-  auto store_b = [&](int buf, const double (&b)[BE]) {
+  for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int h = 0; h < BE; ++h) {
-      const int e = tid + h * BT_T;
-      if (e < BK * BN) Bs[buf][e % BK][e / BK] = (T)b[h];
-    }
-  };
-  acc_t acc[2][NB];
-  double acc64[F64 ? 1 : 2][F64 ? 1 : NB][4];
-#pragma unroll
-  for (int j = 0; j < 2; ++j)
+    for (int v = 0; v < 4; ++v) acc[b][v] = (T)0;
+  if constexpr (!F64) {
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[j][b][v] = (T)0;
-  if constexpr (!F64) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc64[j][b][v] = 0.0;
+      for (int v = 0; v < 4; ++v) acc64[b][v] = 0.0;
   }
-  TD a_cur[BK_STEPS][2], a_nxt[BK_STEPS][2];
-  double bnext[BE];
-  load_a(0, a_cur);
+  // A is loaded two K tiles ahead into a ring of three register tiles
+  // (the loop is unrolled by three so the ring rotates without copies), B
+  // one tile ahead through the double-buffered LDS tile.  The loads are
+  // unconditional (past the last tile they repeat it), so every step has the
+  // same loads in flight, and each step issues B before A: B's wait at the
+  // end of the step then leaves the two A tiles ahead in flight.
+  // (The prologue leaves the loads in flight as every step does: the A
+  // tile of the step after next, nothing else.)
+  TD a0[BK_STEPS], a1[BK_STEPS], a2[BK_STEPS];
+  chunk_t bnext[BCH];
+  const int ntile = (n + BK - 1) / BK;
+  load_a(0, a0);
   load_b(0, bnext);
   store_b(0, bnext);
+  load_a(min(1, ntile - 1) * BK, a1);
   __syncthreads();
-  const int ntile = (n + BK - 1) / BK;
-  for (int t = 0; t < ntile; ++t) {
-    const int k0 = t * BK;
+  auto step = [&](int t, const TD (&a)[BK_STEPS], TD (&fill)[BK_STEPS]) {
     const int buf = t & 1;
-    const bool more = t + 1 < ntile;
-    if (more) {
-      load_a(k0 + BK, a_nxt);
-      load_b(k0 + BK, bnext);
-    }
-    if constexpr (!F64) {
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[j][b][v] = (T)0;
-    }
+    load_b(min(t + 1, ntile - 1) * BK, bnext);
+    load_a(min(t + 2, ntile - 1) * BK, fill);
 #pragma unroll
     for (int s = 0; s < BK_STEPS; ++s) {
       T bv[NB];
+      b_frag<T, NB>(&Bs[buf][4 * s + lk][NB * li], bv);
+      const T av = (T)a[s];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) bv[b] = Bs[buf][4 * s + lk][b * 16 + li];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const T av = (T)a_cur[s][j];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[j][b] = MfmaB<T>::op(av, bv[b], acc[j][b]);
-      }
+      for (int b = 0; b < NB; ++b) acc[b] = MfmaB<T>::op(av, bv[b], acc[b]);
     }
     if constexpr (!F64) {
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
+      if ((t + 1) % (BT_SUM / BK) == 0 || t + 1 == ntile) {
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc64[j][b][v] += (double)acc[j][b][v];
-    }
-    if (more) {
-      store_b(buf ^ 1, bnext);
-#pragma unroll
-      for (int s = 0; s < BK_STEPS; ++s) {
-        a_cur[s][0] = a_nxt[s][0];
-        a_cur[s][1] = a_nxt[s][1];
+          for (int v = 0; v < 4; ++v) {
+            acc64[b][v] += (double)acc[b][v];
+            acc[b][v] = 0.0f;
+          }
       }
     }
+    // (after the last tile this rewrites the other buffer, which nobody
+    // reads any more)
+    store_b(buf ^ 1, bnext);
     // the next tile's B is visible, and nobody reads this tile's buffer
     // after it is rewritten two tiles on
     __syncthreads();
+  };
+  int t = 0;
+  for (; t + 3 <= ntile; t += 3) {
+    step(t, a0, a2);
+    step(t + 1, a1, a0);
+    step(t + 2, a2, a1);
   }
+  if (t < ntile) step(t, a0, a2);
+  if (t + 1 < ntile) step(t + 1, a1, a0);
   const double mu = P.cs[s_p[0] >= 0 ? s_p[0] : 0].mu;
   const double sqmu = sqrt(mu);
-  // Epilogue, one group of 16 problems at a time: the group's BT_M x 16
-  // results are staged in LDS by (problem, row), then BT_LPP consecutive
-  // lanes walk the rows of one problem, so the FP64 d-vector loads and
-  // stores of a wave cover contiguous runs; each problem's partials are
-  // summed by its lanes in a fixed tree (the same for every tile width).
-  const int ej = tid / BT_LPP, er = tid % BT_LPP;
+  // Epilogue: the tile's 64 x 16 NB results are staged in LDS by (slot, row)
+  // (over the B buffers, free after the last barrier); then 16 consecutive
+  // threads take one slot's 64 rows in pairs (16-byte FP64 loads and stores
+  // of the d-vectors) and sum its partials in a fixed tree.
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
+  for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int v = 0; v < 4; ++v) {
+      double zs;
+      if constexpr (F64)
+        zs = acc[b][v];
+      else
+        zs = acc64[b][v];
+      Tz[NB * li + b][wid * 16 + MfmaB<T>::row(lane, v)] = zs;
+    }
+  __syncthreads();
+  // Groups of 16 slots, 16 threads per slot and two row pairs per thread,
+  // whatever NB is (so each slot's partials are summed in the same order for
+  // every tile width); the d-vector loads of all groups are issued first.
+  constexpr int EP = 2;                // row pairs per thread
+  const int eg = tid / 16, q = tid % 16;
+  nt_d2 rho2[NB][EP], u2[NB][EP];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double zs;
-        if constexpr (F64)
-          zs = acc[j][b][v];
-        else
-          zs = acc64[j][b][v];
-        Tz[li][wid * 32 + pass_b_row<T>(lane, v, j)] = zs;
+  for (int g = 0; g < NB; ++g) {
+    const int jj = g * 16 + eg;
+    if (s_live[jj]) {
+      const size_t od = (size_t)s_p[jj] * P.ld + m0;
+#pragma unroll
+      for (int i = 0; i < EP; ++i) {
+        const int r = 2 * (q + 16 * i);
+        rho2[g][i] = *reinterpret_cast<const nt_d2*>(P.RHO + od + r);
+        u2[g][i] = *reinterpret_cast<const nt_d2*>(P.U + od + r);
       }
-    __syncthreads();
-    const int jj = b * 16 + ej;
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NB; ++g) {
+    const int jj = g * 16 + eg;
     const int p = s_p[jj];
     const bool live = s_live[jj] != 0;
     double pw[NP2] = {0, 0, 0, 0, 0, 0};
@@ -632,33 +710,39 @@ k_pass_b(const TD* __restrict__ X, BatchPtrs P, const int* __restrict__ idx, int
       const double rs = s_tau[jj] * sigma * sqmu;
       const size_t od = (size_t)p * P.ld + m0;
 #pragma unroll
-      for (int i = 0; i < BT_M / BT_LPP; ++i) {
-        const int r = er + BT_LPP * i;
-        const double zs = Tz[ej][r];
-        const double rho = P.RHO[od + r];
-        const double bb = mu * P.U[od + r] + br * rho;
-        const double w = (bb - zs) / mu;
-        const double u = gamma * (w - gr * rho);
-        const double rn = rho - rs * (w - u);
-        P.W[od + r] = w;
-        P.U[od + r] = u;
-        P.RHO[od + r] = rn;
-        pw[0] += (w - u) * (w - u);
-        pw[1] += w * w;
-        pw[4] += rn * rn;
-        pw[5] += u * u;
+      for (int i = 0; i < EP; ++i) {
+        const int r = 2 * (q + 16 * i);
+        nt_d2 w2, un2, rn2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double zs = Tz[jj][r + h];
+          const double rho = rho2[g][i][h];
+          const double bb = mu * u2[g][i][h] + br * rho;
+          const double w = (bb - zs) / mu;
+          const double u = gamma * (w - gr * rho);
+          const double rn = rho - rs * (w - u);
+          w2[h] = w;
+          un2[h] = u;
+          rn2[h] = rn;
+          pw[0] += (w - u) * (w - u);
+          pw[1] += w * w;
+          pw[4] += rn * rn;
+          pw[5] += u * u;
+        }
+        *reinterpret_cast<nt_d2*>(P.W + od + r) = w2;
+        *reinterpret_cast<nt_d2*>(P.U + od + r) = un2;
+        *reinterpret_cast<nt_d2*>(P.RHO + od + r) = rn2;
       }
     }
 #pragma unroll
-    for (int q = 0; q < NP2; ++q)
+    for (int qq = 0; qq < NP2; ++qq)
 #pragma unroll
-      for (int o = BT_LPP / 2; o > 0; o >>= 1) pw[q] += __shfl_xor(pw[q], o, 64);
-    if (live && er == 0) {
+      for (int o = 8; o > 0; o >>= 1) pw[qq] += __shfl_xor(pw[qq], o, 64);
+    if (live && q == 0) {
 #pragma unroll
-      for (int q = 0; q < NP2; ++q)
-        P.part_g[((size_t)p * P.npb + blockIdx.x) * NP2 + q] = pw[q];
+      for (int qq = 0; qq < NP2; ++qq)
+        P.part_g[((size_t)p * P.npb + rt) * NP2 + qq] = pw[qq];
     }
-    __syncthreads();  // the next group reuses Tz
   }
 }
 
@@ -877,27 +961,32 @@ __global__ void __launch_bounds__(NTB) k_tail_b(BatchPtrs P, const int* __restri
 bool batch_ptrs_ok(const BatchPtrs& P) {
   const void* req[] = {P.y, P.my, P.Minv, P.G, P.R, P.XI, P.AL, P.PU, P.PR, P.T, P.XX, P.F,
                        P.S, P.V, P.DR, P.RN, P.S1, P.V1, P.XI0, P.XI1, P.AL0, P.AL1, P.HA,
-                       P.U, P.RHO, P.W, P.SB, P.part_n1, P.part_it, P.part_c, P.part_g,
+                       P.U, P.RHO, P.W, P.SB, P.SBf, P.part_n1, P.part_it, P.part_c, P.part_g,
                        P.part_ga, P.sc, P.cs};
   for (const void* q : req)
     if (!q) return false;
-  return P.ld % kLdAlign == 0;
+  // (K tile offsets into X and offsets into S are 32-bit)
+  return P.ld % kLdAlign == 0 && (P.ld / BT_M) % 8 == 0 && P.ld <= ((int64_t)1 << 23) &&
+         P.sbld % 64 == 0 && (int64_t)batch_sb_rows(P.n) * P.sbld * 8 < ((int64_t)1 << 32);
 }
 
 // The pass with a tile of 16 * tile slots per block (tile = 1, 2 or 4).
+// One-dimensional grid of (row tile, slot tile) pairs, grouped by XCD in
+// the kernel (the row tile count ld / 64 is a multiple of 8).
 template <int NB>
 static void pass_b_nb(const void* X, int storage, int fp64_mfma, const BatchPtrs& P,
                       const int* idx, int bact, hipStream_t st) {
-  const dim3 gp((unsigned)(P.ld / BT_M), (bact + 16 * NB - 1) / (16 * NB));
+  const int ny = (bact + 16 * NB - 1) / (16 * NB);
+  const dim3 gp((unsigned)(P.ld / BT_M * ny));
   if (storage == DWD_FP32 && !fp64_mfma)
     hipLaunchKernelGGL((k_pass_b<float, float, NB>), gp, dim3(BT_T), 0, st, (const float*)X, P,
-                       idx, bact);
+                       (const float*)P.SBf, idx, bact, ny);
   else if (storage == DWD_FP32)
     hipLaunchKernelGGL((k_pass_b<float, double, NB>), gp, dim3(BT_T), 0, st, (const float*)X, P,
-                       idx, bact);
+                       (const double*)P.SB, idx, bact, ny);
   else
     hipLaunchKernelGGL((k_pass_b<double, double, NB>), gp, dim3(BT_T), 0, st, (const double*)X,
-                       P, idx, bact);
+                       P, (const double*)P.SB, idx, bact, ny);
 }
 
 hipError_t launch_pass_b(const void* X, int storage, int fp64_mfma, const BatchPtrs& P,
@@ -920,7 +1009,9 @@ hipError_t launch_batch_iteration(const void* X, int storage, int fp64_mfma, con
   const dim3 gnm(nm_grid(P.n, bact));
   hipLaunchKernelGGL(k_s1ab_mm, gnm, dim3(NM_T), 0, st, P, idx, bact);
   hipLaunchKernelGGL(k_s1c_mm, gnm, dim3(NM_T), 0, st, P, idx, bact);
-  hipLaunchKernelGGL(k_plan_b, dim3(bact), dim3(256), 0, st, P, idx);
+  if (bact > P.sbld) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_plan_b, dim3(bact), dim3(256), 0, st, P, idx,
+                     storage == DWD_FP32 && !fp64_mfma ? 1 : 0);
   if (P.rep) {
     if (!P.AU || !P.ARHO || !P.AW || !P.CV || !P.part_gc || P.npg < (P.n + RB_T - 1) / RB_T)
       return hipErrorInvalidValue;
