@@ -493,7 +493,7 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
 hipError_t Problem::alloc_iter_buffers() {
   const int n_ = n;
   hipError_t e;
-  // 27 n-vectors
+  // 27 n-vectors (24 used)
   double* nb = nullptr;
   if ((e = alloc((void**)&nb, (size_t)n_ * 8 * 27)) != hipSuccess) return e;
   double* q = nb;
@@ -504,7 +504,7 @@ hipError_t Problem::alloc_iter_buffers() {
   take(ip.r); take(ip.xi); take(ip.alpha); take(ip.Pu); take(ip.Prho); take(ip.t); take(ip.x);
   take(ip.f); take(ip.s); take(ip.v); take(ip.dr); take(ip.hG); take(ip.rn); take(ip.s1);
   take(ip.v1); take(ip.xi0); take(ip.xi1); take(ip.al0); take(ip.al1);
-  take(ip.au); take(ip.arho); take(ip.aw);
+  take(ip.au); take(ip.arho); take(ip.aw); take(ip.au_n); take(ip.arho_n);
   double* db = nullptr;
   if ((e = alloc((void**)&db, (size_t)ld * 8 * 3)) != hipSuccess) return e;
   ip.u = db;

@@ -104,6 +104,7 @@ struct IterPtrs {
   double *r, *xi, *alpha, *Pu, *Prho, *t, *x, *f, *s, *v, *dr, *hG, *rn;
   double *s1, *v1, *xi0, *xi1, *al0, *al1;  // the two outcomes of Step 1c
   double *au, *arho, *aw;  // representer coefficients: u~ = Z~ au, rho = Z~ arho, w~ = Z~ aw
+  double *au_n, *arho_n;   // the representer step's new au, arho (the tail commits them)
   double *u, *rho, *w;  // d-space, length ld
   double *part_g;       // pass partials (NP2 per block)
   double *part_n1;      // Step 1b block partials of y^T dr

@@ -90,7 +90,8 @@ static hipError_t gemvT_t(const void* X, int64_t ld, int n, const double* v1, co
 bool iter_ptrs_ok(const IterPtrs& p) {
   const void* req[] = {p.y, p.my, p.Minv, p.G, p.r, p.xi, p.alpha, p.Pu, p.Prho, p.t, p.x,
                        p.f, p.s, p.v, p.dr, p.hG, p.rn, p.s1, p.v1, p.xi0, p.xi1, p.al0,
-                       p.al1, p.au, p.arho, p.aw, p.u, p.rho, p.w, p.part_g, p.part_n1,
+                       p.al1, p.au, p.arho, p.aw, p.au_n, p.arho_n, p.u, p.rho, p.w, p.part_g,
+                       p.part_n1,
                        p.part_it, p.part_c, p.partT, p.sc};
   for (const void* q : req)
     if (!q) return false;
@@ -647,7 +648,10 @@ hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterP
 // every d-space norm as a dot product of a coefficient vector with its image
 // under G~: ||Z~ a||^2 = a^T (G~ a).  The one n x n product per iteration is
 // G~ alpha' (for ||Z~ alpha'|| and ||Z~ alpha' + D rho'||).  One wave per
-// row; the block partials have the layout of the pass's (NP2).
+// row; the block partials have the layout of the pass's (NP2).  Every block
+// stages cv from the whole of au and arho, so the new coefficients go to
+// au_n and arho_n (committed by the tail): a block that starts after another
+// has finished still reads this iteration's au and arho.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void rep_step_body(const Consts& c, const IterPtrs& p) {
   Scal* sc = p.sc;
@@ -709,8 +713,8 @@ __device__ __forceinline__ void rep_step_body(const Consts& c, const IterPtrs& p
     const double ar1 = ar - rs * (aw - au1);
     const double pr1 = pr - rs * (gaw - pu1);
     p.aw[row] = aw;
-    p.au[row] = au1;
-    p.arho[row] = ar1;
+    p.au_n[row] = au1;
+    p.arho_n[row] = ar1;
     const double a = al[row];
     acc[0] = (aw - au1) * (gaw - pu1);           // ||w - u||^2
     acc[1] = aw * gaw;                           // ||w||^2
@@ -979,6 +983,12 @@ __device__ __forceinline__ void tail_body(const Consts& c, const IterPtrs& p, in
   const double sig1 = s_sigma;
   const double gr = 1.0 / (sigma * c.sqmu);
   const double rs = c.tau * sigma * c.sqmu;
+  // representer iteration: the coefficients the step wrote aside
+  if (c.representer)
+    for (int i = threadIdx.x; i < c.n; i += NTT) {
+      p.au[i] = p.au_n[i];
+      p.arho[i] = p.arho_n[i];
+    }
   // commit the outcome and form the next iteration's t and x
   auto commit = [&](int i, double rn, double xi, double al, double v, double s1, double yi,
                     double pr) {

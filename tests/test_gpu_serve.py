@@ -108,6 +108,39 @@ def test_serve_result_is_the_same_alone_and_in_the_mix(dwd):
     assert any(a2 < d1 and a1 < d2 for j, (a1, d1) in enumerate(iv) for (a2, d2) in iv[j + 1:])
 
 
+def test_serve_representer_mix_is_the_same_alone(dwd):
+    """The representer step reads every coefficient of its problem in every
+    block while each block updates its own rows; in a multi-problem launch a
+    small problem's blocks can run far apart, so the step must not read a
+    coefficient another block of the same launch already replaced.  A
+    small-n problem among large-n ones must follow exactly its lone
+    trajectory (and the plain representer solve)."""
+    specs = [  # (d, n, q, C, storage)
+        (20000, 60, 1.0, 0.25, "bf16"),
+        (4000, 1800, 2.0, 1.0, "f32"),
+        (3000, 2000, 1.0, 3.0, "f32"),
+        (6000, 1500, 2.0, 0.5, "bf16"),
+        (9000, 75, 1.0, 0.3, "f32"),
+    ]
+    reqs = []
+    for j, (d, n, q, C, storage) in enumerate(specs):
+        X, y = synth.random_two_class(d, n, seed=700 + j, mean=0.5, dtype="f32")
+        reqs.append(dict(X=X, y=y, t_arrival=0.0,
+                         params=dict(C=C, q=q, tol=1e-5, storage=storage, representer=1)))
+    mix = dwd.serve(reqs, iters_per_round=8)
+    for j, r in enumerate(reqs):
+        alone = dwd.serve([r], iters_per_round=8)[0]
+        m = mix[j]
+        assert m["status"] == 0 and alone["status"] == 0, (j, m["info"], alone["info"])
+        assert m["info"]["iters"] == alone["info"]["iters"], j
+        assert np.array_equal(m["w"], alone["w"]), j
+        p = r["params"]
+        P = dwd.Problem(r["X"], r["y"], storage=p["storage"])
+        single = P.solve(p["C"], p["q"], tol=p["tol"], want_state=False, representer=1)
+        P.close()
+        assert np.array_equal(single["w"], m["w"]), j
+
+
 def test_serve_matches_single_solves_and_oracle(dwd):
     reqs = _mixed_requests()[:3]
     res = dwd.serve(reqs)
