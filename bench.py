@@ -243,21 +243,26 @@ def serving_leg(dwd, torch, dev, count, tol, budget_gb=64.0, fixed_rate=30.0):
             reqs.append(dict(X=X, y=y))
         reqs[-1]["params"] = dict(C=r.C, q=r.q, tol=tol, storage=r.storage)
     torch.cuda.synchronize()
-    # plain per-request solves, one after another
-    t_plain = []
-    conv_plain = 0
-    for rq in reqs:
-        p = rq["params"]
-        t = time.perf_counter()
-        if "csr" in rq:
-            P = dwd.Problem(csr=rq["csr"], y=rq["y"], storage=p["storage"])
-        else:
-            P = dwd.Problem(rq["X"], rq["y"], storage=p["storage"])
-        res = P.solve(p["C"], p["q"], tol=tol, want_state=False)
-        P.close()
-        t_plain.append(time.perf_counter() - t)
-        conv_plain += res["info"]["converged"]
-    cap = len(reqs) / sum(t_plain)
+
+    def plain(rep):
+        """The requests solved one after another (set-up included)."""
+        ts, conv, nrep = [], 0, 0
+        for rq in reqs:
+            p = rq["params"]
+            t = time.perf_counter()
+            if "csr" in rq:
+                P = dwd.Problem(csr=rq["csr"], y=rq["y"], storage=p["storage"])
+            else:
+                P = dwd.Problem(rq["X"], rq["y"], storage=p["storage"])
+            res = P.solve(p["C"], p["q"], tol=tol, want_state=False, representer=rep)
+            P.close()
+            ts.append(time.perf_counter() - t)
+            conv += res["info"]["converged"]
+            nrep += res["info"]["representer"]
+        return len(reqs) / sum(ts), ts, conv, nrep
+
+    cap, t_plain, conv_plain, _ = plain(0)
+    cap_auto, t_plain_auto, conv_plain_auto, nrep_auto = plain(2)
     budget = budget_gb * (1 << 30)
 
     def replay(rate, rep=0):
@@ -276,13 +281,16 @@ def serving_leg(dwd, torch, dev, count, tol, budget_gb=64.0, fixed_rate=30.0):
         return {"solves_per_s": len(reqs) / el, "span_s": el,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "ok": sum(o["status"] == 0 for o in out),
-                "kkt_check_max": max(o["info"]["kkt_check"] for o in out)}
+                "kkt_check_max": max(o["info"]["kkt_check"] for o in out),
+                "representer_requests": sum(o["info"]["representer"] for o in out)}
 
-    lam = 0.75 * cap
-    at_075 = replay(lam)
-    at_fixed = replay(fixed_rate)
+    # latency under load with the per-request iteration choice (representer = 2)
+    lam = 0.75 * cap_auto
+    at_075 = replay(lam, rep=2)
+    at_fixed = replay(fixed_rate, rep=2)
     sat = replay(None)
     sat_rep = replay(None, rep=1)
+    sat_auto = replay(None, rep=2)
     kinds = {"dense_f32": 0, "dense_bf16": 0, "csr": 0}
     for r in base:
         kinds["csr" if r.layout == "csr" else "dense_" + r.storage] += 1
@@ -292,11 +300,18 @@ def serving_leg(dwd, torch, dev, count, tol, budget_gb=64.0, fixed_rate=30.0):
         "plain_solves_per_s": cap,
         "plain_p50_ms": float(np.percentile(np.array(t_plain) * 1e3, 50)),
         "converged_plain": conv_plain,
+        "plain_auto": {"solves_per_s": cap_auto, "converged": conv_plain_auto,
+                       "representer_requests": nrep_auto,
+                       "p50_ms": float(np.percentile(np.array(t_plain_auto) * 1e3, 50)),
+                       "rule": "representer iteration when 8 n^2 < Z bytes + 5 FP64 d-vectors"},
+        "latency_policy": "representer = 2 (per-request iteration form)",
         "arrival_rate_per_s": lam, "p50_ms": at_075["p50_ms"], "p99_ms": at_075["p99_ms"],
         "ok": at_075["ok"], "span_s": at_075["span_s"],
         "fixed_rate": dict(at_fixed, arrival_rate_per_s=fixed_rate),
         "saturated": dict(sat, gain_vs_plain=sat["solves_per_s"] / cap),
         "representer_saturated": dict(sat_rep, gain_vs_plain=sat_rep["solves_per_s"] / cap),
+        "auto_saturated": dict(sat_auto, gain_vs_plain=sat_auto["solves_per_s"] / cap,
+                               gain_vs_plain_auto=sat_auto["solves_per_s"] / cap_auto),
     }
     del reqs
     torch.cuda.empty_cache()

@@ -151,7 +151,13 @@ typedef struct {
                         end (w = Z~ a_w) and by the final FP64 check.  Same
                         iterates as 0 in exact arithmetic.  0 (default) = one
                         pass over Z per iteration.  BF16 storage is not used
-                        by the iteration in this mode.                         */
+                        by the iteration in this mode.  2 = choose per
+                        problem: the representer iteration when one more read
+                        of the n x n G~ (8 n^2 bytes) costs less than the pass
+                        it replaces (Z once in its storage type plus five
+                        FP64 d-vectors), else the pass; the SMW set-up only
+                        (the direct and iterative set-ups take 2 as 0).
+                        dwd_info.representer reports the choice.              */
   int32_t class_weights; /* 1: weight the loss term of sample i by tau_i^q, the
                         class weights of Section 4.5 (tau_i = tau_-/max(tau_+,
                         tau_-) for y_i = +1, tau_+/max(tau_+, tau_-) for
@@ -208,7 +214,7 @@ typedef struct {
   int32_t psqmr_switch; /* DWD_SOLVER_ITERATIVE: iteration from which the
                            proximal term of eq-T was used (0 with psqmr_max = 0);
                            -1 if PSQMR solved every system                     */
-  int32_t reserved;
+  int32_t representer;  /* the iteration form that ran: 1 representer, 0 pass   */
 } dwd_info;
 
 typedef struct dwd_problem_s* dwd_problem;

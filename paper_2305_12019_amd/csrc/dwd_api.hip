@@ -76,6 +76,8 @@ dwd_status validate_params(const dwd_params* p, bool for_solve) {
   if (p->batch_tile != 0 && p->batch_tile != 1 && p->batch_tile != 2 && p->batch_tile != 4)
     return fail(DWD_E_INVALID, "batch_tile must be 0, 1, 2 or 4");
   if (p->sigma_every < 1) return fail(DWD_E_INVALID, "sigma_every must be >= 1");
+  if (p->representer < 0 || p->representer > 2)
+    return fail(DWD_E_INVALID, "representer must be 0, 1 or 2");
   if (p->psqmr_max < 0 || p->psqmr_max > 100000)
     return fail(DWD_E_INVALID, "psqmr_max must be in [0, 100000]");
   if (p->class_weights != 0 && p->class_weights != 1)
@@ -557,6 +559,22 @@ hipError_t Problem::set_penalty(const double* eh) {
   return r;
 }
 
+// The iteration form (dwd_params.representer; 2 = by the bytes an iteration
+// moves): the representer iteration reads G~ once more (8 n^2 bytes) instead
+// of streaming Z (in the storage type of its main phase) and the five FP64
+// d-vectors of Steps 2-3.  Only the SMW set-up has the representer form.
+int choose_representer(const Problem* P, int req) {
+  if (P->solver != DWD_SOLVER_SMW) return 0;
+  if (req != 2) return req ? 1 : 0;
+  const double n = (double)P->n, ld = (double)P->ld;
+  double zbytes;
+  if (P->layout == DWD_CSR)
+    zbytes = (double)P->nnz * (4.0 + (P->csr_dtype == DWD_FP64 ? 8.0 : 4.0));
+  else
+    zbytes = ld * n * (P->storage == DWD_FP64 ? 8.0 : (P->storage == DWD_BF16 ? 2.0 : 4.0));
+  return 8.0 * n * n < zbytes + 5.0 * 8.0 * ld ? 1 : 0;
+}
+
 Consts make_consts(const Problem* P, const dwd_params* p) {
   Consts c;
   c.d = P->d;
@@ -582,7 +600,7 @@ Consts make_consts(const Problem* P, const dwd_params* p) {
   c.rho_residual = p->rho_residual ? 1 : 0;
   c.qkind = qkind_of(p->q);
   c.sigma_every = p->sigma_every;
-  c.representer = p->representer ? 1 : 0;
+  c.representer = choose_representer(P, p->representer);
   // Section 4.5: tau_+- = (n_+- / K)^(1/(1+q)), K = n / log(n); the loss term
   // of class +1 carries tau_-/max(tau_+, tau_-), of class -1
   // tau_+/max(tau_+, tau_-), raised to q.
@@ -886,6 +904,7 @@ dwd_status solve_problem(Problem* P, const dwd_params* p, double* w, dwd_info* i
     info->streamT_ms = stream_ms[1];
     info->streamT_launches = launches[1];
     info->resumed = resumed;
+    info->representer = c.representer;
     info->status = conv ? DWD_OK : DWD_NOT_CONVERGED;
   }
   return conv ? DWD_OK : DWD_NOT_CONVERGED;

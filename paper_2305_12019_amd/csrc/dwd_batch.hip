@@ -180,7 +180,7 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   bp.npb = batch_pass_row_blocks(ld);
   // Representer iteration (params[0].representer): no pass; the element
   // kernel writes the d-norm partials in blocks of 256 rows.
-  bp.rep = p[0].representer ? 1 : 0;
+  bp.rep = choose_representer(P, p[0].representer);
   bp.npg = bp.rep ? (n + 255) / 256 : bp.npb;
   const size_t nB = (size_t)n * B;
   double* nv = nullptr;
@@ -275,7 +275,7 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
   EvGuard guard{all_ev, 4};
   // Optional timing of every pass launch (params[0].profile): event pairs
   // around the Z~ [s_1..s_B] product, summed after the solve.
-  const bool profile = p[0].profile != 0 && !p[0].representer;  // (no pass to time)
+  const bool profile = p[0].profile != 0 && !bp.rep;  // (no pass to time)
   std::vector<hipEvent_t> pev;
   struct PoolGuard {
     std::vector<hipEvent_t>& v;
@@ -509,6 +509,7 @@ dwd_status solve_batch(Problem* P, int B, const dwd_params* p, double* W, dwd_in
       in.solve_ms = ms;
       in.status = conv ? DWD_OK : DWD_NOT_CONVERGED;
       in.resumed = resumed[j];
+      in.representer = bp.rep;
       in.stream_ms = pass_ms;  // all pass launches of the batch
       in.stream_launches = (int32_t)(pev.size() / 2);
       in.graph_launches = graph_launches;

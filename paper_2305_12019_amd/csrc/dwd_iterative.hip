@@ -325,7 +325,7 @@ dwd_status solve_iterative(Problem* P, const dwd_params* p, double* w, dwd_info*
   dwd_status s;
   if ((s = validate_params(p, true)) != DWD_OK) return s;
   if ((s = validate_penalty(p, P->n)) != DWD_OK) return s;
-  if (p->representer) return fail(DWD_E_INVALID, "the representer iteration needs the SMW set-up");
+  if (p->representer == 1) return fail(DWD_E_INVALID, "the representer iteration needs the SMW set-up");
   HIP_TRY_I(hipSetDevice(P->device));
   const hipStream_t st = P->stream;
   HIP_TRY_I(hipStreamSynchronize(st));

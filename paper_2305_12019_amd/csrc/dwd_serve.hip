@@ -253,6 +253,7 @@ void fill_info(const Live& s, dwd_info* info) {
   info->converged = conv;
   info->iters_lowp = s.iters_lowp;
   info->resumed = s.resumed;
+  info->representer = s.c.representer;
   info->setup_ms = s.P->setup_ms;
   info->status = conv ? DWD_OK : DWD_NOT_CONVERGED;
 }
@@ -269,7 +270,7 @@ dwd_status serve(const dwd_request* reqs, int nreq, const dwd_serve_opts* opts,
   for (int i = 0; i < nreq; ++i) {
     dwd_status s = validate_params(&reqs[i].params, true);
     if (s == DWD_OK) s = validate_penalty(&reqs[i].params, reqs[i].X.n);
-    if (s == DWD_OK && reqs[i].params.representer &&
+    if (s == DWD_OK && reqs[i].params.representer == 1 &&
         resolve_solver(&reqs[i].params, &reqs[i].X) == DWD_SOLVER_DIRECT)
       s = fail(DWD_E_INVALID, "the representer iteration needs the SMW set-up");
     if (s == DWD_OK && resolve_solver(&reqs[i].params, &reqs[i].X) == DWD_SOLVER_ITERATIVE)

@@ -169,6 +169,8 @@ dwd_status validate_params(const dwd_params* p, bool for_solve);
 // p->e, when given, must hold n positive finite values.
 dwd_status validate_penalty(const dwd_params* p, int64_t n);
 Consts make_consts(const Problem* P, const dwd_params* p);
+// iteration form for dwd_params.representer (0, 1, or 2 = by bytes moved)
+int choose_representer(const Problem* P, int req);
 // Constants of the BF16 phase: its own y^T M^-1 y and the looser tolerance.
 Consts lowp_consts(const Problem* P, const dwd_params* p);
 double default_sigma0(const dwd_params* p, int n);

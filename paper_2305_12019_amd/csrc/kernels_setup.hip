@@ -408,10 +408,19 @@ static hipError_t gemm(int m, int n, int k, double alpha, const double* A, int l
 constexpr int GJB = 32;  // pivot block width
 constexpr int GJT = 64;  // output tile edge of the panel and update kernels
 
+// One lane's double, read by the whole wave (lane p uniform).
+__device__ __forceinline__ double lane_value(double v, int p) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, p);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), p);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // P = A[K,K]^-1 by Gauss-Jordan in one wave: lane i < GJB holds row i of the
 // block in registers (rows beyond m are the identity; lanes >= GJB carry
-// identity rows that no result uses); the pivot row is broadcast by wave
-// shuffles.  Writes P into Pbuf (GJB x GJB, row-major) and -P into A[K,K].
+// identity rows that no result uses); the pivot row is read lane by lane
+// into scalar registers.  Writes P into Pbuf (GJB x GJB, row-major) and -P
+// into A[K,K].
 __global__ void __launch_bounds__(64) k_gj_pivot(double* __restrict__ M, int ld, int k0, int m,
                                                  double* __restrict__ Pbuf,
                                                  int* __restrict__ status) {
@@ -425,7 +434,7 @@ __global__ void __launch_bounds__(64) k_gj_pivot(double* __restrict__ M, int ld,
   for (int p = 0; p < GJB; ++p) {
     double rowp[GJB];
 #pragma unroll
-    for (int j = 0; j < GJB; ++j) rowp[j] = __shfl(a[j], p, 64);
+    for (int j = 0; j < GJB; ++j) rowp[j] = lane_value(a[j], p);
     const double piv = rowp[p];
     ok = ok && (piv > 0.0);
     const double ip = 1.0 / piv;

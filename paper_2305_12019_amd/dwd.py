@@ -63,7 +63,7 @@ class Info(C.Structure):
                 ("streamT_ms", C.c_double), ("streamT_launches", C.c_int32),
                 ("graph_launches", C.c_int32), ("psqmr_steps", C.c_int32),
                 ("psqmr_solves", C.c_int32), ("psqmr_switch", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("representer", C.c_int32)]
 
     def to_dict(self) -> Dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}

@@ -141,6 +141,35 @@ def test_serve_representer_mix_is_the_same_alone(dwd):
         assert np.array_equal(single["w"], m["w"]), j
 
 
+def test_auto_iteration_form_follows_the_byte_rule(dwd):
+    """representer = 2 picks the representer iteration when one more read of
+    the n x n G~ (8 n^2 bytes) costs less than the pass it replaces (Z in its
+    storage type plus five FP64 d-vectors), and then runs exactly the chosen
+    form, in dwd_solve and in dwd_serve."""
+    cases = [(20000, 100, "f32"), (1500, 1400, "f32"), (3000, 700, "bf16")]
+    reqs = []
+    for j, (d, n, storage) in enumerate(cases):
+        ld = (d + 1023) // 1024 * 1024
+        es = {"f32": 4, "bf16": 2}[storage]
+        want = 1 if 8 * n * n < ld * n * es + 40 * ld else 0
+        X, y = synth.random_two_class(d, n, seed=900 + j, mean=0.5, dtype="f32")
+        P = dwd.Problem(X, y, storage=storage)
+        auto = P.solve(1.0, 1.0, tol=1e-5, want_state=False, representer=2)
+        same = P.solve(1.0, 1.0, tol=1e-5, want_state=False, representer=want)
+        P.close()
+        assert auto["info"]["representer"] == want, (d, n, storage)
+        assert auto["info"]["converged"] == 1
+        assert np.array_equal(auto["w"], same["w"]), (d, n, storage)
+        reqs.append(dict(X=X, y=y, t_arrival=0.0,
+                         params=dict(C=1.0, q=1.0, tol=1e-5, storage=storage, representer=2),
+                         want=want, w=same["w"]))
+    assert {r["want"] for r in reqs} == {0, 1}
+    out = dwd.serve(reqs, iters_per_round=8)
+    for r, o in zip(reqs, out):
+        assert o["status"] == 0 and o["info"]["representer"] == r["want"]
+        assert np.array_equal(o["w"], r["w"])
+
+
 def test_serve_matches_single_solves_and_oracle(dwd):
     reqs = _mixed_requests()[:3]
     res = dwd.serve(reqs)
