@@ -497,6 +497,9 @@ def main():
     ap.add_argument("--no-iterative", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration) and one solve")
+    ap.add_argument("--batch-probe", action="store_true",
+                    help="run only a 1 GiB device copy and the 64-problem sweep of the batched "
+                         "leg for 24 iterations (counters of the batched pass)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver runs on one GPU; runs on several GPUs are not "
@@ -517,15 +520,22 @@ def main():
     d, n = wl.data.d, wl.data.n
     ld = ((d + 1023) // 1024) * 1024
 
-    if args.copy_probe:
-        # counter calibration: a plain copy of known size, then one solve
+    if args.copy_probe or args.batch_probe:
+        # counter calibration: a plain copy of known size, then one solve (or
+        # the batched sweep, every problem running for 24 iterations)
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
-        r = dwd.Problem(Xd, y, storage="f32").solve(wl.C, wl.q, tol=wl.tol, want_state=False)
-        print(json.dumps({"copy_bytes": 2 * a.numel() * 4, "iters": r["info"]["iters"]}),
-              flush=True)
+        P = dwd.Problem(Xd, y, storage="f32")
+        if args.batch_probe:
+            r = P.solve_batch([dict(C=C, q=q, tol=wl.tol, max_iter=24)
+                               for C, q in synth.sweep_grid()])
+            iters = sum(i["iters"] for i in r["info"])
+        else:
+            iters = P.solve(wl.C, wl.q, tol=wl.tol, want_state=False)["info"]["iters"]
+        P.close()
+        print(json.dumps({"copy_bytes": 2 * a.numel() * 4, "iters": iters}), flush=True)
         return
 
     def step(profile, representer=0):

@@ -383,9 +383,11 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
 #pragma unroll
   for (int j = 0; j < KS; ++j) ssum[j] = 0.0;
   __shared__ double lds_red[4];
-  // the group's next sample is loaded while the current one is processed
-  // (its dot product, the Step 1b-3 scalar work and the accumulation)
-  auto load_sample = [&](int i, T (&xv)[NF][4]) {
+  // the group's next sample (its row of X and its n-vector entries) is
+  // loaded while the current one is processed (its dot product, the Step
+  // 1b-3 scalar work and the accumulation)
+  constexpr int NS = MODE == 1 ? 4 : (MODE == 2 ? 5 : 0);
+  auto load_sample = [&](int i, T (&xv)[NF][4], double (&sv)[NS > 0 ? NS : 1]) {
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
       const int64_t f = 4 * (int64_t)(lg + j * TPS);
@@ -396,9 +398,23 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
         for (int q = 0; q < 4; ++q) xv[j][q] = (T)0;
       }
     }
+    if constexpr (NS > 0) {
+      const bool in = i < i1;
+      sv[0] = in ? p.y[i] : 0.0;
+      sv[1] = in ? p.alpha[i] : 0.0;
+      if constexpr (MODE == 1) {
+        sv[2] = in ? p.r[i] : 0.0;
+        sv[3] = in ? p.xi[i] : 0.0;
+      } else {
+        sv[2] = in ? p.zb[i] : 0.0;
+        sv[3] = in ? p.rn[i] : 0.0;
+        sv[4] = in ? p.e[i] : 0.0;
+      }
+    }
   };
   T xnext[NF][4];
-  load_sample(i0 + g, xnext);
+  double snext[NS > 0 ? NS : 1];
+  load_sample(i0 + g, xnext, snext);
   for (int ib = i0; ib < i1; ib += G) {
     const int i = ib + g;
     const bool live = i < i1;
@@ -407,7 +423,10 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
     for (int j = 0; j < NF; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) xv[j][q] = xnext[j][q];
-    load_sample(i + G, xnext);
+    double sv[NS > 0 ? NS : 1];
+#pragma unroll
+    for (int j = 0; j < (NS > 0 ? NS : 1); ++j) sv[j] = snext[j];
+    load_sample(i + G, xnext, snext);
     double cf0 = 1.0, cf1 = 0.0;
     if constexpr (MODE != 0) {
       double dot = 0.0;
@@ -418,19 +437,15 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
           for (int q = 0; q < 4; ++q) dot = fma((double)xv[j][q], wv[j][q], dot);
         dot = group_sum<TPS>(dot, lds_red);
       }
-      double yi = 0.0, al = 0.0;
-      if (live) {
-        yi = p.y[i];
-        al = p.alpha[i];
-      }
+      const double yi = sv[0], al = sv[1];
       // A group that spans several waves (TPS = 256): every wave has read
-      // alpha_i before the group leader overwrites it in sweep 2.
+      // alpha_i (a step ago) before the group leader overwrites it in sweep 2.
       if constexpr (MODE == 2 && TPS > 64) __syncthreads();
       if (live) {
         if constexpr (MODE == 1) {
           const double z = yi * dot * c.inv_zs;
-          const double r0 = p.r[i];
-          const double cc = z + yi * beta + p.xi[i] - al / sigma;
+          const double r0 = sv[2];
+          const double cc = z + yi * beta + sv[3] - al / sigma;
           int steps = 0;
           const double rn = prox_weighted(cc, sigma, r0, tolN, loss_weight(c, yi), c, steps);
           const double dr = rn - r0;
@@ -443,9 +458,9 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
             ssum[1] = fmax(ssum[1], (double)steps);
           }
         } else {
-          const double z = redo ? yi * dot * c.inv_zs : p.zb[i];
-          const double rn = p.rn[i];
-          const double ei = p.e[i];
+          const double z = redo ? yi * dot * c.inv_zs : sv[2];
+          const double rn = sv[3];
+          const double ei = sv[4];
           const double xin = fmax(0.0, rn - z - yi * beta + (al - c.C * ei) / sigma);
           const double pres = z + yi * beta + xin - rn;
           const double a1 = al - c.tau * sigma * pres;
