@@ -189,6 +189,24 @@ def test_batch_representer_matches_oracle_and_single_representer(dwd):
     P.close()
 
 
+def test_batch_auto_iteration_form(dwd):
+    """representer = 2 in dwd_solve_batch takes the form the byte rule gives
+    for the shared X (the representer iteration when 8 n^2 is below the
+    pass's bytes) and then runs exactly that form."""
+    for d, n, want in ((12000, 150, 1), (1500, 1400, 0)):
+        ld = (d + 1023) // 1024 * 1024
+        assert (1 if 8 * n * n < ld * n * 4 + 40 * ld else 0) == want
+        X, y = synth.random_two_class(d, n, seed=31 + n, mean=0.6, dtype="f32")
+        grid = [(0.5, 1.0), (2.0, 2.0), (1.0, 0.5)]
+        P = dwd.Problem(X, y, storage="f32")
+        auto = P.solve_batch([dict(C=C, q=q, tol=1e-6, representer=2) for C, q in grid])
+        same = P.solve_batch([dict(C=C, q=q, tol=1e-6, representer=want) for C, q in grid])
+        P.close()
+        assert np.array_equal(auto["W"], same["W"]), (d, n)
+        for i in auto["info"]:
+            assert i["representer"] == want and i["converged"] == 1, (d, n, i)
+
+
 def test_batch_representer_sweep_full_size(dwd):
     X, y = synth.two_class(synth.SWEEP_DATA)
     P = dwd.Problem(X, y, storage="f32")
