@@ -152,6 +152,10 @@ static void release(Problem* P) {
 hipError_t Problem::host_objects() {
   hipError_t e;
   if ((e = hipHostMalloc((void**)&h_flags, 4096, 0)) != hipSuccess) return e;
+  // the tail kernel of the n-space solver sets this word when it stops
+  void* dflags = nullptr;
+  if ((e = hipHostGetDevicePointer(&dflags, h_flags, 0)) != hipSuccess) return e;
+  ip.hdone = ip_lp.hdone = (int32_t*)dflags + kHostDoneWord;
   if ((e = hipEventCreate(&ev_a)) != hipSuccess) return e;
   if ((e = hipEventCreate(&ev_b)) != hipSuccess) return e;
   for (auto& ev : ev_chunk)
@@ -517,6 +521,7 @@ hipError_t Problem::alloc_iter_buffers() {
   // partials of the pass (FP64 has the most blocks) or of the representer step
   const int npb = std::max({pass2_blocks(DWD_FP64, ld), csr_pass_blocks(ld), ngemv_blocks(n_), 1});
   if ((e = alloc((void**)&ip.part_g, (size_t)npb * NP2 * 8)) != hipSuccess) return e;
+  ip.pg_ld = npb;
   if ((e = alloc((void**)&ip.part_n1, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
   if ((e = alloc((void**)&ip.part_it, (size_t)ngemv_blocks(n_) * 8)) != hipSuccess) return e;
   if ((e = alloc((void**)&ip.part_c, (size_t)ngemv_blocks(n_) * NPC * 8)) != hipSuccess) return e;
@@ -747,8 +752,13 @@ hipError_t Problem::run_loop(const Consts& c, const void* Xit, int st_it, int re
   const int chunk = std::max(1, check_every);
   const int ev_first = ev_used;
   int queued = 0;
-  int pending = -1;  // index of the chunk whose flag is in flight
-  volatile int32_t* hf = (volatile int32_t*)h_flags;
+  int pending = -1;  // index of the chunk last queued before this one
+  // The tail kernel sets the pinned word when it sets the stop flag; every
+  // earlier launch on the stream is done (and its writes visible) once a
+  // chunk's event has completed.  Nothing writes the word while the host
+  // clears it: the stream is idle between solve phases.
+  volatile int32_t* hd = (volatile int32_t*)h_flags + kHostDoneWord;
+  *hd = 0;
   hipError_t e;
   for (int cidx = 0;; ++cidx) {
     for (int j = 0; j < chunk && k_start + queued < c.max_iter; ++j, ++queued) {
@@ -756,16 +766,12 @@ hipError_t Problem::run_loop(const Consts& c, const void* Xit, int st_it, int re
       const bool fresh = (queued == 0) || (resync > 0 && (k % resync) == 0);
       if ((e = queue_iteration(c, Xit, st_it, fresh, profile, k)) != hipSuccess) return e;
     }
-    // flag copy for this chunk
     const int slot = cidx & 1;
-    if ((e = hipMemcpyAsync((void*)(hf + slot * 16), &ip.sc->done, 4, hipMemcpyDeviceToHost,
-                            stream)) != hipSuccess)
-      return e;
     if ((e = hipEventRecord(ev_chunk[slot], stream)) != hipSuccess) return e;
     if (k_start + queued >= c.max_iter) break;
     if (pending >= 0) {
       if ((e = hipEventSynchronize(ev_chunk[pending & 1])) != hipSuccess) return e;
-      if (hf[(pending & 1) * 16]) break;
+      if (*hd) break;
     }
     pending = cidx;
   }

@@ -203,6 +203,38 @@ __device__ __forceinline__ void wave_row_dot2(const double* __restrict__ a,
   rb = wave_sum(sb);
 }
 
+// Three dot products with x by one wave (two matrix rows and one n-vector),
+// every load of the three issued in one round.  With the same vector as c
+// in every wave, each wave forms c^T x in the same fixed order, so a value
+// that every row needs comes without a block reduction.
+__device__ __forceinline__ void wave_row_dot3(const double* __restrict__ a,
+                                              const double* __restrict__ b,
+                                              const double* __restrict__ cv,
+                                              const double* __restrict__ x, int n, int lane,
+                                              double& ra, double& rb, double& rc) {
+  double sa = 0.0, sb = 0.0, sc = 0.0;
+  for (int base = 0; base < n; base += 64 * CH) {
+    double av[CH], bv[CH], cw[CH], xv[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int j = base + q * 64 + lane;
+      av[q] = j < n ? a[j] : 0.0;
+      bv[q] = j < n ? b[j] : 0.0;
+      cw[q] = j < n ? cv[j] : 0.0;
+      xv[q] = j < n ? x[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      sa = fma(av[q], xv[q], sa);
+      sb = fma(bv[q], xv[q], sb);
+      sc = fma(cw[q], xv[q], sc);
+    }
+  }
+  ra = wave_sum(sa);
+  rb = wave_sum(sb);
+  rc = wave_sum(sc);
+}
+
 
 // a^(q/(q+1)) for a > 0: sqrt for q = 1, cube roots for q = 2 and 0.5
 __device__ __forceinline__ double pow_qexp(double a, const Consts& c) {
@@ -316,15 +348,15 @@ __device__ __forceinline__ double stop_and_sigma(const Consts& c, const double* 
 // Block partials that decide Step 1c and size the Step 2 ball scaling:
 // 0: dr^T G~ dr, 1: y^T dr, 2/3: s^T G~ s and (Z~^T u)^T s of outcome 0,
 // 4/5: the same for outcome 1.
-__device__ __forceinline__ double plan_part(const IterPtrs& p, int q, int b) {
-  const double* r = p.part_c + (size_t)b * NPC;
+__device__ __forceinline__ double plan_part(const IterPtrs& p, int q, int b, int nb) {
+  const double* r = p.part_c + b;
   switch (q) {
     case 0: return r[0];
     case 1: return p.part_n1[b];
-    case 2: return r[1 + 9];
-    case 3: return r[1 + 10];
-    case 4: return r[1 + NPO + 9];
-    default: return r[1 + NPO + 10];
+    case 2: return r[(size_t)(1 + 9) * nb];
+    case 3: return r[(size_t)(1 + 10) * nb];
+    case 4: return r[(size_t)(1 + NPO + 9) * nb];
+    default: return r[(size_t)(1 + NPO + 10) * nb];
   }
 }
 
@@ -336,7 +368,7 @@ __device__ __forceinline__ void plan_sums(const IterPtrs& p, int nb, double (&a)
   for (int j = 0; j < 6; ++j) a[j] = 0.0;
   for (int b = threadIdx.x; b < nb; b += NT) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) a[j] += plan_part(p, j, b);
+    for (int j = 0; j < 6; ++j) a[j] += plan_part(p, j, b, nb);
   }
   block_sum_k<NT, 6>(a);
 }

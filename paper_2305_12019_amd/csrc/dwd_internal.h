@@ -106,12 +106,16 @@ struct IterPtrs {
   double *au, *arho, *aw;  // representer coefficients: u~ = Z~ au, rho = Z~ arho, w~ = Z~ aw
   double *au_n, *arho_n;   // the representer step's new au, arho (the tail commits them)
   double *u, *rho, *w;  // d-space, length ld
-  double *part_g;       // pass partials (NP2 per block)
+  // Block partials are stored slot-major, so that a reader summing one slot
+  // over the blocks reads contiguous memory.
+  double *part_g;       // pass partials: slot j of block b at part_g[j * pg_ld + b]
   double *part_n1;      // Step 1b block partials of y^T dr
   double *part_it;      // Step 1b block maxima of Newton steps
-  double *part_c;       // Step 1c block partials (NPC per block)
+  double *part_c;       // Step 1c partials: slot j of block b at part_c[j * ngemv_blocks(n) + b]
   double *partT;        // GEMV-T partials: [chunks][2][n]
   Scal* sc;
+  int32_t* hdone;       // pinned host word set to 1 with the stop flag (nullptr: none)
+  int pg_ld;            // blocks per slot of part_g (the most blocks any pass launches)
 };
 
 // Pointers of a batch of B problems over one shared X.  n-space arrays are

@@ -76,6 +76,11 @@ struct DeviceArena {
   virtual ~DeviceArena() {}
 };
 
+// Word of Problem::h_flags that the n-space solver's tail kernel sets when it
+// stops.  Words 0 and 16 take the direct and iterative solvers' copies of
+// their flags, words 64 on the iterative solver's scalars.
+constexpr int kHostDoneWord = 48;
+
 struct Problem {
   int device = 0;
   DeviceArena* arena = nullptr;  // buffers from this pool (serving), else hipMalloc
@@ -116,7 +121,7 @@ struct Problem {
   IterPtrs ip{};
   IterPtrs ip_lp{};
   int nchunks = 0;
-  void* h_flags = nullptr;     // pinned host words for stop flags
+  void* h_flags = nullptr;     // pinned host words for stop flags (see kHostDoneWord)
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   hipEvent_t ev_chunk[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> ev_pool;

@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(CSR_T) k_csr_pass(const int64_t* __restrict__ 
     acc[5] = u * u;
   }
   block_sum_k<CSR_T, NP2>(acc);
-  if (threadIdx.x < NP2) p.part_g[(size_t)blockIdx.x * NP2 + threadIdx.x] = acc[threadIdx.x];
+  if (threadIdx.x < NP2) p.part_g[(size_t)threadIdx.x * p.pg_ld + blockIdx.x] = acc[threadIdx.x];
 }
 
 // Expansion of the representer coefficients over CSR(X): w~ = Z~ aw,
@@ -253,6 +253,7 @@ hipError_t launch_csr_pass(const int64_t* ip, const int32_t* ix, const void* val
                            int64_t d, const Consts& c, const IterPtrs& p, hipStream_t st) {
   if (!ip || !ix || !val) return hipErrorInvalidValue;
   const int nb = csr_pass_blocks(c.ld);
+  if (nb > p.pg_ld) return hipErrorInvalidValue;
   if (dtype == DWD_FP64)
     hipLaunchKernelGGL(k_csr_pass<double>, dim3(nb), dim3(CSR_T), 0, st, ip, ix,
                        (const double*)val, d, c, p);

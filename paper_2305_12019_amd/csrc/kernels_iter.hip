@@ -95,7 +95,7 @@ bool iter_ptrs_ok(const IterPtrs& p) {
                        p.part_it, p.part_c, p.partT, p.sc};
   for (const void* q : req)
     if (!q) return false;
-  return true;
+  return p.pg_ld >= 1;
 }
 
 hipError_t launch_gemvT(const void* X, int storage, int64_t ld, int n, const double* v1,
@@ -255,8 +255,9 @@ hipError_t launch_ngemv(int n, const double* A1, const double* x1, double* o1, c
 // ---------------------------------------------------------------------------
 // Step 1a (solve) fused with Step 1b (prox).  One wave per row i:
 //   f_i = (M^-1 x)_i,  beta_bar = -y^T M^-1 x / y^T M^-1 y = -(M^-1 y)^T x / y^T M^-1 y
-// (M^-1 is symmetric, so every block forms beta_bar from x directly, in the
-// same order), s_bar = f + beta_bar M^-1 y, v_bar = s_bar - t,
+// (M^-1 is symmetric, so every wave forms beta_bar from x directly, with the
+// loads of its row and in the same order), s_bar = f + beta_bar M^-1 y,
+// v_bar = s_bar - t,
 // c = v_bar + xi - alpha/sigma, r^{k+1}_i = prox(c_i), dr = r^{k+1} - r^k.
 // Block partials: y^T dr and the most Newton steps.
 // ---------------------------------------------------------------------------
@@ -283,11 +284,9 @@ __device__ __forceinline__ void step1ab_body(const Consts& c, const IterPtrs& p)
   const double sigma = sc->sigma;
   const int kk = sc->k;
   if (done) return;
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < c.n; j += 256) acc = fma(p.my[j], p.x[j], acc);
-  double f = 0.0;
-  if (row < c.n) f = wave_row_dot(p.Minv + (size_t)row * c.n, p.x, c.n, lane);
-  const double beta_bar = -bsum<256>(acc) / c.ymy;
+  double f = 0.0, mx = 0.0;
+  if (row < c.n) wave_row_dot2(p.Minv + (size_t)row * c.n, p.my, p.x, c.n, lane, f, mx);
+  const double beta_bar = -mx / c.ymy;
   double ydr = 0.0;
   int steps = 0;
   if (mine) {
@@ -324,7 +323,8 @@ hipError_t launch_step1ab(const Consts& c, const IterPtrs& p, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Step 1c, row-parallel.  One wave per row i forms (G~ dr)_i and (M^-1 dr)_i.
+// Step 1c, row-parallel.  One wave per row i forms (G~ dr)_i and (M^-1 dr)_i,
+// and with the same round of loads (M^-1 y)^T dr.
 // The test ||h - A [wbar; betabar]||^2 = dr^T G~ dr + (y^T dr)^2 <= (5 eps_k)^2
 // needs a global sum, so each row prepares both outcomes:
 //   0: keep Step 1a's solution:  s0 = s_bar = M^-1 (x + beta_bar y), v0 = v_bar;
@@ -338,7 +338,7 @@ hipError_t launch_step1ab(const Consts& c, const IterPtrs& p, hipStream_t st) {
 // (g = w - rho/(sigma sqrt(mu)) = u - Z~ s_o / mu), where
 // G~ s_o = mu (x_o + beta_o y - s_o) because G~ M^-1 = mu (I - M^-1).
 // The consumers take the decision from the same fixed-order sums.
-// part_c[b*NPC + 0] = block sum of dr_i (G~ dr)_i; [1 + o*NPO + j] outcome o.
+// Slot 0 of part_c = block sum of dr_i (G~ dr)_i; slot 1 + o*NPO + j outcome o.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void step1c_body(const Consts& c, const IterPtrs& p) {
   Scal* sc = p.sc;
@@ -366,12 +366,10 @@ __device__ __forceinline__ void step1c_body(const Consts& c, const IterPtrs& p) 
   const double sigma = sc->sigma;
   const double beta_bar = sc->beta_bar;
   if (done) return;
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < c.n; j += 256) acc = fma(p.my[j], p.dr[j], acc);
-  double hg = 0.0, hm = 0.0;
+  double hg = 0.0, hm = 0.0, mdr = 0.0;
   if (row < c.n)
-    wave_row_dot2(p.G + (size_t)row * c.n, p.Minv + (size_t)row * c.n, p.dr, c.n, lane, hg, hm);
-  const double mdr = bsum<256>(acc);
+    wave_row_dot3(p.G + (size_t)row * c.n, p.Minv + (size_t)row * c.n, p.my, p.dr, c.n, lane, hg,
+                  hm, mdr);
   const double beta1 = beta_bar + mdr / c.ymy;
   double out[NPC];
 #pragma unroll
@@ -415,7 +413,8 @@ __device__ __forceinline__ void step1c_body(const Consts& c, const IterPtrs& p) 
   __syncthreads();
   if (threadIdx.x < NPC) {
     const int j = threadIdx.x;
-    p.part_c[(size_t)blockIdx.x * NPC + j] = (wsum[0][j] + wsum[1][j]) + (wsum[2][j] + wsum[3][j]);
+    p.part_c[(size_t)j * ngemv_blocks(c.n) + blockIdx.x] =
+        (wsum[0][j] + wsum[1][j]) + (wsum[2][j] + wsum[3][j]);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->beta1 = beta1;
 }
@@ -462,32 +461,46 @@ __device__ __forceinline__ void pass2_body(const T* __restrict__ X, const Consts
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t rbase = (int64_t)blockIdx.x * ROWS;
   const T* xrow = X + rbase + lane * V;
-  // Everything the prologue needs is requested before anything waits: the
-  // first four columns of this wave's share of the first panel, the rows'
-  // u and rho for the epilogue, the plan partials and the staged operand.
-  typename Vec<T>::raw_t pf[4];
-  const int per0 = (min(PANEL, c.n) + NW - 1) / NW;
-  const int pj0 = wid * per0, pj1 = min(min(PANEL, c.n), pj0 + per0);
-  const bool have_pf = pj0 + 4 <= pj1;
-  if (have_pf) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) pf[u] = Vec<T>::raw(xrow + (int64_t)(pj0 + u) * c.ld);
-  }
-  double u_in[RPT], rho_in[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int rr = threadIdx.x + q * NT;
-    u_in[q] = rr < ROWS ? p.u[rbase + rr] : 0.0;
-    rho_in[q] = rr < ROWS ? p.rho[rbase + rr] : 0.0;
-  }
+  // Everything the prologue needs is requested before anything waits, the
+  // loads that hit the caches first: the plan partials and the first panel's
+  // operand (so that staging and the plan wait only for these), then the
+  // first four columns of this wave's share of the first panel and the rows'
+  // u and rho for the epilogue.  Every load is unconditional (clamped
+  // indexes, the surplus discarded), which keeps the waits counted exactly.
   const int nb = ngemv_blocks(c.n);
   const bool few = nb <= RB * NT;
   double raw[RB][6];
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
-    const int b = threadIdx.x + r * NT;
+    const int b = min(threadIdx.x + r * NT, nb - 1);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) raw[r][j] = (few && b < nb) ? plan_part(p, j, b) : 0.0;
+    for (int j = 0; j < 6; ++j) raw[r][j] = plan_part(p, j, b, nb);
+  }
+  constexpr int SPT = PANEL / NT;  // first-panel entries staged per thread
+  const int pn0 = min(PANEL, c.n);
+  double sy[SPT], ss0[SPT], ss1[SPT], sa0[SPT], sa1[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int i = min((int)threadIdx.x + q * NT, pn0 - 1);
+    sy[q] = p.y[i];
+    ss0[q] = p.s[i];
+    ss1[q] = p.s1[i];
+    sa0[q] = p.al0[i];
+    sa1[q] = p.al1[i];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  typename Vec<T>::raw_t pf[4];
+  const int per0 = (pn0 + NW - 1) / NW;
+  const int pj0 = wid * per0, pj1 = min(pn0, pj0 + per0);
+  const bool have_pf = pj0 + 4 <= pj1;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) pf[u] = Vec<T>::raw(xrow + (int64_t)min(pj0 + u, c.n - 1) * c.ld);
+  double u_in[RPT], rho_in[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int rr = min((int)threadIdx.x + q * NT, ROWS - 1);
+    u_in[q] = p.u[rbase + rr];
+    rho_in[q] = p.rho[rbase + rr];
   }
   const int k_it = p.sc->k;
   const double u2 = p.sc->u2;
@@ -501,7 +514,17 @@ __device__ __forceinline__ void pass2_body(const T* __restrict__ X, const Consts
       lds[3 * PANEL + i] = yz * p.al1[pc + i];
     }
   };
-  stage(0, min(PANEL, c.n));
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < pn0) {
+      const double yz = sy[q] * c.inv_zs;
+      lds[i] = yz * ss0[q];
+      lds[PANEL + i] = yz * ss1[q];
+      lds[2 * PANEL + i] = yz * sa0[q];
+      lds[3 * PANEL + i] = yz * sa1[q];
+    }
+  }
   double a[6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) a[j] = 0.0;
@@ -509,11 +532,12 @@ __device__ __forceinline__ void pass2_body(const T* __restrict__ X, const Consts
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int j = 0; j < 6; ++j) a[j] += raw[r][j];
+      for (int j = 0; j < 6; ++j)
+        if (threadIdx.x + r * NT < nb) a[j] += raw[r][j];
   } else {
     for (int b = threadIdx.x; b < nb; b += NT)
 #pragma unroll
-      for (int j = 0; j < 6; ++j) a[j] += plan_part(p, j, b);
+      for (int j = 0; j < 6; ++j) a[j] += plan_part(p, j, b, nb);
   }
   block_sum_k<NT, 6>(a);  // also orders the staging writes before their reads
   const Step2Plan pl = step2_plan_finish(c, a, k_it, u2);
@@ -605,7 +629,7 @@ __device__ __forceinline__ void pass2_body(const T* __restrict__ X, const Consts
     acc[5] += u * u;
   }
   block_sum_k<NW * 64, NP2>(acc);
-  if (threadIdx.x < NP2) p.part_g[(size_t)blockIdx.x * NP2 + threadIdx.x] = acc[threadIdx.x];
+  if (threadIdx.x < NP2) p.part_g[(size_t)threadIdx.x * p.pg_ld + blockIdx.x] = acc[threadIdx.x];
 }
 
 template <typename T, int NW>
@@ -627,6 +651,7 @@ hipError_t launch_pass2(const void* X, int storage, const Consts& c, const IterP
                         hipStream_t st) {
   if (!X || !iter_ptrs_ok(p) || c.ld % kLdAlign != 0) return hipErrorInvalidValue;
   const int nb = pass2_blocks(storage, c.ld);
+  if (nb > p.pg_ld) return hipErrorInvalidValue;
   if (storage == DWD_FP64)
     hipLaunchKernelGGL((k_pass2<double, 4>), dim3(nb), dim3(256), 0, st, (const double*)X, c, p);
   else if (storage == DWD_FP32)
@@ -730,14 +755,14 @@ __device__ __forceinline__ void rep_step_body(const Consts& c, const IterPtrs& p
   __syncthreads();
   if (threadIdx.x < NP2) {
     const int j = threadIdx.x;
-    p.part_g[(size_t)blockIdx.x * NP2 + j] = (ws[0][j] + ws[1][j]) + (ws[2][j] + ws[3][j]);
+    p.part_g[(size_t)j * p.pg_ld + blockIdx.x] = (ws[0][j] + ws[1][j]) + (ws[2][j] + ws[3][j]);
   }
 }
 
 __global__ void __launch_bounds__(256) k_rep_step(Consts c, IterPtrs p) { rep_step_body(c, p); }
 
 hipError_t launch_rep_step(const Consts& c, const IterPtrs& p, hipStream_t st) {
-  if (!iter_ptrs_ok(p)) return hipErrorInvalidValue;
+  if (!iter_ptrs_ok(p) || ngemv_blocks(c.n) > p.pg_ld) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rep_step, dim3(ngemv_blocks(c.n)), dim3(256), 0, st, c, p);
   return hipGetLastError();
 }
@@ -869,18 +894,17 @@ constexpr int TAIL_UNROLL = 16;
 constexpr int TAIL_SLOTS = 2 * 9 + NP2 + 1;
 static_assert(TAIL_SLOTS * TAIL_GROUP <= NTT, "every tail slot needs a lane group");
 
-// Sum (or maximum, for the Newton steps) of src[b * stride] over b = g,
+// Sum (or maximum, for the Newton steps) of src[b] over b = g,
 // g + TAIL_GROUP, ... < nb, in that order.
 template <bool MAX>
-__device__ __forceinline__ double tail_lane_sum(const double* __restrict__ src, int stride, int nb,
-                                                int g) {
+__device__ __forceinline__ double tail_lane_sum(const double* __restrict__ src, int nb, int g) {
   double v = 0.0;
   for (int b0 = g; b0 < nb; b0 += TAIL_GROUP * TAIL_UNROLL) {
     double t[TAIL_UNROLL];
 #pragma unroll
     for (int u = 0; u < TAIL_UNROLL; ++u) {
       const int b = b0 + u * TAIL_GROUP;
-      t[u] = b < nb ? src[(size_t)b * stride] : 0.0;
+      t[u] = b < nb ? src[b] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < TAIL_UNROLL; ++u) v = MAX ? fmax(v, t[u]) : v + t[u];
@@ -894,7 +918,9 @@ __device__ __forceinline__ double tail_lane_sum(const double* __restrict__ src, 
 // this thread's first TAIL_PRE rows; the outcome is picked afterwards.
 __device__ __forceinline__ void tail_body(const Consts& c, const IterPtrs& p, int nblk_d) {
   Scal* sc = p.sc;
-  if (sc->done) return;
+  // (the stop flag is tested once the loads below are in flight; nothing is
+  // written before the test)
+  const int done = sc->done;
   __shared__ double s_sigma;
   __shared__ double s_sum[TAIL_SLOTS];
   const int nb = ngemv_blocks(c.n);
@@ -929,11 +955,12 @@ __device__ __forceinline__ void tail_body(const Consts& c, const IterPtrs& p, in
     const bool is_max = slot == TAIL_SLOTS - 1;
     double v = 0.0;
     if (slot < 18)
-      v = tail_lane_sum<false>(p.part_c + 1 + (slot / 9) * NPO + slot % 9, NPC, nb, g);
+      v = tail_lane_sum<false>(p.part_c + (size_t)(1 + (slot / 9) * NPO + slot % 9) * nb, nb, g);
     else if (slot < 18 + NP2)
-      v = tail_lane_sum<false>(p.part_g + (slot - 18), NP2, nblk_d, g);
+      v = tail_lane_sum<false>(p.part_g + (size_t)(slot - 18) * p.pg_ld, nblk_d, g);
     else if (is_max)
-      v = tail_lane_sum<true>(p.part_it, 1, nb, g);
+      v = tail_lane_sum<true>(p.part_it, nb, g);
+    if (done) return;
 #pragma unroll
     for (int off = TAIL_GROUP / 2; off > 0; off >>= 1) {
       const double w = __shfl_xor(v, off, 64);
@@ -970,11 +997,11 @@ __device__ __forceinline__ void tail_body(const Consts& c, const IterPtrs& p, in
     sc->k = k1;
     bool stop = false;
     const double sig = stop_and_sigma(c, e, sigma, k1, &stop);
-    if (stop) {
-      sc->converged = 1;
+    if (stop) sc->converged = 1;
+    if (stop || k1 >= c.max_iter) {
       sc->done = 1;
-    } else if (k1 >= c.max_iter) {
-      sc->done = 1;
+      // the host polls this word between chunks of queued iterations
+      if (p.hdone) __hip_atomic_store(p.hdone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     sc->sigma = sig;
     s_sigma = sig;
