@@ -39,10 +39,10 @@ struct DirSizes {
   size_t factor_tmp;  // doubles of set-up scratch
 };
 
-static DirSizes dir_sizes(int64_t d, int n) {
+static DirSizes dir_sizes(int64_t d, int n, int storage) {
   DirSizes z;
   z.ld = direct_ld(d);
-  z.per_block = dir_sweep_samples_per_block(z.ld, n);
+  z.per_block = dir_sweep_samples_per_block(z.ld, n, storage);
   z.nblk = (n + z.per_block - 1) / z.per_block;
   z.nred = dir_reduce_blocks((int)d, 1);
   z.splits = fgram_splits((int)d, n);
@@ -51,7 +51,7 @@ static DirSizes dir_sizes(int64_t d, int n) {
 }
 
 int64_t direct_footprint(int64_t d, int n, int storage) {
-  const DirSizes z = dir_sizes(d, n);
+  const DirSizes z = dir_sizes(d, n, storage);
   const int64_t el = storage == DWD_FP64 ? 8 : 4;
   int64_t b = z.ld * n * el;                               // X
   b += (int64_t)n * 8 * 8;                                 // y, e, six n-vectors
@@ -65,7 +65,7 @@ int64_t direct_footprint(int64_t d, int n, int storage) {
 dwd_status setup_direct(Problem* P, hipStream_t st) {
   const int n = P->n;
   const int64_t d = P->d, ld = P->ld;
-  const DirSizes z = dir_sizes(d, n);
+  const DirSizes z = dir_sizes(d, n, P->st_rec);
   DirPtrs& dp = P->dp;
   auto alloc = [&](double** dst, size_t count) -> hipError_t {
     return P->alloc((void**)dst, std::max<size_t>(count, 1) * 8);

@@ -258,7 +258,7 @@ hipError_t launch_fgram(const void* X, int storage, int64_t ld, int n, int d, do
                         int splits, hipStream_t st);
 hipError_t launch_fgram_finish(const double* Kpart, int splits, int d, int n, const double* zy,
                                double inv_zs2, double mu, double* A, hipStream_t st);
-int dir_sweep_samples_per_block(int64_t ld, int n);
+int dir_sweep_samples_per_block(int64_t ld, int n, int storage);
 int dir_reduce_blocks(int d, int nvec);
 
 }  // namespace dwd

@@ -581,7 +581,319 @@ static void sweep_shape(int64_t ld, int* tps, int* nf) {
   *nf = (int)((quads + 255) / 256);
 }
 
-int dir_sweep_samples_per_block(int64_t ld, int n) {
+// ---------------------------------------------------------------------------
+// Sweeps 1 and 2 through LDS, for leading dimensions up to 512.  A block
+// takes its samples in chunks of S (64, 32 or 16) consecutive ones.  A
+// chunk's rows, contiguous in X, are read with 16-byte loads into registers
+// while the chunk before is processed, then written to LDS with an odd row
+// stride rs (in 4-byte words, for FP32: lanes reading the same column of
+// different rows hit different banks).  Dot products: the features split
+// into NP = 256 / S equal ranges; lane l of wave v takes sample l mod S and
+// range M v + l / S (M = 64 / S ranges per wave), so that each wave reads
+// only M entries of the d-vector (staged in LDS) at a time.  The NP partial sums of a sample are added in range order by
+// thread t = sample, which then does the sample's Step 1b-3 scalar work
+// (a full lane per sample) and stages its coefficients.  Accumulation:
+// lanes over features, each thread over its slice of the chunk's samples
+// in order.  Every sum has a fixed order, so the results do not depend on
+// timing.  The partials have the layout of k_dir_sweep.
+// ---------------------------------------------------------------------------
+constexpr int DL_NQ = 10;            // 16-byte row loads per thread and chunk
+constexpr int DL_ROWS = 48 * 1024;   // LDS bytes of a chunk's rows (padded) at most
+typedef unsigned int dl_u2 __attribute__((ext_vector_type(2)));
+typedef double dl_d2 __attribute__((ext_vector_type(2)));
+
+// 16 bytes to LDS at an address aligned to AL bytes
+template <int AL>
+__device__ __forceinline__ void lds_put16(void* dst, const nt_u4& v) {
+  if constexpr (AL == 16) {
+    *reinterpret_cast<nt_u4*>(dst) = v;
+  } else if constexpr (AL == 8) {
+    dl_u2* d = reinterpret_cast<dl_u2*>(dst);
+    d[0] = dl_u2{v.x, v.y};
+    d[1] = dl_u2{v.z, v.w};
+  } else {
+    unsigned* d = reinterpret_cast<unsigned*>(dst);
+    d[0] = v.x;
+    d[1] = v.y;
+    d[2] = v.z;
+    d[3] = v.w;
+  }
+}
+
+template <typename T, int S, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_dir_sweepl(const T* __restrict__ X,
+                                                    const double* __restrict__ wg, Consts c,
+                                                    DirPtrs p, int rs, int rb) {
+  static_assert(MODE == 1 || MODE == 2, "sweeps 1 and 2");
+  static_assert(S == 16 || S == 32 || S == 64, "a whole number of samples per wave");
+  constexpr int M = 64 / S, NP = 4 * M;
+  constexpr int NV = MODE == 2 ? 2 : 1;
+  constexpr int KS = MODE == 2 ? 10 : 2;
+  constexpr int NS = MODE == 1 ? 4 : 5;
+  constexpr int EQ = 16 / (int)sizeof(T);  // elements per 16-byte load
+  extern __shared__ __align__(16) unsigned char dl_lds[];
+  T* rows = reinterpret_cast<T*>(dl_lds);                    // [S][rs]
+  double* dpart = reinterpret_cast<double*>(dl_lds + rb);    // [NP][S]
+  double* cfs = dpart + NP * S;                              // [NV][S]
+  double* wl = cfs + 2 * 64;                                 // [ld] the d-vector
+  const int ldi = (int)c.ld;
+  for (int f = threadIdx.x; f < ldi; f += 256) wl[f] = wg[f];
+  Scal* sc = p.sc;
+  const int done = sc->done;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int i0 = blockIdx.x * p.per_block;
+  const int i1 = min(c.n, i0 + p.per_block);
+  const double sigma = sc->sigma;
+  const double beta = MODE == 1 ? p.wbar[c.d] : sc->beta;
+  const int redo = MODE == 2 ? sc->doubled : 1;
+  const int kk = sc->k;
+  if (done) return;
+  const double tolN = eps_k(c, kk) / sqrt((double)c.n);
+  // dot products: sample s_me, feature range pm of the wave's M
+  const int s_me = lane % S, pm = lane / S;
+  const int lf = ldi / NP;                 // features per range (ld is a multiple of 16)
+  const int fb = wv * M * lf;              // the wave's first feature (uniform)
+  // accumulation: feature fa (and fa + 256), sample slice r
+  int ldp = 16;
+  while (ldp < ldi) ldp <<= 1;
+  const int fw = min(ldp, 256), nsl = 256 / fw;
+  const int fa = t % fw, r = t / fw;
+  const int s_lo = r * (S / nsl), s_hi = s_lo + S / nsl;
+  double acc[NV][2];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v][0] = acc[v][1] = 0.0;
+  double ssum[KS];
+#pragma unroll
+  for (int j = 0; j < KS; ++j) ssum[j] = 0.0;
+  nt_u4 pre[DL_NQ];
+  double psv[NS];
+  auto load_chunk = [&](int cb) {
+    const int cnt = min(S, i1 - cb) * (ldi / EQ);
+    const nt_u4* src = reinterpret_cast<const nt_u4*>(X + (int64_t)cb * ldi);
+#pragma unroll
+    for (int q = 0; q < DL_NQ; ++q) {
+      const int u = t + 256 * q;
+      pre[q] = u < cnt ? src[u] : nt_u4{0u, 0u, 0u, 0u};
+    }
+    // thread t < S: sample t's n-vector entries
+    const int i = cb + t;
+    const bool in = t < S && i < i1;
+    psv[0] = in ? p.y[i] : 0.0;
+    psv[1] = in ? p.alpha[i] : 0.0;
+    if constexpr (MODE == 1) {
+      psv[2] = in ? p.r[i] : 0.0;
+      psv[3] = in ? p.xi[i] : 0.0;
+    } else {
+      psv[2] = in ? p.zb[i] : 0.0;
+      psv[3] = in ? p.rn[i] : 0.0;
+      psv[4] = in ? p.e[i] : 0.0;
+    }
+  };
+  if (i0 < i1) load_chunk(i0);
+  for (int cb = i0; cb < i1; cb += S) {
+    const int ns = min(S, i1 - cb);
+    {
+      const int cnt = ns * (ldi / EQ);
+#pragma unroll
+      for (int q = 0; q < DL_NQ; ++q) {
+        const int u = t + 256 * q;
+        if (u < cnt) {
+          const int e = u * EQ, s = e / ldi, col = e - s * ldi;
+          lds_put16<(int)sizeof(T)>(rows + s * rs + col, pre[q]);
+        }
+      }
+    }
+    double sv[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) sv[j] = psv[j];
+    if (cb + S < i1) load_chunk(cb + S);  // the next chunk in flight meanwhile
+    __syncthreads();
+    if (MODE == 1 || redo) {
+      const T* rw = rows + s_me * rs + fb + pm * lf;  // range wv M + pm
+      double dd[4] = {0.0, 0.0, 0.0, 0.0};
+      int k = 0;
+
+      const double* ww = wl + fb + pm * lf;  // (M addresses per wave: broadcast reads)
+      for (; k + 4 <= lf; k += 4) {
+        T xr[4];
+        double wr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          xr[u] = rw[k + u];
+          wr[u] = ww[k + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dd[u] = fma((double)xr[u], wr[u], dd[u]);
+      }
+      for (; k < lf; ++k) dd[k & 3] = fma((double)rw[k], ww[k], dd[k & 3]);
+      dpart[(wv * M + pm) * S + s_me] = (dd[0] + dd[1]) + (dd[2] + dd[3]);
+    }
+    __syncthreads();
+    if (t < S) {
+      const int i = cb + t;
+      double cf0 = 0.0, cf1 = 0.0;
+      if (i < i1) {
+        double dot = 0.0;
+        if (MODE == 1 || redo) {
+#pragma unroll
+          for (int q = 0; q < NP; ++q) dot += dpart[q * S + t];
+        }
+        const double yi = sv[0], al = sv[1];
+        if constexpr (MODE == 1) {
+          const double z = yi * dot * c.inv_zs;
+          const double r0 = sv[2];
+          const double cc = z + yi * beta + sv[3] - al / sigma;
+          int steps = 0;
+          const double rn = prox_weighted(cc, sigma, r0, tolN, loss_weight(c, yi), c, steps);
+          const double dr = rn - r0;
+          cf0 = yi * dr;
+          p.zb[i] = z;
+          p.rn[i] = rn;
+          p.dr[i] = dr;
+          ssum[0] += yi * dr;
+          ssum[1] = fmax(ssum[1], (double)steps);
+        } else {
+          const double z = redo ? yi * dot * c.inv_zs : sv[2];
+          const double rn = sv[3];
+          const double ei = sv[4];
+          const double xin = fmax(0.0, rn - z - yi * beta + (al - c.C * ei) / sigma);
+          const double pres = z + yi * beta + xin - rn;
+          const double a1 = al - c.tau * sigma * pres;
+          cf0 = yi * (xin - rn);
+          cf1 = yi * a1;
+          p.r[i] = rn;
+          p.xi[i] = xin;
+          p.alpha[i] = a1;
+          double s9[9];
+          nspace_sums(c, pow_q(rn, c), pow_qp1(rn, c), a1, xin, pres, yi, ei, s9);
+#pragma unroll
+          for (int j = 0; j < 9; ++j) ssum[j] += s9[j];
+          ssum[9] += yi * (xin - rn);
+        }
+      }
+      cfs[t] = cf0;
+      if constexpr (NV == 2) cfs[S + t] = cf1;
+    }
+    __syncthreads();
+    // (samples in order; eight rows and coefficients read before they are added)
+    const int se = min(s_hi, ns);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int f = fa + 256 * m;
+      if (f < ldi) {
+        int s = s_lo;
+        for (; s + 8 <= se; s += 8) {
+          T xr[8];
+          double c0[8], c1[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) xr[u] = rows[(s + u) * rs + f];
+#pragma unroll
+          for (int u = 0; u < 8; u += 2) {
+            const dl_d2 a0 = *reinterpret_cast<const dl_d2*>(cfs + s + u);
+            c0[u] = a0.x;
+            c0[u + 1] = a0.y;
+            if constexpr (NV == 2) {
+              const dl_d2 a1 = *reinterpret_cast<const dl_d2*>(cfs + S + s + u);
+              c1[u] = a1.x;
+              c1[u + 1] = a1.y;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            acc[0][m] = fma(c0[u], (double)xr[u], acc[0][m]);
+            if constexpr (NV == 2) acc[1][m] = fma(c1[u], (double)xr[u], acc[1][m]);
+          }
+        }
+        for (; s < se; ++s) {
+          const double x = (double)rows[s * rs + f];
+          acc[0][m] = fma(cfs[s], x, acc[0][m]);
+          if constexpr (NV == 2) acc[1][m] = fma(cfs[S + s], x, acc[1][m]);
+        }
+      }
+    }
+    __syncthreads();  // the rows and coefficients are rewritten next
+  }
+  // d-vector partials: the slices of each feature added in slice order
+  double* red = reinterpret_cast<double*>(dl_lds);
+  if (nsl > 1) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) red[(r * NV + v) * fw + fa] = acc[v][0];
+    __syncthreads();
+    if (r == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double s = red[v * fw + fa];
+        for (int rr = 1; rr < nsl; ++rr) s += red[(rr * NV + v) * fw + fa];
+        acc[v][0] = s;
+      }
+    }
+  }
+  if (r == 0) {
+    double* out = p.part_d + blockIdx.x;
+    const size_t nb = (size_t)p.nblk;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int f = fa + 256 * m;
+        if (f < ldi) out[((size_t)v * ldi + f) * nb] = acc[v][m];
+      }
+  }
+  // scalar partials (Newton steps by maximum)
+  double* part = (MODE == 1 ? p.part_n : p.part_n2) + (size_t)blockIdx.x * NPD;
+  if constexpr (MODE == 1) {
+    double mx = ssum[1];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    __shared__ double wmax[4];
+    if ((t & 63) == 0) wmax[t >> 6] = mx;
+    double a[1] = {ssum[0]};
+    block_sum_k<256, 1>(a);  // (its barriers also order the wmax writes)
+    if (t == 0) {
+      part[0] = a[0];
+      part[1] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    }
+  } else {
+    block_sum_k<256, KS>(ssum);
+    if (t < KS) {
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < KS; ++j)
+        if (t == j) v = ssum[j];
+      part[t] = v;
+    }
+  }
+}
+
+// Samples per chunk, LDS row stride and rows-area bytes of the LDS sweeps:
+// the largest chunk whose padded rows fit in DL_ROWS and whose data fits
+// the loads in registers; false above 512 features or when none fits.
+static bool sweepl_shape(int64_t ld, int elem, int* sn, int* rs, int* rb) {
+  if (ld > 512 || ld % 16 != 0) return false;
+  const int r = (int)ld + 1;  // odd
+  for (int s = 64; s >= 16; s /= 2) {
+    const size_t bytes = (size_t)s * r * elem;
+    const size_t loaded = (size_t)s * ld * elem;
+    if (bytes <= (size_t)DL_ROWS && loaded <= (size_t)DL_NQ * 256 * 16) {
+      *sn = s;
+      *rs = r;
+      // the rows area also takes the slice sums at the end
+      *rb = (int)((std::max(bytes, (size_t)(2 * 256 * 8)) + 15) / 16 * 16);
+      return true;
+    }
+  }
+  return false;
+}
+
+int dir_sweep_samples_per_block(int64_t ld, int n, int storage) {
+  int S, rs, rb;
+  if (sweepl_shape(ld, storage == DWD_FP64 ? 8 : 4, &S, &rs, &rb)) {
+    // whole chunks, one round of blocks (three per compute unit)
+    int per = std::max(S, (n + 767) / 768);
+    return (per + S - 1) / S * S;
+  }
   int tps, nf;
   sweep_shape(ld, &tps, &nf);
   const int G = 256 / tps;
@@ -594,8 +906,23 @@ int dir_sweep_samples_per_block(int64_t ld, int n) {
 template <typename T, int MODE>
 static hipError_t sweep_t(const T* X, const Consts& c, const DirPtrs& p, hipStream_t st) {
   int tps, nf;
-  sweep_shape(c.ld, &tps, &nf);
   const dim3 grid((unsigned)p.nblk), blk(256);
+  int sn, rs, rb;
+  if (MODE != 0 && sweepl_shape(c.ld, (int)sizeof(T), &sn, &rs, &rb)) {
+    // (the samples per block are whole chunks of this shape)
+    if (p.per_block % sn != 0) return hipErrorInvalidValue;
+    constexpr int M = MODE == 0 ? 1 : MODE;
+    const double* wg = M == 1 ? p.wbar : p.w;
+    const size_t shm = (size_t)rb + 8 * (size_t)(256 + 2 * 64) + 8 * (size_t)c.ld;
+    if (sn == 64)
+      hipLaunchKernelGGL((k_dir_sweepl<T, 64, M>), grid, blk, shm, st, X, wg, c, p, rs, rb);
+    else if (sn == 32)
+      hipLaunchKernelGGL((k_dir_sweepl<T, 32, M>), grid, blk, shm, st, X, wg, c, p, rs, rb);
+    else
+      hipLaunchKernelGGL((k_dir_sweepl<T, 16, M>), grid, blk, shm, st, X, wg, c, p, rs, rb);
+    return hipGetLastError();
+  }
+  sweep_shape(c.ld, &tps, &nf);
 #define DWD_SWEEP(TP, NFV)                                                                 \
   if (tps == TP && nf == NFV) {                                                            \
     hipLaunchKernelGGL((k_dir_sweep<T, TP, NFV, MODE>), grid, blk, 0, st, X, c, p);        \
