@@ -213,6 +213,35 @@ def test_direct_rejections_and_cap(dwd):
         dwd.serve([dict(X=X, y=y, t_arrival=0.0, params=dict(solver=1, representer=1))])
 
 
+@pytest.mark.parametrize("d,n,storage", [(120, 120000, "f32"), (500, 20000, "f32"),
+                                         (300, 30000, "f64")])
+def test_direct_chunked_sweeps_follow_oracle(dwd, d, n, storage):
+    # Shapes whose sweeps run through LDS with several chunks per block and a
+    # partial chunk at the end: 64 samples per chunk (d=120), 16 (d=500 FP32,
+    # d=300 FP64).  The iterates follow the oracle's, and repeats agree bit
+    # for bit.
+    X, y = synth.random_two_class(d, n, seed=7 * d + n, mean=0.5, pos_frac=0.3,
+                                  dtype="f64" if storage == "f64" else "f32")
+    e = synth.penalty_vector(n, seed=n + 3)
+    C, q = 1.5, 1.0
+    P = dwd.Problem(X, y, storage=storage, solver="direct")
+    for k in (1, 3, 8):
+        o = O.solve(X, y, C, q, tol=1e-300, max_iter=k, solver="direct", weights=True, e=e)
+        g = P.solve(C, q, tol=1e-300, max_iter=k, class_weights=1, e=e)
+        assert g["info"]["iters"] == k
+        for key in ("alpha", "r", "xi"):
+            assert np.allclose(g[key], o[key], rtol=1e-9, atol=1e-12), (k, key)
+        for key in ("w", "u", "rho"):
+            assert np.allclose(g[key], o[key], rtol=1e-9,
+                               atol=1e-12 * max(1e-300, np.abs(o[key]).max())), (k, key)
+        assert abs(g["beta"] - o["beta"]) <= 1e-9 * max(1.0, abs(o["beta"])), k
+        assert g["info"]["n_double"] == o["n_double"], k
+    a = P.solve(C, q, tol=1e-300, max_iter=8, class_weights=1, e=e)
+    for key in ("w", "alpha", "r", "xi", "u", "rho"):
+        assert np.array_equal(a[key], g[key]), key
+    P.close()
+
+
 @pytest.mark.parametrize("d,n", [(54, 3000), (300, 2000), (4000, 6000), (5000, 3000)])
 def test_direct_repeats_are_bit_identical(dwd, d, n):
     # The sweeps reduce in a fixed order, and a sample group that spans
