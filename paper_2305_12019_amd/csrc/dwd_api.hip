@@ -51,7 +51,7 @@ int64_t problem_footprint(int64_t d, int n, int storage, int layout, int64_t nnz
   const int64_t nn = (int64_t)n * n * 8;
   b += 2 * nn;                                          // G~, M^-1
   if (storage == DWD_BF16 && layout != DWD_CSR) b += 2 * nn + (int64_t)n * 8;  // BF16 factor
-  b += (int64_t)n * 8 * 28 + ld * 8 * 3;                // vectors (incl. y, e)
+  b += (int64_t)n * 8 * 33 + ld * 8 * 3;                // vectors (incl. y, e)
   b += (ld / kLdAlign) * 2 * (int64_t)n * 8;            // pass partials
   const int splits = gram_splits(ld, n);
   b += std::max<int64_t>({(int64_t)splits * nn, nn, (int64_t)spd_inverse_work(n) * 8});  // set-up scratch
@@ -499,9 +499,9 @@ dwd_status setup_problem(const dwd_matrix* X, const double* y, const dwd_params*
 hipError_t Problem::alloc_iter_buffers() {
   const int n_ = n;
   hipError_t e;
-  // 27 n-vectors (24 used)
+  // 31 n-vectors: 24 named, and the pass operands (4 per column)
   double* nb = nullptr;
-  if ((e = alloc((void**)&nb, (size_t)n_ * 8 * 27)) != hipSuccess) return e;
+  if ((e = alloc((void**)&nb, (size_t)n_ * 8 * 31)) != hipSuccess) return e;
   double* q = nb;
   auto take = [&](double*& dst) {
     dst = q;
@@ -511,6 +511,8 @@ hipError_t Problem::alloc_iter_buffers() {
   take(ip.f); take(ip.s); take(ip.v); take(ip.dr); take(ip.hG); take(ip.rn); take(ip.s1);
   take(ip.v1); take(ip.xi0); take(ip.xi1); take(ip.al0); take(ip.al1);
   take(ip.au); take(ip.arho); take(ip.aw); take(ip.au_n); take(ip.arho_n);
+  ip.stg = q;  // 4 n
+  q += 4 * (size_t)n_;
   double* db = nullptr;
   if ((e = alloc((void**)&db, (size_t)ld * 8 * 3)) != hipSuccess) return e;
   ip.u = db;

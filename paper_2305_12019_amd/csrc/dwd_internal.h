@@ -105,6 +105,7 @@ struct IterPtrs {
   double *s1, *v1, *xi0, *xi1, *al0, *al1;  // the two outcomes of Step 1c
   double *au, *arho, *aw;  // representer coefficients: u~ = Z~ au, rho = Z~ arho, w~ = Z~ aw
   double *au_n, *arho_n;   // the representer step's new au, arho (the tail commits them)
+  double *stg;             // 4 per column j: (y_j / Z_scale) [s, s1, alpha0, alpha1]_j
   double *u, *rho, *w;  // d-space, length ld
   // Block partials are stored slot-major, so that a reader summing one slot
   // over the blocks reads contiguous memory.

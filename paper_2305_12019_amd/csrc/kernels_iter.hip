@@ -90,7 +90,8 @@ static hipError_t gemvT_t(const void* X, int64_t ld, int n, const double* v1, co
 bool iter_ptrs_ok(const IterPtrs& p) {
   const void* req[] = {p.y, p.my, p.Minv, p.G, p.r, p.xi, p.alpha, p.Pu, p.Prho, p.t, p.x,
                        p.f, p.s, p.v, p.dr, p.hG, p.rn, p.s1, p.v1, p.xi0, p.xi1, p.al0,
-                       p.al1, p.au, p.arho, p.aw, p.au_n, p.arho_n, p.u, p.rho, p.w, p.part_g,
+                       p.al1, p.au, p.arho, p.aw, p.au_n, p.arho_n, p.stg, p.u, p.rho, p.w,
+                       p.part_g,
                        p.part_n1,
                        p.part_it, p.part_c, p.partT, p.sc};
   for (const void* q : req)
@@ -377,6 +378,7 @@ __device__ __forceinline__ void step1c_body(const Consts& c, const IterPtrs& p) 
   if (mine) {
     const double rq1 = pow_qp1(rn, c);
     const double rq = pow_q(rn, c);
+    double al0s = 0.0;  // alpha of outcome 0
     out[0] = dr * hg;
     {  // outcome 0
       const double s = s0;
@@ -386,6 +388,7 @@ __device__ __forceinline__ void step1c_body(const Consts& c, const IterPtrs& p) 
       const double a1 = a0 - c.tau * sigma * pres;
       p.xi0[row] = xi;
       p.al0[row] = a1;
+      al0s = a1;
       nspace_sums(c, rq, rq1, a1, xi, pres, yi, ei, out + 1);
       out[1 + 9] = s * (c.mu * (xr + beta_bar * yi - s));
       out[1 + 10] = pu * s;
@@ -403,6 +406,14 @@ __device__ __forceinline__ void step1c_body(const Consts& c, const IterPtrs& p) 
       nspace_sums(c, rq, rq1, a1, xi, pres, yi, ei, out + 1 + NPO);
       out[1 + NPO + 9] = s * (c.mu * (xr - dr + beta1 * yi - s));
       out[1 + NPO + 10] = pu * s;
+      // the pass's operands of both outcomes, scaled by the label sign and
+      // 1/Z_scale
+      const double yz = yi * c.inv_zs;
+      double* st = p.stg + 4 * (size_t)row;
+      st[0] = yz * s0;
+      st[1] = yz * s;
+      st[2] = yz * al0s;
+      st[3] = yz * a1;
     }
     p.hG[row] = hg;
   }
@@ -428,73 +439,53 @@ hipError_t launch_step1c_rows(const Consts& c, const IterPtrs& p, hipStream_t st
 
 // ---------------------------------------------------------------------------
 // Pass over Z: zs = Z~ s and za = Z~ alpha^{k+1} row by row (the label signs
-// and 1/Z_scale are applied to s and alpha while they are staged in LDS),
-// fused with Steps 2 and 3 in d-space:
+// and 1/Z_scale come with s and alpha from Step 1c), fused with Steps 2 and 3
+// in d-space:
 //   w = (b - zs)/mu,  b = mu u + sqrt(mu) rho / sigma,  g = w - rho/(sigma sqrt(mu)),
 //   u <- gamma g,  rho <- rho - tau sigma sqrt(mu) (w - u),
 // and block partials of ||w-u||^2, ||w||^2, ||za + sqrt(mu) rho||^2,
 // ||za||^2, ||rho||^2, ||u||^2.  Block = NW waves over the same 64*V rows,
-// wave j walks its share of the columns; partial row sums meet in LDS.
+// wave j walks its quarter of the columns; partial row sums meet in LDS.
 // ---------------------------------------------------------------------------
-constexpr int PANEL = 2048;
+constexpr int PANEL = 2048;  // columns staged at a time by the representer step
 
 // The n-space prediction of ||g|| that sizes the ball projection is exact
 // for the data the pass streams: the data of record with its factor, or the
 // BF16 image with the factor of the BF16 image (BF16 phase).
+//
+// The scaled operands of both Step 1c outcomes, (y_j / Z_scale) [s, s1,
+// alpha0, alpha1]_j, come from Step 1c as four consecutive FP64 values per
+// column (p.stg); a wave reads them with scalar loads at addresses common to
+// its lanes, so the column loop needs no staging and no barrier, and starts
+// as soon as the first data columns arrive.  Both outcomes are accumulated;
+// the plan that picks one (and sizes Step 2) is formed after the loop, from
+// partials loaded at the start.
 template <typename T, int NW>
 __device__ __forceinline__ void pass2_body(const T* __restrict__ X, const Consts& c,
                                            const IterPtrs& p) {
-  // The stop flag is tested after the prologue's loads are issued (nothing
-  // is written before the test), so its round trip overlaps theirs.
+  // The stop flag is tested after the first loads are issued (nothing is
+  // written before the test), so its round trip overlaps theirs.
   const int done = p.sc->done;
   constexpr int NT = NW * 64;
   constexpr int V = Vec<T>::N;
   constexpr int ROWS = 64 * V;
   constexpr int RPT = (ROWS + NT - 1) / NT;  // epilogue rows per thread
   constexpr int RB = (512 + NT - 1) / NT;    // plan partial blocks per thread (n <= 2048)
-  // Both Step 1c candidates of the scaled operand, [s | s1 | alpha0 | alpha1],
-  // are staged so that staging does not wait for the plan; after the column
-  // loop the same memory holds the per-wave row sums.
-  __shared__ double lds[4 * PANEL];
-  static_assert(2 * NW * ROWS <= 4 * PANEL, "row sums must fit the staging buffer");
+  __shared__ double lds[2 * NW * ROWS];      // the per-wave row sums
   double(*red)[2][ROWS] = reinterpret_cast<double(*)[2][ROWS]>(lds);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int64_t rbase = (int64_t)blockIdx.x * ROWS;
   const T* xrow = X + rbase + lane * V;
-  // Everything the prologue needs is requested before anything waits, the
-  // loads that hit the caches first: the plan partials and the first panel's
-  // operand (so that staging and the plan wait only for these), then the
-  // first four columns of this wave's share of the first panel and the rows'
-  // u and rho for the epilogue.  Every load is unconditional (clamped
-  // indexes, the surplus discarded), which keeps the waits counted exactly.
-  const int nb = ngemv_blocks(c.n);
-  const bool few = nb <= RB * NT;
-  double raw[RB][6];
-#pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    const int b = min(threadIdx.x + r * NT, nb - 1);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) raw[r][j] = plan_part(p, j, b, nb);
-  }
-  constexpr int SPT = PANEL / NT;  // first-panel entries staged per thread
-  const int pn0 = min(PANEL, c.n);
-  double sy[SPT], ss0[SPT], ss1[SPT], sa0[SPT], sa1[SPT];
-#pragma unroll
-  for (int q = 0; q < SPT; ++q) {
-    const int i = min((int)threadIdx.x + q * NT, pn0 - 1);
-    sy[q] = p.y[i];
-    ss0[q] = p.s[i];
-    ss1[q] = p.s1[i];
-    sa0[q] = p.al0[i];
-    sa1[q] = p.al1[i];
-  }
-  __builtin_amdgcn_sched_barrier(0);
+  // this wave's columns
+  const int per = (c.n + NW - 1) / NW;
+  const int j0 = min(c.n, wid * per), j1 = min(c.n, j0 + per);
+  // First loads, all unconditional (clamped indexes, the surplus discarded,
+  // which keeps the waits counted exactly): the first four data columns,
+  // the rows' u and rho for the epilogue, and the plan partials.
   typename Vec<T>::raw_t pf[4];
-  const int per0 = (pn0 + NW - 1) / NW;
-  const int pj0 = wid * per0, pj1 = min(pn0, pj0 + per0);
-  const bool have_pf = pj0 + 4 <= pj1;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) pf[u] = Vec<T>::raw(xrow + (int64_t)min(pj0 + u, c.n - 1) * c.ld);
+  for (int u = 0; u < 4; ++u) pf[u] = Vec<T>::raw(xrow + (int64_t)min(j0 + u, c.n - 1) * c.ld);
   double u_in[RPT], rho_in[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
@@ -502,98 +493,80 @@ __device__ __forceinline__ void pass2_body(const T* __restrict__ X, const Consts
     u_in[q] = p.u[rbase + rr];
     rho_in[q] = p.rho[rbase + rr];
   }
+  const int nb = ngemv_blocks(c.n);
+  const bool few = nb <= RB * NT;
+  double raw[RB][6];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int b = min((int)threadIdx.x + r * NT, nb - 1);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) raw[r][j] = plan_part(p, j, b, nb);
+  }
   const int k_it = p.sc->k;
   const double u2 = p.sc->u2;
   if (done) return;
-  auto stage = [&](int pc, int pn) {
-    for (int i = threadIdx.x; i < pn; i += NT) {
-      const double yz = p.y[pc + i] * c.inv_zs;
-      lds[i] = yz * p.s[pc + i];
-      lds[PANEL + i] = yz * p.s1[pc + i];
-      lds[2 * PANEL + i] = yz * p.al0[pc + i];
-      lds[3 * PANEL + i] = yz * p.al1[pc + i];
+  // a*: Z~ s of outcome 0 / 1, b*: Z~ alpha of outcome 0 / 1
+  double a0[V], a1[V], b0[V], b1[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) a0[e] = a1[e] = b0[e] = b1[e] = 0.0;
+  const double* __restrict__ stg = p.stg;
+  auto column = [&](const double (&x)[V], int j) {
+    const double s0 = stg[4 * j], s1 = stg[4 * j + 1];
+    const double t0 = stg[4 * j + 2], t1 = stg[4 * j + 3];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      a0[e] = fma(x[e], s0, a0[e]);
+      a1[e] = fma(x[e], s1, a1[e]);
+      b0[e] = fma(x[e], t0, b0[e]);
+      b1[e] = fma(x[e], t1, b1[e]);
     }
   };
-#pragma unroll
-  for (int q = 0; q < SPT; ++q) {
-    const int i = threadIdx.x + q * NT;
-    if (i < pn0) {
-      const double yz = sy[q] * c.inv_zs;
-      lds[i] = yz * ss0[q];
-      lds[PANEL + i] = yz * ss1[q];
-      lds[2 * PANEL + i] = yz * sa0[q];
-      lds[3 * PANEL + i] = yz * sa1[q];
-    }
-  }
-  double a[6];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) a[j] = 0.0;
-  if (few) {
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int j = 0; j < 6; ++j)
-        if (threadIdx.x + r * NT < nb) a[j] += raw[r][j];
-  } else {
-    for (int b = threadIdx.x; b < nb; b += NT)
-#pragma unroll
-      for (int j = 0; j < 6; ++j) a[j] += plan_part(p, j, b, nb);
-  }
-  block_sum_k<NT, 6>(a);  // also orders the staging writes before their reads
-  const Step2Plan pl = step2_plan_finish(c, a, k_it, u2);
-  publish_plan(p, pl);
-  const int os = pl.redo ? PANEL : 0;
-  double as[V], aa[V];
-#pragma unroll
-  for (int e = 0; e < V; ++e) as[e] = aa[e] = 0.0;
   auto group = [&](const typename Vec<T>::raw_t (&xr)[4], int j) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       double x[V];
       Vec<T>::cvt(xr[u], x);
-      const double s0 = lds[os + j + u], s1 = lds[2 * PANEL + os + j + u];
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        as[e] = fma(x[e], s0, as[e]);
-        aa[e] = fma(x[e], s1, aa[e]);
-      }
+      column(x, j + u);
     }
   };
-  for (int pc = 0; pc < c.n; pc += PANEL) {
-    const int pn = min(PANEL, c.n - pc);
-    if (pc > 0) {
-      stage(pc, pn);
-      __syncthreads();
-    }
-    const int per = (pn + NW - 1) / NW;
-    const int j0 = wid * per, j1 = min(pn, j0 + per);
-    int j = j0;
-    if (pc == 0 && have_pf) {
-      group(pf, j);
-      j += 4;
-    }
-    for (; j + 4 <= j1; j += 4) {
-      typename Vec<T>::raw_t x[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = Vec<T>::raw(xrow + (int64_t)(pc + j + u) * c.ld);
-      group(x, j);
-    }
-    for (; j < j1; ++j) {
-      double x0[V];
-      Vec<T>::load(xrow + (int64_t)(pc + j) * c.ld, x0);
-      const double s0 = lds[os + j], s1 = lds[2 * PANEL + os + j];
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        as[e] = fma(x0[e], s0, as[e]);
-        aa[e] = fma(x0[e], s1, aa[e]);
-      }
-    }
-    __syncthreads();
+  int j = j0;
+  if (j0 + 4 <= j1) {
+    group(pf, j);
+    j += 4;
   }
+  for (; j + 4 <= j1; j += 4) {
+    typename Vec<T>::raw_t x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = Vec<T>::raw(xrow + (int64_t)(j + u) * c.ld);
+    group(x, j);
+  }
+  for (; j < j1; ++j) {
+    double x0[V];
+    Vec<T>::load(xrow + (int64_t)j * c.ld, x0);
+    column(x0, j);
+  }
+  // the plan (every block forms the same one)
+  double a[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) a[q] = 0.0;
+  if (few) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        if (threadIdx.x + r * NT < nb) a[q] += raw[r][q];
+  } else {
+    for (int b = threadIdx.x; b < nb; b += NT)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) a[q] += plan_part(p, q, b, nb);
+  }
+  block_sum_k<NT, 6>(a);
+  const Step2Plan pl = step2_plan_finish(c, a, k_it, u2);
+  publish_plan(p, pl);
 #pragma unroll
   for (int e = 0; e < V; ++e) {
-    red[wid][0][lane * V + e] = as[e];
-    red[wid][1][lane * V + e] = aa[e];
+    red[wid][0][lane * V + e] = pl.redo ? a1[e] : a0[e];
+    red[wid][1][lane * V + e] = pl.redo ? b1[e] : b0[e];
   }
   __syncthreads();
   const double sigma = p.sc->sigma;
