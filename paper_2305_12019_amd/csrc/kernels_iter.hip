@@ -509,7 +509,10 @@ __device__ __forceinline__ void pass2_body(const T* __restrict__ X, const Consts
   double a0[V], a1[V], b0[V], b1[V];
 #pragma unroll
   for (int e = 0; e < V; ++e) a0[e] = a1[e] = b0[e] = b1[e] = 0.0;
-  const double* __restrict__ stg = p.stg;
+  // (a global-memory pointer: the serving form takes p from a descriptor in
+  // memory, and a generic pointer could not be read with scalar loads)
+  typedef __attribute__((address_space(1))) const double gdouble;
+  const gdouble* __restrict__ stg = (const gdouble*)p.stg;
   auto column = [&](const double (&x)[V], int j) {
     const double s0 = stg[4 * j], s1 = stg[4 * j + 1];
     const double t0 = stg[4 * j + 2], t1 = stg[4 * j + 3];
