@@ -305,6 +305,22 @@ def test_iteration_cap_returns_valid_state(dwd, small_ref):
     assert np.all(np.isfinite(got["w"])) and np.all(got["r"] > 0)
 
 
+def test_host_stops_queueing_at_the_device_stop(dwd):
+    # The tail kernel that sets the stop flag also sets a pinned host word,
+    # which the host reads one chunk of queued iterations behind: a solve that
+    # converges long before max_iter queues a chunk or two past the stop.  A
+    # host that missed the word would queue 4e6 launches (seconds of work).
+    X, y = synth.random_two_class(3000, 100, seed=9, dtype="f32")
+    P = dwd.Problem(X, y, storage="f32")
+    first = P.solve(1.0, 1.0, tol=1e-4)
+    r = P.solve(1.0, 1.0, tol=1e-4, max_iter=1000000)
+    P.close()
+    i = r["info"]
+    assert i["converged"] == 1 and i["iters"] == first["info"]["iters"]
+    assert i["solve_ms"] < 1000.0, i["solve_ms"]
+    assert np.array_equal(r["w"], first["w"])
+
+
 def test_invalid_inputs_are_rejected(dwd):
     X, y = synth.random_two_class(100, 10, seed=5)
     Xn = X.copy()
