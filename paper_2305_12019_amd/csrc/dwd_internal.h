@@ -175,8 +175,8 @@ struct DirPtrs {
   double *r, *xi, *alpha, *zb, *rn, *dr;   // n
   double *wbar, *w, *u, *rho, *h, *zz;     // d-space
   double* part_d;       // nblk x 2 ld: sweep partials of the d-vector sums
-  double* part_n;       // nblk x NPD: sweep 1 scalar partials (y^T dr, Newton steps)
-  double* part_n2;      // nblk x NPD: sweep 2 scalar partials (Section 4.3 terms)
+  double* part_n;       // NPD x nblk (slot-major): sweep 1 scalar partials (y^T dr, Newton steps)
+  double* part_n2;      // NPD x nblk (slot-major): sweep 2 scalar partials (Section 4.3 terms)
   double* part_r;       // reduce-kernel partials of ||Z~ dr||^2
   Scal* sc;
   int nblk, per_block, nred;

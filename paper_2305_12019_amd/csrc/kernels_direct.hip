@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(256) k_dir_gemv(Consts c, DirPtrs p, int mode)
   if (mode == 1) {
     double s2 = 0.0, sy = 0.0;
     for (int b = lane; b < p.nred; b += 64) s2 += p.part_r[b];
-    for (int b = lane; b < p.nblk; b += 64) sy += p.part_n[(size_t)b * NPD + 0];
+    for (int b = lane; b < p.nblk; b += 64) sy += p.part_n[b];  // slot 0
     s2 = wave_sum(s2);
     ydr = wave_sum(sy);
     const double res = sqrt(fmax(s2 + ydr * ydr, 0.0));
@@ -301,7 +301,8 @@ hipError_t launch_dir_gemv(const Consts& c, const DirPtrs& p, int mode, hipStrea
 //   MODE 1: sweep 1 of the iteration (see the file comment)
 //   MODE 2: sweep 2
 // Partials: part_d[(v*ld + f) * nblk + b] (v = 0, 1; feature-major, so that
-// the reduction reads each feature's partials contiguously), part_n[b][0..NPD).
+// the reduction reads each feature's partials contiguously), part_n[j * nblk + b]
+// for slots j < NPD (slot-major, read contiguously by the consumers).
 // ---------------------------------------------------------------------------
 // (ordinary cached loads: in the regime of this branch X is often small
 // enough to stay in the last-level cache between the two sweeps; values are
@@ -554,7 +555,7 @@ __global__ void __launch_bounds__(256) k_dir_sweep(const T* __restrict__ X, Cons
       double s = sbuf[0][j];
       for (int gg = 1; gg < G; ++gg)
         s = (MODE == 1 && j == 1) ? fmax(s, sbuf[gg][j]) : s + sbuf[gg][j];
-      (MODE == 1 ? p.part_n : p.part_n2)[(size_t)blockIdx.x * NPD + j] = s;
+      (MODE == 1 ? p.part_n : p.part_n2)[(size_t)j * p.nblk + blockIdx.x] = s;
     }
   }
 }
@@ -842,7 +843,7 @@ k_dir_sweepl(const T* __restrict__ X,
       }
   }
   // scalar partials (Newton steps by maximum)
-  double* part = (MODE == 1 ? p.part_n : p.part_n2) + (size_t)blockIdx.x * NPD;
+  double* part = (MODE == 1 ? p.part_n : p.part_n2) + blockIdx.x;  // slot j at j nblk
   if constexpr (MODE == 1) {
     double mx = ssum[1];
 #pragma unroll
@@ -853,7 +854,7 @@ k_dir_sweepl(const T* __restrict__ X,
     block_sum_k<256, 1>(a);  // (its barriers also order the wmax writes)
     if (t == 0) {
       part[0] = a[0];
-      part[1] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+      part[p.nblk] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
     }
   } else {
     block_sum_k<256, KS>(ssum);
@@ -862,7 +863,7 @@ k_dir_sweepl(const T* __restrict__ X,
 #pragma unroll
       for (int j = 0; j < KS; ++j)
         if (t == j) v = ssum[j];
-      part[t] = v;
+      part[(size_t)t * p.nblk] = v;
     }
   }
 }
@@ -1015,8 +1016,8 @@ __global__ void __launch_bounds__(NTD) k_dir_tail(Consts c, DirPtrs p) {
   double nmax = 0.0;
   for (int b = threadIdx.x; b < p.nblk; b += NTD) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) ns[j] += p.part_n2[(size_t)b * NPD + j];
-    nmax = fmax(nmax, p.part_n[(size_t)b * NPD + 1]);
+    for (int j = 0; j < K; ++j) ns[j] += p.part_n2[(size_t)j * p.nblk + b];
+    nmax = fmax(nmax, p.part_n[(size_t)p.nblk + b]);
   }
   block_sum_k<NTD, K>(ns);
   {
